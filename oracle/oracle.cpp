@@ -1,0 +1,1141 @@
+// FP64 CPU oracle for batched iLQR trajectory optimisation.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+// call this file; only the test-suite, the smoke check and the CPU-baseline
+// leg of the benchmark do.  It shares no code, header or constant with the
+// HIP solver.
+//
+// What it computes (paper Sec. II, eq. 1; Sec. IV-B, eq. 7; Sec. IV-C):
+//   min_{X,U} sum_{k<T} l(x_k,u_k) + l_T(x_T),  x_{k+1} = f(x_k,u_k),  x_0 given,
+// solved per instance by iLQR: forward rollout, linearise/quadratise,
+// eigenvalue-clip the state- and control-cost Hessians (eq. 7), backward
+// Riccati sweep with a Cholesky of Q_uu, backtracking line search, a fixed
+// iteration budget for the whole batch (Sec. IV-A), and afterwards the
+// critic targets of Sec. II: the K-step partial cost-to-go V-bar for every
+// state, its gradient V-bar_x from the backward (costate) pass, and the
+// state K steps later.
+//
+// Plain on purpose: dense row-major loops, no blocking, no fusion, FP64
+// throughout, compiled without floating-point contraction.  Dynamics
+// Jacobians come from complex-step differentiation of f (a forward-mode
+// automatic derivative, as the paper's pipeline obtains its derivatives by
+// automatic differentiation, Sec. IV-C); cost gradients are written
+// analytically and their Hessians are complex-step derivatives of those
+// gradients.
+//
+// Readings of points the paper leaves open (listed in the design notes):
+//   * clipped matrices: the running state-cost Hessian l_xx, the control-cost
+//     Hessian l_uu and the terminal Hessian, every iteration, after
+//     symmetrisation; eps default 1e-6.
+//   * line search: alpha_j = beta^j (repeated multiplication from 1),
+//     j = 0..trials-1, accept the first finite J_hat with J_hat < J.
+//   * no accepted step: the instance is frozen with LS_FAILED (without the
+//     Levenberg-Marquardt loop a retry would repeat the same step).
+//   * tolerance mode: freeze with CONVERGED once an accepted step lowers J by
+//     at most rtol*|J_old|.
+//   * warm start: U0 (zero by default), X0 = rollout of U0.
+//   * V-bar_x_k is the costate lambda_k of the final trajectory.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <omp.h>
+
+namespace {
+
+using cd = std::complex<double>;
+
+enum Kind { KIND_LQ = 0, KIND_PM = 1, KIND_P3 = 2, KIND_QUAD = 3 };
+
+enum StatusBits : uint32_t {
+  ST_CONVERGED = 1u,
+  ST_MAX_ITER = 2u,
+  ST_LS_FAILED = 4u,
+  ST_NONFINITE = 8u,
+  ST_CHOL_FAIL = 16u,
+};
+
+struct Sys {
+  int kind = -1;
+  int n = 0, m = 0;
+  const double* p = nullptr;  // parameter vector
+  // LQ views into p
+  const double *A = nullptr, *B = nullptr, *Q = nullptr, *R = nullptr, *QT = nullptr, *xr = nullptr;
+};
+
+inline double re(double v) { return v; }
+inline double re(const cd& v) { return v.real(); }
+
+// ------------------------------------------------------------ small dense helpers
+template <class S>
+bool gauss_solve(int n, std::vector<S> M, S* rhs, int nrhs) {
+  // Gaussian elimination without pivoting, for the SPD mass matrices only
+  // (so it stays analytic for complex-step derivatives).  M is n x n row-major,
+  // rhs is n x nrhs row-major and is overwritten by the solution.
+  for (int c = 0; c < n; ++c) {
+    S piv = M[c * n + c];
+    if (re(piv) == 0.0) return false;
+    for (int r = c + 1; r < n; ++r) {
+      S f = M[r * n + c] / piv;
+      for (int j = c; j < n; ++j) M[r * n + j] -= f * M[c * n + j];
+      for (int j = 0; j < nrhs; ++j) rhs[r * nrhs + j] -= f * rhs[c * nrhs + j];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    for (int j = 0; j < nrhs; ++j) {
+      S s = rhs[c * nrhs + j];
+      for (int k = c + 1; k < n; ++k) s -= M[c * n + k] * rhs[k * nrhs + j];
+      rhs[c * nrhs + j] = s / M[c * n + c];
+    }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------ point mass
+// p = [dt, w_u, w_p, w_T, w_obs, g_x, g_y, (c_x, c_y, r) x 3]
+// Semi-implicit Euler of a 2-D double integrator: v+ = v + dt u, p+ = p + dt v+.
+template <class S>
+void pm_dyn(const double* p, const S* x, const S* u, S* xn) {
+  const double dt = p[0];
+  S vx = x[2] + dt * u[0];
+  S vy = x[3] + dt * u[1];
+  xn[0] = x[0] + dt * vx;
+  xn[1] = x[1] + dt * vy;
+  xn[2] = vx;
+  xn[3] = vy;
+}
+
+template <class S>
+S pm_cost(const double* p, const S* x, const S* u) {
+  S ex = x[0] - p[5], ey = x[1] - p[6];
+  S l = p[1] * (u[0] * u[0] + u[1] * u[1]) + p[2] * (ex * ex + ey * ey);
+  for (int i = 0; i < 3; ++i) {
+    const double cx = p[7 + 3 * i], cy = p[8 + 3 * i], r = p[9 + 3 * i];
+    S dx = x[0] - cx, dy = x[1] - cy;
+    l += p[4] * std::exp(-(dx * dx + dy * dy) / (r * r));
+  }
+  return l;
+}
+
+template <class S>
+void pm_cost_grad(const double* p, const S* x, const S* u, S* lx, S* lu) {
+  lx[0] = 2.0 * p[2] * (x[0] - p[5]);
+  lx[1] = 2.0 * p[2] * (x[1] - p[6]);
+  lx[2] = 0.0;
+  lx[3] = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    const double cx = p[7 + 3 * i], cy = p[8 + 3 * i], r = p[9 + 3 * i];
+    S dx = x[0] - cx, dy = x[1] - cy;
+    S e = p[4] * std::exp(-(dx * dx + dy * dy) / (r * r));
+    lx[0] += e * (-2.0 * dx / (r * r));
+    lx[1] += e * (-2.0 * dy / (r * r));
+  }
+  lu[0] = 2.0 * p[1] * u[0];
+  lu[1] = 2.0 * p[1] * u[1];
+}
+
+template <class S>
+S pm_term(const double* p, const S* x) {
+  S ex = x[0] - p[5], ey = x[1] - p[6];
+  return p[3] * (ex * ex + ey * ey + x[2] * x[2] + x[3] * x[3]);
+}
+
+template <class S>
+void pm_term_grad(const double* p, const S* x, S* lx) {
+  lx[0] = 2.0 * p[3] * (x[0] - p[5]);
+  lx[1] = 2.0 * p[3] * (x[1] - p[6]);
+  lx[2] = 2.0 * p[3] * x[2];
+  lx[3] = 2.0 * p[3] * x[3];
+}
+
+// ------------------------------------------------------------ planar 3-link arm
+// p = [dt, m1, m2, m3, l1, l2, l3, w_u, w_ee, w_T, w_obs, p_x, p_y, c_x, c_y, r]
+// Uniform rods (centre of mass at half length, inertia m l^2 / 12), relative
+// joint angles, horizontal plane.  Mass matrix from link Jacobians,
+// M = sum_i m_i Jv_i^T Jv_i + I_i Jw_i^T Jw_i, and the velocity-product term
+// from the Christoffel symbols of M.
+template <class S>
+void p3_link_jac(const double* p, const S* q, int i, S Jv[2][3], S dJv[3][2][3]) {
+  // Jv: d(com_i)/dq ; dJv[k]: d Jv / d q_k.
+  const double* len = p + 4;
+  S phi[3];
+  phi[0] = q[0];
+  phi[1] = q[0] + q[1];
+  phi[2] = q[0] + q[1] + q[2];
+  for (int c = 0; c < 3; ++c) {
+    Jv[0][c] = 0.0;
+    Jv[1][c] = 0.0;
+    for (int k = 0; k < 3; ++k) { dJv[k][0][c] = 0.0; dJv[k][1][c] = 0.0; }
+  }
+  for (int j = 0; j <= i; ++j) {
+    const double a = (j < i) ? len[j] : 0.5 * len[j];
+    S s = std::sin(phi[j]), co = std::cos(phi[j]);
+    // com_i contains a*(cos phi_j, sin phi_j); phi_j depends on q_0..q_j.
+    for (int c = 0; c <= j; ++c) {
+      Jv[0][c] += -a * s;
+      Jv[1][c] += a * co;
+      for (int k = 0; k <= j; ++k) {
+        dJv[k][0][c] += -a * co;
+        dJv[k][1][c] += -a * s;
+      }
+    }
+  }
+}
+
+template <class S>
+void p3_mass(const double* p, const S* q, S Mout[3][3], S dM[3][3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      Mout[a][b] = 0.0;
+      for (int k = 0; k < 3; ++k) dM[k][a][b] = 0.0;
+    }
+  for (int i = 0; i < 3; ++i) {
+    const double mi = p[1 + i], li = p[4 + i];
+    const double Ii = mi * li * li / 12.0;
+    S Jv[2][3], dJv[3][2][3];
+    p3_link_jac(p, q, i, Jv, dJv);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        S v = Jv[0][a] * Jv[0][b] + Jv[1][a] * Jv[1][b];
+        Mout[a][b] += mi * v;
+        // angular velocity of link i is the sum of the first i+1 joint rates
+        if (a <= i && b <= i) Mout[a][b] += Ii;
+        for (int k = 0; k < 3; ++k) {
+          S dv = dJv[k][0][a] * Jv[0][b] + Jv[0][a] * dJv[k][0][b] +
+                 dJv[k][1][a] * Jv[1][b] + Jv[1][a] * dJv[k][1][b];
+          dM[k][a][b] += mi * dv;
+        }
+      }
+  }
+}
+
+template <class S>
+void p3_accel(const double* p, const S* q, const S* qd, const S* tau, S* acc) {
+  S M[3][3], dM[3][3][3];
+  p3_mass(p, q, M, dM);
+  S rhs[3];
+  for (int i = 0; i < 3; ++i) {
+    // c_i = sum_jk Gamma_ijk qd_j qd_k,
+    // Gamma_ijk = 1/2 (dM_ij/dq_k + dM_ik/dq_j - dM_jk/dq_i)
+    S ci = 0.0;
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        S g = 0.5 * (dM[k][i][j] + dM[j][i][k] - dM[i][j][k]);
+        ci += g * qd[j] * qd[k];
+      }
+    rhs[i] = tau[i] - ci;
+  }
+  std::vector<S> Mv(9);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Mv[a * 3 + b] = M[a][b];
+  gauss_solve<S>(3, Mv, rhs, 1);
+  for (int i = 0; i < 3; ++i) acc[i] = rhs[i];
+}
+
+template <class S>
+void p3_dyn(const double* p, const S* x, const S* u, S* xn) {
+  const double dt = p[0];
+  S acc[3];
+  p3_accel<S>(p, x, x + 3, u, acc);
+  for (int i = 0; i < 3; ++i) {
+    xn[3 + i] = x[3 + i] + dt * acc[i];
+    xn[i] = x[i] + dt * xn[3 + i];
+  }
+}
+
+template <class S>
+void p3_ee(const double* p, const S* q, S* ee, S J[2][3]) {
+  const double* len = p + 4;
+  S phi[3];
+  phi[0] = q[0];
+  phi[1] = q[0] + q[1];
+  phi[2] = q[0] + q[1] + q[2];
+  ee[0] = 0.0;
+  ee[1] = 0.0;
+  for (int c = 0; c < 3; ++c) { J[0][c] = 0.0; J[1][c] = 0.0; }
+  for (int j = 0; j < 3; ++j) {
+    S s = std::sin(phi[j]), co = std::cos(phi[j]);
+    ee[0] += len[j] * co;
+    ee[1] += len[j] * s;
+    for (int c = 0; c <= j; ++c) {
+      J[0][c] += -len[j] * s;
+      J[1][c] += len[j] * co;
+    }
+  }
+}
+
+template <class S>
+S p3_cost(const double* p, const S* x, const S* u) {
+  S ee[2], J[2][3];
+  p3_ee<S>(p, x, ee, J);
+  S ex = ee[0] - p[11], ey = ee[1] - p[12];
+  S dx = ee[0] - p[13], dy = ee[1] - p[14];
+  const double r = p[15];
+  return p[7] * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) + p[8] * (ex * ex + ey * ey) +
+         p[10] * std::exp(-(dx * dx + dy * dy) / (r * r));
+}
+
+template <class S>
+void p3_cost_grad(const double* p, const S* x, const S* u, S* lx, S* lu) {
+  S ee[2], J[2][3];
+  p3_ee<S>(p, x, ee, J);
+  S ex = ee[0] - p[11], ey = ee[1] - p[12];
+  S dx = ee[0] - p[13], dy = ee[1] - p[14];
+  const double r = p[15];
+  S e = p[10] * std::exp(-(dx * dx + dy * dy) / (r * r));
+  // d l / d ee
+  S gx = 2.0 * p[8] * ex - 2.0 * e * dx / (r * r);
+  S gy = 2.0 * p[8] * ey - 2.0 * e * dy / (r * r);
+  for (int c = 0; c < 3; ++c) {
+    lx[c] = J[0][c] * gx + J[1][c] * gy;
+    lx[3 + c] = 0.0;
+    lu[c] = 2.0 * p[7] * u[c];
+  }
+}
+
+template <class S>
+S p3_term(const double* p, const S* x) {
+  S ee[2], J[2][3];
+  p3_ee<S>(p, x, ee, J);
+  S ex = ee[0] - p[11], ey = ee[1] - p[12];
+  return p[9] * (ex * ex + ey * ey);
+}
+
+template <class S>
+void p3_term_grad(const double* p, const S* x, S* lx) {
+  S ee[2], J[2][3];
+  p3_ee<S>(p, x, ee, J);
+  S gx = 2.0 * p[9] * (ee[0] - p[11]);
+  S gy = 2.0 * p[9] * (ee[1] - p[12]);
+  for (int c = 0; c < 3; ++c) {
+    lx[c] = J[0][c] * gx + J[1][c] * gy;
+    lx[3 + c] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------ synthetic quadruped
+// p = [dt, w_u, w_T, w_q, w_v, A(18x18), W1(18x18), W2(18x18), e(18), x_nom(37)]
+// x = (q in R^19, v in R^18), u in R^12; with qb = q[0:18]:
+//   M(q) = A^T A + diag(1 + 0.1 sin qb),  b = W1 sin qb + (W2 cos qb) .* v,
+//   v+ = v + dt M^-1 (S u - b),  S = [0_{12x6} I_12]^T,
+//   q+ = q + dt E v+,  E = [I_18; e^T].
+constexpr int QOFF_A = 5, QOFF_W1 = QOFF_A + 324, QOFF_W2 = QOFF_W1 + 324,
+              QOFF_E = QOFF_W2 + 324, QOFF_XN = QOFF_E + 18;
+
+template <class S>
+void quad_dyn(const double* p, const S* x, const S* u, S* xn) {
+  const double dt = p[0];
+  const double* A = p + QOFF_A;
+  const double* W1 = p + QOFF_W1;
+  const double* W2 = p + QOFF_W2;
+  const double* e = p + QOFF_E;
+  const S* q = x;
+  const S* v = x + 19;
+  std::vector<S> M(18 * 18);
+  for (int a = 0; a < 18; ++a)
+    for (int b = 0; b < 18; ++b) {
+      double s = 0.0;
+      for (int k = 0; k < 18; ++k) s += A[k * 18 + a] * A[k * 18 + b];
+      M[a * 18 + b] = s;
+    }
+  for (int a = 0; a < 18; ++a) M[a * 18 + a] += 1.0 + 0.1 * std::sin(q[a]);
+  S rhs[18];
+  for (int i = 0; i < 18; ++i) {
+    S b1 = 0.0, b2 = 0.0;
+    for (int j = 0; j < 18; ++j) {
+      b1 += W1[i * 18 + j] * std::sin(q[j]);
+      b2 += W2[i * 18 + j] * std::cos(q[j]);
+    }
+    S bi = b1 + b2 * v[i];
+    S su = (i >= 6) ? u[i - 6] : S(0.0);
+    rhs[i] = su - bi;
+  }
+  gauss_solve<S>(18, M, rhs, 1);
+  S last = 0.0;
+  for (int i = 0; i < 18; ++i) {
+    xn[19 + i] = v[i] + dt * rhs[i];
+    xn[i] = q[i] + dt * xn[19 + i];
+    last += e[i] * xn[19 + i];
+  }
+  xn[18] = q[18] + dt * last;
+}
+
+template <class S>
+S quad_track(const double* p, const S* x) {
+  const double* xn = p + QOFF_XN;
+  S sq = 0.0, sv = 0.0;
+  for (int i = 0; i < 19; ++i) sq += (x[i] - xn[i]) * (x[i] - xn[i]);
+  for (int i = 19; i < 37; ++i) sv += (x[i] - xn[i]) * (x[i] - xn[i]);
+  return p[3] * sq + p[4] * sv;
+}
+
+template <class S>
+S quad_cost(const double* p, const S* x, const S* u) {
+  S su = 0.0;
+  for (int i = 0; i < 12; ++i) su += u[i] * u[i];
+  return quad_track<S>(p, x) + p[1] * su;
+}
+
+template <class S>
+void quad_cost_grad(const double* p, const S* x, const S* u, S* lx, S* lu) {
+  const double* xn = p + QOFF_XN;
+  for (int i = 0; i < 37; ++i) lx[i] = 2.0 * (i < 19 ? p[3] : p[4]) * (x[i] - xn[i]);
+  for (int i = 0; i < 12; ++i) lu[i] = 2.0 * p[1] * u[i];
+}
+
+template <class S>
+S quad_term(const double* p, const S* x) { return p[2] * quad_track<S>(p, x); }
+
+template <class S>
+void quad_term_grad(const double* p, const S* x, S* lx) {
+  const double* xn = p + QOFF_XN;
+  for (int i = 0; i < 37; ++i) lx[i] = 2.0 * p[2] * (i < 19 ? p[3] : p[4]) * (x[i] - xn[i]);
+}
+
+// ------------------------------------------------------------ linear-quadratic
+// p = [n, m, A(nxn), B(nxm), Q(nxn), R(mxm), Q_T(nxn), x_ref(n)]
+// f = A x + B u, l = (x-x_ref)^T Q (x-x_ref) + u^T R u, l_T with Q_T.
+template <class S>
+void lq_dyn(const Sys& s, const S* x, const S* u, S* xn) {
+  for (int i = 0; i < s.n; ++i) {
+    S v = 0.0;
+    for (int j = 0; j < s.n; ++j) v += s.A[i * s.n + j] * x[j];
+    for (int j = 0; j < s.m; ++j) v += s.B[i * s.m + j] * u[j];
+    xn[i] = v;
+  }
+}
+
+template <class S>
+S quadform(int n, const double* Q, const S* a) {
+  S v = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) v += a[i] * Q[i * n + j] * a[j];
+  return v;
+}
+
+template <class S>
+S lq_cost(const Sys& s, const S* x, const S* u) {
+  std::vector<S> d(s.n);
+  for (int i = 0; i < s.n; ++i) d[i] = x[i] - s.xr[i];
+  return quadform<S>(s.n, s.Q, d.data()) + quadform<S>(s.m, s.R, u);
+}
+
+template <class S>
+void lq_cost_grad(const Sys& s, const S* x, const S* u, S* lx, S* lu) {
+  for (int i = 0; i < s.n; ++i) {
+    S v = 0.0;
+    for (int j = 0; j < s.n; ++j) v += (s.Q[i * s.n + j] + s.Q[j * s.n + i]) * (x[j] - s.xr[j]);
+    lx[i] = v;
+  }
+  for (int i = 0; i < s.m; ++i) {
+    S v = 0.0;
+    for (int j = 0; j < s.m; ++j) v += (s.R[i * s.m + j] + s.R[j * s.m + i]) * u[j];
+    lu[i] = v;
+  }
+}
+
+template <class S>
+S lq_term(const Sys& s, const S* x) {
+  std::vector<S> d(s.n);
+  for (int i = 0; i < s.n; ++i) d[i] = x[i] - s.xr[i];
+  return quadform<S>(s.n, s.QT, d.data());
+}
+
+template <class S>
+void lq_term_grad(const Sys& s, const S* x, S* lx) {
+  for (int i = 0; i < s.n; ++i) {
+    S v = 0.0;
+    for (int j = 0; j < s.n; ++j) v += (s.QT[i * s.n + j] + s.QT[j * s.n + i]) * (x[j] - s.xr[j]);
+    lx[i] = v;
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+bool make_sys(int kind, const double* p, int np, Sys* s) {
+  s->kind = kind;
+  s->p = p;
+  switch (kind) {
+    case KIND_PM:
+      if (np != 16) return false;
+      s->n = 4; s->m = 2;
+      return true;
+    case KIND_P3:
+      if (np != 16) return false;
+      s->n = 6; s->m = 3;
+      return true;
+    case KIND_QUAD:
+      if (np != QOFF_XN + 37) return false;
+      s->n = 37; s->m = 12;
+      return true;
+    case KIND_LQ: {
+      if (np < 2) return false;
+      int n = (int)p[0], m = (int)p[1];
+      if (n < 1 || m < 1 || n > 64 || m > 64) return false;
+      if (np != 2 + 3 * n * n + n * m + m * m + n) return false;
+      s->n = n; s->m = m;
+      const double* c = p + 2;
+      s->A = c; c += n * n;
+      s->B = c; c += n * m;
+      s->Q = c; c += n * n;
+      s->R = c; c += m * m;
+      s->QT = c; c += n * n;
+      s->xr = c;
+      return true;
+    }
+    default:
+      return false;
+  }
+}
+
+template <class S>
+void dyn(const Sys& s, const S* x, const S* u, S* xn) {
+  switch (s.kind) {
+    case KIND_PM: pm_dyn<S>(s.p, x, u, xn); break;
+    case KIND_P3: p3_dyn<S>(s.p, x, u, xn); break;
+    case KIND_QUAD: quad_dyn<S>(s.p, x, u, xn); break;
+    default: lq_dyn<S>(s, x, u, xn); break;
+  }
+}
+
+template <class S>
+S cost(const Sys& s, const S* x, const S* u) {
+  switch (s.kind) {
+    case KIND_PM: return pm_cost<S>(s.p, x, u);
+    case KIND_P3: return p3_cost<S>(s.p, x, u);
+    case KIND_QUAD: return quad_cost<S>(s.p, x, u);
+    default: return lq_cost<S>(s, x, u);
+  }
+}
+
+template <class S>
+void cost_grad(const Sys& s, const S* x, const S* u, S* lx, S* lu) {
+  switch (s.kind) {
+    case KIND_PM: pm_cost_grad<S>(s.p, x, u, lx, lu); break;
+    case KIND_P3: p3_cost_grad<S>(s.p, x, u, lx, lu); break;
+    case KIND_QUAD: quad_cost_grad<S>(s.p, x, u, lx, lu); break;
+    default: lq_cost_grad<S>(s, x, u, lx, lu); break;
+  }
+}
+
+template <class S>
+S term(const Sys& s, const S* x) {
+  switch (s.kind) {
+    case KIND_PM: return pm_term<S>(s.p, x);
+    case KIND_P3: return p3_term<S>(s.p, x);
+    case KIND_QUAD: return quad_term<S>(s.p, x);
+    default: return lq_term<S>(s, x);
+  }
+}
+
+template <class S>
+void term_grad(const Sys& s, const S* x, S* lx) {
+  switch (s.kind) {
+    case KIND_PM: pm_term_grad<S>(s.p, x, lx); break;
+    case KIND_P3: p3_term_grad<S>(s.p, x, lx); break;
+    case KIND_QUAD: quad_term_grad<S>(s.p, x, lx); break;
+    default: lq_term_grad<S>(s, x, lx); break;
+  }
+}
+
+// ------------------------------------------------------------ derivatives
+// Complex step: d f / d z_j = Im f(z + i h e_j) / h, exact to rounding for
+// analytic f (no subtractive cancellation).
+constexpr double CS_H = 1e-30;
+
+void dyn_jac(const Sys& s, const double* x, const double* u, double* A, double* B) {
+  const int n = s.n, m = s.m;
+  std::vector<cd> xc(n), uc(m), out(n);
+  for (int i = 0; i < n; ++i) xc[i] = x[i];
+  for (int i = 0; i < m; ++i) uc[i] = u[i];
+  for (int j = 0; j < n; ++j) {
+    xc[j] = cd(x[j], CS_H);
+    dyn<cd>(s, xc.data(), uc.data(), out.data());
+    for (int i = 0; i < n; ++i) A[i * n + j] = out[i].imag() / CS_H;
+    xc[j] = x[j];
+  }
+  for (int j = 0; j < m; ++j) {
+    uc[j] = cd(u[j], CS_H);
+    dyn<cd>(s, xc.data(), uc.data(), out.data());
+    for (int i = 0; i < n; ++i) B[i * m + j] = out[i].imag() / CS_H;
+    uc[j] = u[j];
+  }
+}
+
+// First and second cost derivatives: lx, lu analytic; lxx, luu, lux by
+// complex step of the analytic gradient.  lux is m x n.
+void cost_derivs(const Sys& s, const double* x, const double* u, double* lx, double* lu,
+                 double* lxx, double* luu, double* lux) {
+  const int n = s.n, m = s.m;
+  cost_grad<double>(s, x, u, lx, lu);
+  std::vector<cd> xc(n), uc(m), gx(n), gu(m);
+  for (int i = 0; i < n; ++i) xc[i] = x[i];
+  for (int i = 0; i < m; ++i) uc[i] = u[i];
+  for (int j = 0; j < n; ++j) {
+    xc[j] = cd(x[j], CS_H);
+    cost_grad<cd>(s, xc.data(), uc.data(), gx.data(), gu.data());
+    for (int i = 0; i < n; ++i) lxx[i * n + j] = gx[i].imag() / CS_H;
+    for (int i = 0; i < m; ++i) lux[i * n + j] = gu[i].imag() / CS_H;
+    xc[j] = x[j];
+  }
+  for (int j = 0; j < m; ++j) {
+    uc[j] = cd(u[j], CS_H);
+    cost_grad<cd>(s, xc.data(), uc.data(), gx.data(), gu.data());
+    for (int i = 0; i < m; ++i) luu[i * m + j] = gu[i].imag() / CS_H;
+    uc[j] = u[j];
+  }
+}
+
+void term_derivs(const Sys& s, const double* x, double* lx, double* lxx) {
+  const int n = s.n;
+  term_grad<double>(s, x, lx);
+  std::vector<cd> xc(n), gx(n);
+  for (int i = 0; i < n; ++i) xc[i] = x[i];
+  for (int j = 0; j < n; ++j) {
+    xc[j] = cd(x[j], CS_H);
+    term_grad<cd>(s, xc.data(), gx.data());
+    for (int i = 0; i < n; ++i) lxx[i * n + j] = gx[i].imag() / CS_H;
+    xc[j] = x[j];
+  }
+}
+
+// ------------------------------------------------------------ eigenvalue clipping (eq. 7)
+// Cyclic Jacobi eigen-decomposition of a symmetric matrix: H = W diag(S) W^T.
+void jacobi_eig(int n, const double* H, double* S, double* W) {
+  std::vector<double> a(H, H + n * n);
+  for (int i = 0; i < n * n; ++i) W[i] = 0.0;
+  for (int i = 0; i < n; ++i) W[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i * n + j] * a[i * n + j];
+        if (i != j) off += a[i * n + j] * a[i * n + j];
+      }
+    if (off == 0.0 || off <= 1e-32 * tot) break;
+    for (int pi = 0; pi < n - 1; ++pi)
+      for (int qi = pi + 1; qi < n; ++qi) {
+        const double apq = a[pi * n + qi];
+        if (apq == 0.0) continue;
+        const double app = a[pi * n + pi], aqq = a[qi * n + qi];
+        // rotation angle that zeroes a_pq (symmetric Schur decomposition)
+        const double tau = (aqq - app) / (2.0 * apq);
+        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // a <- a J   (columns p, q)
+          const double akp = a[k * n + pi], akq = a[k * n + qi];
+          a[k * n + pi] = c * akp - sn * akq;
+          a[k * n + qi] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // a <- J^T a (rows p, q)
+          const double apk = a[pi * n + k], aqk = a[qi * n + k];
+          a[pi * n + k] = c * apk - sn * aqk;
+          a[qi * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {  // W <- W J
+          const double wkp = W[k * n + pi], wkq = W[k * n + qi];
+          W[k * n + pi] = c * wkp - sn * wkq;
+          W[k * n + qi] = sn * wkp + c * wkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) S[i] = a[i * n + i];
+}
+
+// Q_psd = sym(W diag(max(S, eps)) W^T) for the symmetric part of H.
+void psd_clip(int n, const double* H, double eps, double* out) {
+  std::vector<double> Hs(n * n), S(n), W(n * n), Qp(n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Hs[i * n + j] = 0.5 * (H[i * n + j] + H[j * n + i]);
+  jacobi_eig(n, Hs.data(), S.data(), W.data());
+  for (int i = 0; i < n; ++i) S[i] = std::max(S[i], eps);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < n; ++k) v += W[i * n + k] * S[k] * W[j * n + k];
+      Qp[i * n + j] = v;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[i * n + j] = 0.5 * (Qp[i * n + j] + Qp[j * n + i]);
+}
+
+// ------------------------------------------------------------ Cholesky of Q_uu
+// Lower-triangular L with L L^T = A; false on a non-positive or non-finite pivot.
+bool cholesky(int m, const double* A, double* L) {
+  for (int i = 0; i < m * m; ++i) L[i] = 0.0;
+  for (int j = 0; j < m; ++j) {
+    double d = A[j * m + j];
+    for (int k = 0; k < j; ++k) d -= L[j * m + k] * L[j * m + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    const double ljj = std::sqrt(d);
+    L[j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      double v = A[i * m + j];
+      for (int k = 0; k < j; ++k) v -= L[i * m + k] * L[j * m + k];
+      L[i * m + j] = v / ljj;
+    }
+  }
+  return true;
+}
+
+// Solve (L L^T) X = Bm for nrhs columns; Bm is m x nrhs row-major, overwritten.
+void chol_solve(int m, const double* L, double* Bm, int nrhs) {
+  for (int c = 0; c < nrhs; ++c) {
+    for (int i = 0; i < m; ++i) {
+      double v = Bm[i * nrhs + c];
+      for (int k = 0; k < i; ++k) v -= L[i * m + k] * Bm[k * nrhs + c];
+      Bm[i * nrhs + c] = v / L[i * m + i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      double v = Bm[i * nrhs + c];
+      for (int k = i + 1; k < m; ++k) v -= L[k * m + i] * Bm[k * nrhs + c];
+      Bm[i * nrhs + c] = v / L[i * m + i];
+    }
+  }
+}
+
+// ------------------------------------------------------------ one instance
+struct Opts {
+  int32_t max_iter;
+  int32_t ls_trials;
+  int32_t stop_mode;  // 0 fixed iterations, 1 relative-decrease tolerance
+  int32_t lookahead;  // K of the K-step cost-to-go; <= 0 means the horizon
+  double eps;
+  double beta;
+  double rtol;
+};
+
+bool all_finite(const double* v, int k) {
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// J = sum_{k<T} l(x_k,u_k) + l_T(x_T), summed in index order; X = rollout of U.
+double rollout(const Sys& s, int T, const double* x0, const double* U, double* X) {
+  const int n = s.n, m = s.m;
+  for (int i = 0; i < n; ++i) X[i] = x0[i];
+  double J = 0.0;
+  for (int k = 0; k < T; ++k) {
+    J += cost<double>(s, X + k * n, U + k * m);
+    dyn<double>(s, X + k * n, U + k * m, X + (k + 1) * n);
+  }
+  J += term<double>(s, X + T * n);
+  return J;
+}
+
+// Costate lambda_k = l_x + A_k^T lambda_{k+1} (lambda_T = d l_T / dx) and the
+// control gradient g_k = l_u + B_k^T lambda_{k+1} of J along (X, U).
+void costate(const Sys& s, int T, const double* X, const double* U, double* lam, double* g) {
+  const int n = s.n, m = s.m;
+  std::vector<double> A(n * n), B(n * m), lx(n), lu(m), lxx(n * n), luu(m * m), lux(m * n);
+  term_grad<double>(s, X + T * n, lam + T * n);
+  for (int k = T - 1; k >= 0; --k) {
+    dyn_jac(s, X + k * n, U + k * m, A.data(), B.data());
+    cost_grad<double>(s, X + k * n, U + k * m, lx.data(), lu.data());
+    const double* ln = lam + (k + 1) * n;
+    for (int i = 0; i < n; ++i) {
+      double v = lx[i];
+      for (int j = 0; j < n; ++j) v += A[j * n + i] * ln[j];
+      lam[k * n + i] = v;
+    }
+    if (g)
+      for (int i = 0; i < m; ++i) {
+        double v = lu[i];
+        for (int j = 0; j < n; ++j) v += B[j * m + i] * ln[j];
+        g[k * m + i] = v;
+      }
+  }
+}
+
+struct Out {
+  double* X;       // (T+1) x n
+  double* U;       // T x m
+  double* J;
+  int32_t* iters;
+  uint32_t* status;
+  double* trace;   // max_iter+1 or null
+  int32_t* jtrace; // max_iter or null: accepted j per iteration, -1 no step, -2 not run
+  double* margin;  // max_iter or null: min over tried j of |J_hat - J| / |J|
+  double* Vbar;    // T+1 or null
+  double* Vx;      // (T+1) x n or null
+  double* xK;      // (T+1) x n or null
+  const int32_t* force_j;  // max_iter or null: replay these accepted j (-1 = none)
+};
+
+void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Opts& o, Out r) {
+  const int n = s.n, m = s.m;
+  std::vector<double> X((T + 1) * n), U(T * m, 0.0), Xn((T + 1) * n), Un(T * m);
+  std::vector<double> Kg(T * m * n), kf(T * m);
+  if (U0) std::memcpy(U.data(), U0, sizeof(double) * T * m);
+  double J = rollout(s, T, x0, U.data(), X.data());
+  uint32_t status = 0;
+  int iters = 0;
+  bool frozen = false;
+  if (!std::isfinite(J)) {
+    status |= ST_NONFINITE;
+    frozen = true;
+  }
+  if (r.trace) r.trace[0] = J;
+  if (r.jtrace) for (int i = 0; i < o.max_iter; ++i) r.jtrace[i] = -2;
+  if (r.margin) for (int i = 0; i < o.max_iter; ++i) r.margin[i] = INFINITY;
+
+  std::vector<double> A(n * n), B(n * m), lx(n), lu(m), lxx(n * n), luu(m * m), lux(m * n);
+  std::vector<double> Qc(n * n), Rc(m * m), P(n * n), p(n), PA(n * n), PB(n * m);
+  std::vector<double> Qx(n), Qu(m), Qxx(n * n), Quu(m * m), Qux(m * n), L(m * m), rhs(m * (n + 1));
+
+  for (int it = 0; it < o.max_iter && !frozen; ++it) {
+    // ---- backward Riccati sweep
+    term_derivs(s, X.data() + T * n, p.data(), lxx.data());
+    psd_clip(n, lxx.data(), o.eps, P.data());
+    bool ok = true;
+    for (int k = T - 1; k >= 0 && ok; --k) {
+      const double* xk = X.data() + k * n;
+      const double* uk = U.data() + k * m;
+      dyn_jac(s, xk, uk, A.data(), B.data());
+      cost_derivs(s, xk, uk, lx.data(), lu.data(), lxx.data(), luu.data(), lux.data());
+      psd_clip(n, lxx.data(), o.eps, Qc.data());
+      psd_clip(m, luu.data(), o.eps, Rc.data());
+      // PA = P A, PB = P B
+      for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) {
+          double v = 0.0;
+          for (int t = 0; t < n; ++t) v += P[i * n + t] * A[t * n + j];
+          PA[i * n + j] = v;
+        }
+        for (int j = 0; j < m; ++j) {
+          double v = 0.0;
+          for (int t = 0; t < n; ++t) v += P[i * n + t] * B[t * m + j];
+          PB[i * m + j] = v;
+        }
+      }
+      for (int i = 0; i < n; ++i) {  // Q_x = l_x + A^T p ; Q_xx = Q + A^T P A
+        double v = lx[i];
+        for (int t = 0; t < n; ++t) v += A[t * n + i] * p[t];
+        Qx[i] = v;
+        for (int j = 0; j < n; ++j) {
+          double w = Qc[i * n + j];
+          for (int t = 0; t < n; ++t) w += A[t * n + i] * PA[t * n + j];
+          Qxx[i * n + j] = w;
+        }
+      }
+      for (int i = 0; i < m; ++i) {  // Q_u, Q_uu = R + B^T P B, Q_ux = l_ux + B^T P A
+        double v = lu[i];
+        for (int t = 0; t < n; ++t) v += B[t * m + i] * p[t];
+        Qu[i] = v;
+        for (int j = 0; j < m; ++j) {
+          double w = Rc[i * m + j];
+          for (int t = 0; t < n; ++t) w += B[t * m + i] * PB[t * m + j];
+          Quu[i * m + j] = w;
+        }
+        for (int j = 0; j < n; ++j) {
+          double w = lux[i * n + j];
+          for (int t = 0; t < n; ++t) w += B[t * m + i] * PA[t * n + j];
+          Qux[i * n + j] = w;
+        }
+      }
+      if (!cholesky(m, Quu.data(), L.data())) {
+        status |= ST_CHOL_FAIL;
+        ok = false;
+        break;
+      }
+      // [K k] = -Q_uu^-1 [Q_ux Q_u]
+      for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < n; ++j) rhs[i * (n + 1) + j] = Qux[i * n + j];
+        rhs[i * (n + 1) + n] = Qu[i];
+      }
+      chol_solve(m, L.data(), rhs.data(), n + 1);
+      double* Kk = Kg.data() + k * m * n;
+      double* kk = kf.data() + k * m;
+      for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < n; ++j) Kk[i * n + j] = -rhs[i * (n + 1) + j];
+        kk[i] = -rhs[i * (n + 1) + n];
+      }
+      if (!all_finite(Kk, m * n) || !all_finite(kk, m)) {
+        status |= ST_NONFINITE;
+        ok = false;
+        break;
+      }
+      // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
+      for (int i = 0; i < n; ++i) {
+        double v = Qx[i];
+        for (int t = 0; t < m; ++t) v += Qux[t * n + i] * kk[t];
+        p[i] = v;
+        for (int j = 0; j < n; ++j) {
+          double w = Qxx[i * n + j];
+          for (int t = 0; t < m; ++t) w += Qux[t * n + i] * Kk[t * n + j];
+          PA[i * n + j] = w;  // reuse as scratch
+        }
+      }
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) P[i * n + j] = 0.5 * (PA[i * n + j] + PA[j * n + i]);
+    }
+    if (!ok) {
+      frozen = true;
+      if (r.jtrace) r.jtrace[it] = -1;
+      break;
+    }
+    // ---- backtracking line search on the closed-loop rollout
+    int accepted = -1;
+    double Jnew = J;
+    double alpha = 1.0;
+    double margin = INFINITY;
+    const int jmax = o.ls_trials;
+    for (int j = 0; j < jmax; ++j) {
+      if (r.force_j && r.force_j[it] >= 0 && j != r.force_j[it]) {
+        alpha *= o.beta;
+        continue;
+      }
+      if (r.force_j && r.force_j[it] < 0) break;
+      for (int i = 0; i < n; ++i) Xn[i] = X[i];
+      double Jh = 0.0;
+      for (int k = 0; k < T; ++k) {
+        const double* Kk = Kg.data() + k * m * n;
+        const double* kk = kf.data() + k * m;
+        for (int i = 0; i < m; ++i) {
+          double v = U[k * m + i] + alpha * kk[i];
+          for (int t = 0; t < n; ++t) v += Kk[i * n + t] * (Xn[k * n + t] - X[k * n + t]);
+          Un[k * m + i] = v;
+        }
+        Jh += cost<double>(s, Xn.data() + k * n, Un.data() + k * m);
+        dyn<double>(s, Xn.data() + k * n, Un.data() + k * m, Xn.data() + (k + 1) * n);
+      }
+      Jh += term<double>(s, Xn.data() + T * n);
+      if (std::isfinite(Jh)) margin = std::min(margin, std::fabs(Jh - J) / std::max(std::fabs(J), 1e-300));
+      const bool take = r.force_j ? std::isfinite(Jh) : (std::isfinite(Jh) && Jh < J);
+      if (take) {
+        accepted = j;
+        Jnew = Jh;
+        break;
+      }
+      alpha *= o.beta;
+    }
+    if (r.margin) r.margin[it] = margin;
+    if (r.jtrace) r.jtrace[it] = accepted;
+    if (accepted < 0) {
+      status |= ST_LS_FAILED;
+      frozen = true;
+      break;
+    }
+    X.swap(Xn);
+    U.swap(Un);
+    const double Jold = J;
+    J = Jnew;
+    ++iters;
+    if (r.trace) r.trace[it + 1] = J;
+    if (o.stop_mode == 1 && (Jold - J) <= o.rtol * std::fabs(Jold)) {
+      status |= ST_CONVERGED;
+      frozen = true;
+      break;
+    }
+  }
+  if (!frozen) status |= ST_MAX_ITER;
+  if (r.trace)
+    for (int i = iters + 1; i <= o.max_iter; ++i) r.trace[i] = J;
+
+  std::memcpy(r.X, X.data(), sizeof(double) * (T + 1) * n);
+  std::memcpy(r.U, U.data(), sizeof(double) * T * m);
+  *r.J = J;
+  *r.iters = iters;
+  *r.status = status;
+
+  // ---- critic targets on the final trajectory
+  const int K = (o.lookahead <= 0) ? T : o.lookahead;
+  if (r.Vbar) {
+    std::vector<double> c(T + 1);
+    for (int k = 0; k < T; ++k) c[k] = cost<double>(s, X.data() + k * n, U.data() + k * m);
+    c[T] = term<double>(s, X.data() + T * n);
+    for (int k = 0; k <= T; ++k) {
+      const int end = std::min(k + K, T);
+      double v = 0.0;
+      for (int t = k; t < end; ++t) v += c[t];
+      if (k + K >= T) v += c[T];
+      r.Vbar[k] = v;
+    }
+  }
+  if (r.Vx) costate(s, T, X.data(), U.data(), r.Vx, nullptr);
+  if (r.xK)
+    for (int k = 0; k <= T; ++k) {
+      const int t = std::min(k + K, T);
+      for (int i = 0; i < n; ++i) r.xK[k * n + i] = X[t * n + i];
+    }
+}
+
+thread_local char g_err[256];
+
+}  // namespace
+
+extern "C" {
+
+struct orc_opts {
+  int32_t max_iter;
+  int32_t ls_trials;
+  int32_t stop_mode;
+  int32_t lookahead;
+  double eps;
+  double beta;
+  double rtol;
+};
+
+const char* orc_last_error() { return g_err; }
+
+int orc_dims(int kind, const double* p, int np, int* n, int* m) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  *n = s.n;
+  *m = s.m;
+  return 0;
+}
+
+int orc_dyn(int kind, const double* p, int np, const double* x, const double* u, double* xn) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  dyn<double>(s, x, u, xn);
+  return 0;
+}
+
+int orc_dyn_jac(int kind, const double* p, int np, const double* x, const double* u, double* A,
+                double* B) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  dyn_jac(s, x, u, A, B);
+  return 0;
+}
+
+int orc_cost(int kind, const double* p, int np, const double* x, const double* u, double* l) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  *l = cost<double>(s, x, u);
+  return 0;
+}
+
+int orc_cost_derivs(int kind, const double* p, int np, const double* x, const double* u,
+                    double* lx, double* lu, double* lxx, double* luu, double* lux) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  cost_derivs(s, x, u, lx, lu, lxx, luu, lux);
+  return 0;
+}
+
+int orc_term(int kind, const double* p, int np, const double* x, double* l) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  *l = term<double>(s, x);
+  return 0;
+}
+
+int orc_term_derivs(int kind, const double* p, int np, const double* x, double* lx, double* lxx) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  term_derivs(s, x, lx, lxx);
+  return 0;
+}
+
+int orc_psd_clip(int n, const double* H, double eps, double* out) {
+  if (n < 1) return -1;
+  psd_clip(n, H, eps, out);
+  return 0;
+}
+
+int orc_eig(int n, const double* H, double* S, double* W) {
+  if (n < 1) return -1;
+  jacobi_eig(n, H, S, W);
+  return 0;
+}
+
+int orc_p3_mass(const double* p, const double* q, double* M) {
+  double Mm[3][3], dM[3][3][3];
+  p3_mass<double>(p, q, Mm, dM);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[a * 3 + b] = Mm[a][b];
+  return 0;
+}
+
+int orc_p3_ee(const double* p, const double* q, double* ee) {
+  double J[2][3];
+  p3_ee<double>(p, q, ee, J);
+  return 0;
+}
+
+// Total cost of nb control sequences (each T x m) from one x0, in parallel.
+int orc_rollout_costs(int kind, const double* p, int np, int T, const double* x0, int nb,
+                      const double* U, double* J, int nthreads) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  const int n = s.n, m = s.m;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+  {
+    std::vector<double> X((T + 1) * n);
+#pragma omp for schedule(static)
+    for (int b = 0; b < nb; ++b) J[b] = rollout(s, T, x0, U + (size_t)b * T * m, X.data());
+  }
+  return 0;
+}
+
+// Rollout X, total cost J, costate lambda ((T+1) x n) and dJ/dU (T x m).
+int orc_gradient(int kind, const double* p, int np, int T, const double* x0, const double* U,
+                 double* X, double* J, double* lam, double* g) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  *J = rollout(s, T, x0, U, X);
+  costate(s, T, X, U, lam, g);
+  return 0;
+}
+
+// Batched solve.  All arrays are host, row-major, padded to T_max:
+// X[B][Tmax+1][n], U[B][Tmax][m], Vbar[B][Tmax+1], Vx/xK[B][Tmax+1][n],
+// trace[B][max_iter+1], jtrace/margin/force_j[B][max_iter].  Optional ones may be null.
+int orc_solve_batch(int kind, const double* p, int np, int B, int Tmax, const int32_t* Tb,
+                    const double* x0, const double* U0, const orc_opts* opt, double* X, double* U,
+                    double* J, int32_t* iters, uint32_t* status, double* Vbar, double* Vx,
+                    double* xK, double* trace, int32_t* jtrace, double* margin,
+                    const int32_t* force_j, int nthreads) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) {
+    std::snprintf(g_err, sizeof g_err, "bad system kind/params");
+    return -1;
+  }
+  if (B < 0 || Tmax < 1 || !opt || opt->max_iter < 0 || opt->ls_trials < 0) {
+    std::snprintf(g_err, sizeof g_err, "bad sizes/options");
+    return -1;
+  }
+  const int n = s.n, m = s.m;
+  Opts o{opt->max_iter, opt->ls_trials, opt->stop_mode, opt->lookahead, opt->eps, opt->beta, opt->rtol};
+  const size_t sx = (size_t)(Tmax + 1) * n, su = (size_t)Tmax * m;
+  std::memset(X, 0, sizeof(double) * sx * B);
+  std::memset(U, 0, sizeof(double) * su * B);
+  if (Vbar) std::memset(Vbar, 0, sizeof(double) * (Tmax + 1) * B);
+  if (Vx) std::memset(Vx, 0, sizeof(double) * sx * B);
+  if (xK) std::memset(xK, 0, sizeof(double) * sx * B);
+  for (int b = 0; b < B; ++b)
+    if (Tb && (Tb[b] < 1 || Tb[b] > Tmax)) {
+      std::snprintf(g_err, sizeof g_err, "horizon out of range");
+      return -1;
+    }
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+  for (int b = 0; b < B; ++b) {
+    const int T = Tb ? Tb[b] : Tmax;
+    std::vector<double> U0t;
+    const double* u0 = nullptr;
+    if (U0) {
+      U0t.assign(U0 + (size_t)b * su, U0 + (size_t)b * su + (size_t)T * m);
+      u0 = U0t.data();
+    }
+    Out r{X + b * sx, U + b * su, J + b, iters + b, status + b,
+          trace ? trace + (size_t)b * (o.max_iter + 1) : nullptr,
+          jtrace ? jtrace + (size_t)b * o.max_iter : nullptr,
+          margin ? margin + (size_t)b * o.max_iter : nullptr,
+          Vbar ? Vbar + (size_t)b * (Tmax + 1) : nullptr,
+          Vx ? Vx + b * sx : nullptr,
+          xK ? xK + b * sx : nullptr,
+          force_j ? force_j + (size_t)b * o.max_iter : nullptr};
+    solve_one(s, T, x0 + (size_t)b * n, u0, o, r);
+  }
+  return 0;
+}
+
+int orc_max_threads() { return omp_get_max_threads(); }
+
+}  // extern "C"

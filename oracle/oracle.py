@@ -1,0 +1,229 @@
+"""ctypes binding of the FP64 CPU oracle (oracle.cpp).
+
+Test infrastructure only: the tests, the smoke check and the CPU-baseline leg
+of the benchmark use it; the solver library never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+ST_CONVERGED, ST_MAX_ITER, ST_LS_FAILED, ST_NONFINITE, ST_CHOL_FAIL = 1, 2, 4, 8, 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no contraction, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
+               "-shared", "-Wall", "-o", LIB + ".tmp", SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Opts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("ls_trials", C.c_int32),
+                ("stop_mode", C.c_int32), ("lookahead", C.c_int32),
+                ("eps", C.c_double), ("beta", C.c_double), ("rtol", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        _lib = C.CDLL(LIB)
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Options:
+    max_iter: int = 50
+    ls_trials: int = 16
+    stop_mode: int = 0
+    lookahead: int = 0
+    eps: float = 1e-6
+    beta: float = 0.5
+    rtol: float = 1e-10
+
+    def c(self):
+        return _Opts(self.max_iter, self.ls_trials, self.stop_mode, self.lookahead,
+                     self.eps, self.beta, self.rtol)
+
+
+def dims(kind, params):
+    params = _f64(params)
+    n, m = C.c_int(), C.c_int()
+    if lib().orc_dims(kind, _p(params), len(params), C.byref(n), C.byref(m)) != 0:
+        raise ValueError("bad system kind / parameter vector")
+    return n.value, m.value
+
+
+def dyn(kind, params, x, u):
+    params = _f64(params)
+    n, _ = dims(kind, params)
+    out = np.zeros(n)
+    lib().orc_dyn(kind, _p(params), len(params), _p(_f64(x)), _p(_f64(u)), _p(out))
+    return out
+
+
+def dyn_jac(kind, params, x, u):
+    params = _f64(params)
+    n, m = dims(kind, params)
+    A, B = np.zeros((n, n)), np.zeros((n, m))
+    lib().orc_dyn_jac(kind, _p(params), len(params), _p(_f64(x)), _p(_f64(u)), _p(A), _p(B))
+    return A, B
+
+
+def cost(kind, params, x, u):
+    params = _f64(params)
+    out = C.c_double()
+    lib().orc_cost(kind, _p(params), len(params), _p(_f64(x)), _p(_f64(u)), C.byref(out))
+    return out.value
+
+
+def cost_derivs(kind, params, x, u):
+    params = _f64(params)
+    n, m = dims(kind, params)
+    lx, lu = np.zeros(n), np.zeros(m)
+    lxx, luu, lux = np.zeros((n, n)), np.zeros((m, m)), np.zeros((m, n))
+    lib().orc_cost_derivs(kind, _p(params), len(params), _p(_f64(x)), _p(_f64(u)),
+                          _p(lx), _p(lu), _p(lxx), _p(luu), _p(lux))
+    return lx, lu, lxx, luu, lux
+
+
+def term(kind, params, x):
+    params = _f64(params)
+    out = C.c_double()
+    lib().orc_term(kind, _p(params), len(params), _p(_f64(x)), C.byref(out))
+    return out.value
+
+
+def term_derivs(kind, params, x):
+    params = _f64(params)
+    n, _ = dims(kind, params)
+    lx, lxx = np.zeros(n), np.zeros((n, n))
+    lib().orc_term_derivs(kind, _p(params), len(params), _p(_f64(x)), _p(lx), _p(lxx))
+    return lx, lxx
+
+
+def psd_clip(H, eps):
+    H = _f64(H)
+    out = np.zeros_like(H)
+    lib().orc_psd_clip(H.shape[0], _p(H), C.c_double(eps), _p(out))
+    return out
+
+
+def eig(H):
+    H = _f64(H)
+    n = H.shape[0]
+    S, W = np.zeros(n), np.zeros((n, n))
+    lib().orc_eig(n, _p(H), _p(S), _p(W))
+    return S, W
+
+
+def p3_mass(params, q):
+    M = np.zeros((3, 3))
+    lib().orc_p3_mass(_p(_f64(params)), _p(_f64(q)), _p(M))
+    return M
+
+
+def p3_ee(params, q):
+    ee = np.zeros(2)
+    lib().orc_p3_ee(_p(_f64(params)), _p(_f64(q)), _p(ee))
+    return ee
+
+
+def rollout_costs(kind, params, x0, U, nthreads=0):
+    """Total cost of each control sequence in U (nb, T, m) from one x0."""
+    params = _f64(params)
+    U = _f64(U)
+    nb, T = U.shape[0], U.shape[1]
+    J = np.zeros(nb)
+    lib().orc_rollout_costs(kind, _p(params), len(params), T, _p(_f64(x0)), nb, _p(U), _p(J),
+                            nthreads)
+    return J
+
+
+def gradient(kind, params, x0, U):
+    """(X, J, lambda, dJ/dU) along the rollout of U from x0."""
+    params = _f64(params)
+    U = _f64(U)
+    n, m = dims(kind, params)
+    T = U.shape[0]
+    X, lam, g = np.zeros((T + 1, n)), np.zeros((T + 1, n)), np.zeros((T, m))
+    J = C.c_double()
+    lib().orc_gradient(kind, _p(params), len(params), T, _p(_f64(x0)), _p(U), _p(X),
+                       C.byref(J), _p(lam), _p(g))
+    return X, J.value, lam, g
+
+
+@dataclass
+class Result:
+    X: np.ndarray
+    U: np.ndarray
+    J: np.ndarray
+    iters: np.ndarray
+    status: np.ndarray
+    Vbar: np.ndarray
+    Vx: np.ndarray
+    xK: np.ndarray
+    trace: np.ndarray
+    jtrace: np.ndarray
+    margin: np.ndarray
+
+
+def solve_batch(kind, params, x0, T_max, T=None, U0=None, opts: Options | None = None,
+                force_j=None, nthreads=0) -> Result:
+    """Solve every instance (rows of x0) on the CPU in FP64."""
+    opts = opts or Options()
+    params = _f64(params)
+    x0 = _f64(x0)
+    n, m = dims(kind, params)
+    B = x0.shape[0]
+    Tb = None if T is None else np.ascontiguousarray(T, dtype=np.int32)
+    U0c = None if U0 is None else _f64(U0).reshape(B, T_max, m)
+    fj = None if force_j is None else np.ascontiguousarray(force_j, dtype=np.int32)
+    X = np.zeros((B, T_max + 1, n))
+    U = np.zeros((B, T_max, m))
+    J = np.zeros(B)
+    iters = np.zeros(B, np.int32)
+    status = np.zeros(B, np.uint32)
+    Vbar = np.zeros((B, T_max + 1))
+    Vx = np.zeros((B, T_max + 1, n))
+    xK = np.zeros((B, T_max + 1, n))
+    trace = np.zeros((B, opts.max_iter + 1))
+    jtrace = np.zeros((B, max(opts.max_iter, 1)), np.int32)
+    margin = np.zeros((B, max(opts.max_iter, 1)))
+    o = opts.c()
+    rc = lib().orc_solve_batch(kind, _p(params), len(params), B, T_max, _p(Tb), _p(x0), _p(U0c),
+                               C.byref(o), _p(X), _p(U), _p(J), _p(iters), _p(status), _p(Vbar),
+                               _p(Vx), _p(xK), _p(trace), _p(jtrace), _p(margin), _p(fj),
+                               nthreads)
+    if rc != 0:
+        lib().orc_last_error.restype = C.c_char_p
+        raise ValueError(lib().orc_last_error().decode())
+    return Result(X, U, J, iters, status, Vbar, Vx, xK, trace, jtrace, margin)
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
