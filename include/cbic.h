@@ -1,0 +1,241 @@
+/*
+ * cbic.h -- C ABI of the MI355X batched trajectory-optimisation solver.
+ *
+ * The library solves many finite-horizon discrete-time optimal control
+ * problems at once, one per initial state (paper Sec. II, eq. 1):
+ *
+ *     min_{X,U}  sum_{k=0}^{T-1} l(x_k, u_k) + l_T(x_T)
+ *     s.t.       x_{k+1} = f(x_k, u_k),  x_0 = x_init,
+ *
+ * with x in R^n and u in R^m, by iLQR (paper Sec. II and IV): a forward
+ * rollout, analytic linearisation and quadratisation, eigenvalue clipping of
+ * the state- and control-cost Hessians (Sec. IV-B, eq. 7), a backward Riccati
+ * sweep with a Cholesky factorisation of Q_uu, a backtracking line search, a
+ * fixed iteration budget shared by the whole batch (Sec. IV-A), and at the end
+ * the critic targets of Sec. II: the K-step partial cost-to-go V-bar of every
+ * state, its gradient V-bar_x from the backward (costate) pass, and the state
+ * K steps later.  The control bound |u| <= u_max of eq. 1 is not supported.
+ *
+ * Conventions for every call
+ *  - Return value: CBIC_OK (0) on success, CBIC_NOT_READY (1) for a pending
+ *    result, a negative cbic_status on error.  No C++ exception crosses the
+ *    ABI.  cbic_last_error() returns a message for the last failing call on
+ *    the calling thread (valid until that thread's next failing call).
+ *  - Invalid arguments are rejected with CBIC_E_INVALID before anything is
+ *    launched.  Per-instance numerical outcomes are never errors; they are
+ *    reported in the per-instance status word (CBIC_ST_* bits).
+ *  - Pointers named d_* are device pointers (HIP device memory of the
+ *    context's GPU); pointers named h_* are host pointers.  All arrays are
+ *    C-contiguous, row-major, double precision unless stated otherwise, and
+ *    8-byte aligned.  The caller owns every buffer it passes; the library
+ *    never frees or retains caller memory beyond the call (device outputs are
+ *    written by work enqueued on the caller's stream).
+ *  - Stream ordering: cbic_solve_batch enqueues its kernels on the given HIP
+ *    stream (hipStream_t passed as void*, NULL = the null stream) and returns
+ *    without waiting; outputs are valid once that stream has completed the
+ *    work.  A context's workspace serves one solve at a time: a solve on a
+ *    different stream than the previous one first waits for the previous one.
+ *
+ * Parameter vectors (double, copied at cbic_system_create):
+ *  CBIC_SYS_LQ          [n, m, A(n x n), B(n x m), Q(n x n), R(m x m), Q_T(n x n), x_ref(n)]
+ *                       f = A x + B u, l = (x-x_ref)^T Q (x-x_ref) + u^T R u,
+ *                       l_T = (x-x_ref)^T Q_T (x-x_ref).  (n,m) in {(2,1),(4,2),(6,3)}.
+ *  CBIC_SYS_POINT_MASS  [dt, w_u, w_p, w_T, w_o, g_x, g_y, (c_x, c_y, r) x 3]   (n=4, m=2)
+ *                       2-D double integrator, semi-implicit Euler v+ = v + dt u,
+ *                       p+ = p + dt v+; l = w_u|u|^2 + w_p|p-g|^2
+ *                       + w_o sum_i exp(-|p-c_i|^2/r_i^2); l_T = w_T(|p-g|^2 + |v|^2).
+ *  CBIC_SYS_PLANAR3     [dt, m1, m2, m3, l1, l2, l3, w_u, w_ee, w_T, w_o, p_x, p_y, c_x, c_y, r]
+ *                       (n=6, m=3) planar arm of uniform rods in a horizontal
+ *                       plane, relative joint angles, semi-implicit Euler;
+ *                       l = w_u|tau|^2 + w_ee|ee-p|^2 + w_o exp(-|ee-c|^2/r^2);
+ *                       l_T = w_T|ee-p|^2.
+ *  CBIC_SYS_QUAD_SYNTH  [dt, w_u, w_T, w_q, w_v, A(18x18), W1(18x18), W2(18x18), e(18), x_nom(37)]
+ *                       (n=37 with q in R^19, v in R^18; m=12)
+ *                       M(q) = A^T A + diag(1 + 0.1 sin q[0:18]),
+ *                       b = W1 sin q[0:18] + (W2 cos q[0:18]) .* v,
+ *                       v+ = v + dt M^-1 ([0_6; u] - b), q+ = q + dt [I_18; e^T] v+;
+ *                       l = w_q|q-q_nom|^2 + w_v|v-v_nom|^2 + w_u|u|^2,
+ *                       l_T = w_T (w_q|q-q_nom|^2 + w_v|v-v_nom|^2).
+ */
+#ifndef CBIC_H
+#define CBIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cbic_status;
+#define CBIC_OK 0
+#define CBIC_NOT_READY 1
+#define CBIC_E_INVALID (-1)     /* bad argument; nothing was launched          */
+#define CBIC_E_OOM (-2)         /* workspace would exceed the context's cap     */
+#define CBIC_E_HIP (-3)         /* a HIP runtime call failed                    */
+#define CBIC_E_BUSY (-4)        /* server: the request can never be admitted    */
+#define CBIC_E_UNSUPPORTED (-5) /* valid but not supported (e.g. LQ dimensions)  */
+
+/* Per-instance status bits (cbic_outputs.status).  Exactly one of the first
+ * three describes how the iteration ended; NONFINITE / CHOL_FAIL mark a
+ * numerical stop.  The returned trajectory is always the last accepted one. */
+#define CBIC_ST_CONVERGED 1u  /* tolerance mode: relative decrease <= rtol        */
+#define CBIC_ST_MAX_ITER 2u   /* the iteration budget was used up                 */
+#define CBIC_ST_LS_FAILED 4u  /* no trial step lowered the cost: frozen           */
+#define CBIC_ST_NONFINITE 8u  /* non-finite cost or gains: frozen                 */
+#define CBIC_ST_CHOL_FAIL 16u /* Q_uu not positive definite: frozen               */
+#define CBIC_ST_BAD_INPUT 32u /* horizon outside 1..T_max: instance not solved,
+                                 J = NaN and all its trajectory outputs zero       */
+
+typedef enum {
+  CBIC_SYS_LQ = 0,
+  CBIC_SYS_POINT_MASS = 1,
+  CBIC_SYS_PLANAR3 = 2,
+  CBIC_SYS_QUAD_SYNTH = 3
+} cbic_system_kind;
+
+typedef enum { CBIC_FP64 = 0, CBIC_MIXED = 1 } cbic_precision;
+
+typedef struct cbic_context cbic_context;
+typedef struct cbic_system cbic_system;
+typedef struct cbic_server cbic_server;
+
+/* Solver options.  Fill with cbic_opts_default() and then change fields;
+ * struct_size must equal sizeof(cbic_solve_opts). */
+typedef struct {
+  uint32_t struct_size;
+  int32_t max_iter;      /* iteration budget for every instance (>= 0); default 50          */
+  double psd_eps;        /* eigenvalue floor of the clipped Hessians (>= 0); default 1e-6   */
+  int32_t ls_max_trials; /* line-search trials alpha = beta^j, j < trials (>= 0); default 16 */
+  double ls_beta;        /* backtracking factor in (0,1); default 0.5                        */
+  int32_t stop_mode;     /* 0: run the budget (freeze only on failure); 1: also stop when an
+                            accepted step lowers J by at most rtol*|J|                       */
+  double rtol;           /* default 1e-10                                                    */
+  int32_t lookahead_K;   /* K of the K-step cost-to-go; <= 0 means the horizon (default 0)  */
+  int32_t precision;     /* cbic_precision; default CBIC_FP64                                */
+  int32_t schedule;      /* 0 = automatic (tuned table), else a schedule id (see below)      */
+  int32_t iters_per_launch; /* G: iterations per kernel launch; <= 0 = all in one launch     */
+  uint32_t flags;        /* CBIC_FLAG_* bits                                                 */
+} cbic_solve_opts;
+
+/* schedule ids */
+#define CBIC_SCHED_LANE 1  /* one lane per instance, registers + step-major HBM          */
+#define CBIC_SCHED_GROUP 2 /* a workgroup per instance, matrices in LDS (37-dim system)   */
+
+/* flags */
+#define CBIC_FLAG_GRAPH 1u /* launch the iteration chain through a captured HIP graph */
+
+/* Output buffers: caller-owned DEVICE pointers, AoS per instance, padded to
+ * T_max; entries past an instance's horizon are written as zero.
+ * Required: X[B][T_max+1][n], U[B][T_max][m], J[B] (double), iters[B] (int32),
+ * status[B] (uint32).  Optional (NULL = not computed): Vbar[B][T_max+1],
+ * Vx[B][T_max+1][n], xK[B][T_max+1][n], cost_trace[B][max_iter+1] (J after each
+ * accepted iteration, then repeated), work[B][2] (int32: backward sweeps and
+ * line-search trials that instance ran). */
+typedef struct {
+  double* X;
+  double* U;
+  double* J;
+  int32_t* iters;
+  uint32_t* status;
+  double* Vbar;
+  double* Vx;
+  double* xK;
+  double* cost_trace;
+  int32_t* work;
+} cbic_outputs;
+
+/* Last error message of the calling thread ("" if none). */
+const char* cbic_last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t cbic_version(void);
+
+/* Fill *opts with the defaults listed above. */
+cbic_status cbic_opts_default(cbic_solve_opts* opts);
+
+/* Create a context on HIP device `hip_device`.  workspace_cap_bytes bounds the
+ * device memory the context may allocate for its workspace (0 = no bound).
+ * The context owns its workspace and frees it in cbic_context_destroy. */
+cbic_status cbic_context_create(int hip_device, size_t workspace_cap_bytes, cbic_context** out);
+cbic_status cbic_context_destroy(cbic_context* ctx);
+
+/* Create a system of the given kind from its parameter vector (host memory,
+ * copied).  ctx may be NULL: the system is then only validated and usable for
+ * cbic_system_dims / cbic_workspace_size; a solve needs a system created on
+ * that solve's context (its device copy of the parameters lives there).
+ * Errors: CBIC_E_INVALID for a wrong length or non-finite entry. */
+cbic_status cbic_system_create(cbic_context* ctx, cbic_system_kind kind, const double* h_params,
+                               size_t n_params, cbic_system** out);
+cbic_status cbic_system_dims(const cbic_system* sys, int32_t* n, int32_t* m);
+cbic_status cbic_system_destroy(cbic_system* sys);
+
+/* Device workspace a solve of B instances with horizon capacity T_max needs. */
+cbic_status cbic_workspace_size(const cbic_system* sys, int32_t B, int32_t T_max, const cbic_solve_opts* opts,
+                                size_t* bytes);
+
+/* Solve B instances (paper Sec. II, eq. 1; iLQR of Sec. IV).
+ *  d_T   [B] int32 horizons in 1..T_max, or NULL for T_max everywhere;
+ *  d_x0  [B][n] initial states (required);
+ *  d_U0  [B][T_max][m] warm-start controls, or NULL for zeros (the initial
+ *        states are the rollout of these controls).
+ * Enqueues on `stream` and returns.  Errors: CBIC_E_INVALID (B < 1,
+ * T_max < 1, NULL required pointer, misaligned pointer, bad opts),
+ * CBIC_E_OOM, CBIC_E_HIP. */
+cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max,
+                             const int32_t* d_T, const double* d_x0, const double* d_U0,
+                             const cbic_solve_opts* opts, const cbic_outputs* out, void* stream);
+
+/* ---------------------------------------------------------------- serving
+ * A continuous-batching request loop.  Requests (one TO instance each, any
+ * system created on the server's context, any horizon up to that system
+ * class's T_max) are admitted into per-class device slot pools while their
+ * device footprint fits under mem_cap_bytes; admitted requests iterate
+ * G iterations per launch beside the requests already resident, so work of
+ * requests that arrive while others run overlaps on the GPU.  Their iterates
+ * stay in device memory until they finish; finished slots are extracted,
+ * copied to host and freed for new admissions. */
+typedef struct {
+  uint32_t struct_size;
+  size_t mem_cap_bytes;    /* device memory for all slot pools; default 32 GiB              */
+  int32_t slots_per_class; /* slots of each (system, precision) pool; default 4096           */
+  int32_t t_max;           /* largest horizon a request may have; default 200               */
+  int32_t iters_per_launch;/* G; default 4                                                  */
+} cbic_server_opts;
+
+/* Per-request result: host buffers the caller provides to cbic_server_poll.
+ * X[(T+1) n], U[T m], Vbar[T+1], Vx[(T+1) n] (Vbar, Vx may be NULL). */
+typedef struct {
+  double* X;
+  double* U;
+  double* Vbar;
+  double* Vx;
+  double J;
+  int32_t iters;
+  uint32_t status;
+  double t_submit;   /* seconds, server clock */
+  double t_admit;
+  double t_done;
+} cbic_result;
+
+cbic_status cbic_server_opts_default(cbic_server_opts* opts);
+cbic_status cbic_server_create(cbic_context* ctx, const cbic_server_opts* opts, cbic_server** out);
+/* Queue one request.  h_x0 [n]; h_U0 [T][m] or NULL.  The solve options of the
+ * request's class are fixed by the first request of that (system, precision).
+ * Returns a ticket.  CBIC_E_BUSY if the request can never fit under the cap. */
+cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t T, const double* h_x0,
+                               const double* h_U0, const cbic_solve_opts* opts, uint64_t* ticket);
+/* CBIC_OK with *out filled once the ticket is done (the ticket is then
+ * released), CBIC_NOT_READY while pending, CBIC_E_INVALID for an unknown ticket. */
+cbic_status cbic_server_poll(cbic_server* srv, uint64_t ticket, cbic_result* out);
+/* Server clock in seconds (the time base of cbic_result's t_* fields). */
+double cbic_server_clock(const cbic_server* srv);
+/* Block until every submitted request is done. */
+cbic_status cbic_server_drain(cbic_server* srv);
+cbic_status cbic_server_destroy(cbic_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBIC_H */

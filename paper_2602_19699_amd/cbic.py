@@ -1,0 +1,294 @@
+"""Python binding of the C ABI in include/cbic.h (argument marshalling only).
+
+Every step of the solve runs in the HIP kernels of libcbic.so; PyTorch is used
+here only to hold device memory and to name the stream.  If the library is
+missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcbic.so")
+
+OK, NOT_READY = 0, 1
+E_INVALID, E_OOM, E_HIP, E_BUSY, E_UNSUPPORTED = -1, -2, -3, -4, -5
+ST_CONVERGED, ST_MAX_ITER, ST_LS_FAILED, ST_NONFINITE, ST_CHOL_FAIL, ST_BAD_INPUT = 1, 2, 4, 8, 16, 32
+SYS_LQ, SYS_POINT_MASS, SYS_PLANAR3, SYS_QUAD_SYNTH = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+SCHED_AUTO, SCHED_LANE, SCHED_GROUP = 0, 1, 2
+FLAG_GRAPH = 1
+
+
+class CbicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cbic error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("max_iter", C.c_int32), ("psd_eps", C.c_double),
+                ("ls_max_trials", C.c_int32), ("ls_beta", C.c_double), ("stop_mode", C.c_int32),
+                ("rtol", C.c_double), ("lookahead_K", C.c_int32), ("precision", C.c_int32),
+                ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("flags", C.c_uint32)]
+
+
+class _Outputs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("X", "U", "J", "iters", "status", "Vbar", "Vx", "xK",
+                                            "cost_trace", "work")]
+
+
+class _ServerOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("mem_cap_bytes", C.c_size_t), ("slots_per_class", C.c_int32),
+                ("t_max", C.c_int32), ("iters_per_launch", C.c_int32)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("X", C.c_void_p), ("U", C.c_void_p), ("Vbar", C.c_void_p), ("Vx", C.c_void_p),
+                ("J", C.c_double), ("iters", C.c_int32), ("status", C.c_uint32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+_lib = None
+
+# every entry point of include/cbic.h with its ctypes signature
+_SIGS = {
+    "cbic_last_error": (C.c_char_p, []),
+    "cbic_version": (C.c_int32, []),
+    "cbic_opts_default": (C.c_int32, [C.c_void_p]),
+    "cbic_context_create": (C.c_int32, [C.c_int, C.c_size_t, C.c_void_p]),
+    "cbic_context_destroy": (C.c_int32, [C.c_void_p]),
+    "cbic_system_create": (C.c_int32, [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "cbic_system_dims": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_system_destroy": (C.c_int32, [C.c_void_p]),
+    "cbic_workspace_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    "cbic_solve_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_server_opts_default": (C.c_int32, [C.c_void_p]),
+    "cbic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_server_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p]),
+    "cbic_server_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p]),
+    "cbic_server_clock": (C.c_double, [C.c_void_p]),
+    "cbic_server_drain": (C.c_int32, [C.c_void_p]),
+    "cbic_server_destroy": (C.c_int32, [C.c_void_p]),
+}
+
+
+def lib():
+    """Load libcbic.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2602_19699_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code < 0:
+        raise CbicError(code, lib().cbic_last_error().decode())
+    return code
+
+
+@dataclass
+class Options:
+    max_iter: int = 50
+    psd_eps: float = 1e-6
+    ls_max_trials: int = 16
+    ls_beta: float = 0.5
+    stop_mode: int = 0
+    rtol: float = 1e-10
+    lookahead_K: int = 0
+    precision: int = FP64
+    schedule: int = SCHED_AUTO
+    iters_per_launch: int = 0
+    flags: int = 0
+
+    def c(self) -> _Opts:
+        o = _Opts()
+        _check(lib().cbic_opts_default(C.byref(o)))
+        for f in ("max_iter", "psd_eps", "ls_max_trials", "ls_beta", "stop_mode", "rtol", "lookahead_K",
+                  "precision", "schedule", "iters_per_launch", "flags"):
+            setattr(o, f, getattr(self, f))
+        return o
+
+
+class Context:
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
+        self.h = C.c_void_p()
+        _check(lib().cbic_context_create(device, workspace_cap, C.byref(self.h)))
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _check(lib().cbic_context_destroy(self.h))
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class System:
+    def __init__(self, ctx: Context | None, kind: int, params):
+        self.params = np.ascontiguousarray(params, dtype=np.float64)
+        self.kind = kind
+        self.ctx = ctx
+        self.h = C.c_void_p()
+        _check(lib().cbic_system_create(ctx.h if ctx else None, kind, self.params.ctypes.data,
+                                        self.params.size, C.byref(self.h)))
+        n, m = C.c_int32(), C.c_int32()
+        _check(lib().cbic_system_dims(self.h, C.byref(n), C.byref(m)))
+        self.n, self.m = n.value, m.value
+
+    def workspace_size(self, B, T_max, opts: Options | None = None):
+        o = (opts or Options()).c()
+        v = C.c_size_t()
+        _check(lib().cbic_workspace_size(self.h, B, T_max, C.byref(o), C.byref(v)))
+        return v.value
+
+    def close(self):
+        if self.h:
+            _check(lib().cbic_system_destroy(self.h))
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Outputs:
+    """Device tensors of one solve (torch, on the context's GPU)."""
+    X: object
+    U: object
+    J: object
+    iters: object
+    status: object
+    Vbar: object = None
+    Vx: object = None
+    xK: object = None
+    cost_trace: object = None
+    work: object = None
+
+    @staticmethod
+    def allocate(B, T_max, n, m, device, targets=True, trace_iters=None, work=True):
+        import torch
+        f64 = dict(dtype=torch.float64, device=device)
+        i32 = dict(dtype=torch.int32, device=device)
+        return Outputs(
+            X=torch.empty(B, T_max + 1, n, **f64), U=torch.empty(B, T_max, m, **f64),
+            J=torch.empty(B, **f64), iters=torch.empty(B, **i32), status=torch.empty(B, **i32),
+            Vbar=torch.empty(B, T_max + 1, **f64) if targets else None,
+            Vx=torch.empty(B, T_max + 1, n, **f64) if targets else None,
+            xK=torch.empty(B, T_max + 1, n, **f64) if targets else None,
+            cost_trace=torch.empty(B, trace_iters + 1, **f64) if trace_iters is not None else None,
+            work=torch.empty(B, 2, **i32) if work else None)
+
+    def c(self) -> _Outputs:
+        o = _Outputs()
+        for f in _Outputs._fields_:
+            t = getattr(self, f[0])
+            setattr(o, f[0], None if t is None else t.data_ptr())
+        return o
+
+
+def _dptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def solve_batch(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts: Options | None = None,
+                out: Outputs | None = None, targets=True, trace=False, stream=None) -> Outputs:
+    """Enqueue a batched solve; inputs are torch device tensors (float64 / int32)."""
+    import torch
+    opts = opts or Options()
+    dev = torch.device("cuda", ctx.device)
+    x0 = x0.to(device=dev, dtype=torch.float64).contiguous()
+    B = x0.shape[0]
+    if T is not None:
+        T = T.to(device=dev, dtype=torch.int32).contiguous()
+    if U0 is not None:
+        U0 = U0.to(device=dev, dtype=torch.float64).contiguous()
+    if out is None:
+        out = Outputs.allocate(B, T_max, sys.n, sys.m, dev, targets=targets,
+                               trace_iters=opts.max_iter if trace else None)
+    o = opts.c()
+    oc = out.c()
+    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().cbic_solve_batch(ctx.h, sys.h, B, T_max, _dptr(T), x0.data_ptr(), _dptr(U0), C.byref(o),
+                                  C.byref(oc), st))
+    out._keep = (x0, T, U0)  # keep inputs alive until the caller synchronises
+    return out
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    def __init__(self, ctx: Context, mem_cap=32 << 30, slots_per_class=4096, t_max=200, iters_per_launch=4):
+        o = _ServerOpts()
+        _check(lib().cbic_server_opts_default(C.byref(o)))
+        o.mem_cap_bytes = mem_cap
+        o.slots_per_class = slots_per_class
+        o.t_max = t_max
+        o.iters_per_launch = iters_per_launch
+        self.h = C.c_void_p()
+        _check(lib().cbic_server_create(ctx.h, C.byref(o), C.byref(self.h)))
+        self.ctx = ctx
+        self._req = {}
+
+    def submit(self, sys: System, x0, T: int, U0=None, opts: Options | None = None) -> int:
+        x0 = np.ascontiguousarray(x0, dtype=np.float64)
+        U0c = None if U0 is None else np.ascontiguousarray(U0, dtype=np.float64)
+        o = (opts or Options()).c()
+        tk = C.c_uint64()
+        _check(lib().cbic_server_submit(self.h, sys.h, T, x0.ctypes.data,
+                                        None if U0c is None else U0c.ctypes.data, C.byref(o), C.byref(tk)))
+        self._req[tk.value] = (sys.n, sys.m, T)
+        return tk.value
+
+    def poll(self, ticket: int, targets=True):
+        n, m, T = self._req[ticket]
+        X = np.zeros((T + 1, n))
+        U = np.zeros((T, m))
+        Vb = np.zeros(T + 1) if targets else None
+        Vx = np.zeros((T + 1, n)) if targets else None
+        r = _Result()
+        r.X, r.U = X.ctypes.data, U.ctypes.data
+        r.Vbar = None if Vb is None else Vb.ctypes.data
+        r.Vx = None if Vx is None else Vx.ctypes.data
+        code = _check(lib().cbic_server_poll(self.h, ticket, C.byref(r)))
+        if code == NOT_READY:
+            return None
+        del self._req[ticket]
+        return dict(X=X, U=U, Vbar=Vb, Vx=Vx, J=r.J, iters=r.iters, status=r.status,
+                    t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done)
+
+    def clock(self) -> float:
+        return lib().cbic_server_clock(self.h)
+
+    def drain(self):
+        _check(lib().cbic_server_drain(self.h))
+
+    def close(self):
+        if self.h:
+            _check(lib().cbic_server_destroy(self.h))
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

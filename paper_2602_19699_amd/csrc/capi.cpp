@@ -1,0 +1,314 @@
+// extern "C" entry points of include/cbic.h: argument validation, context and
+// system objects, workspace management and the batched solve.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "runtime.hpp"
+
+namespace cbic {
+const char* last_error();
+bool make_device_block(cbic_system* s, double eps);
+bool validate_params(int kind, const double* p, size_t np, int* n, int* m);
+}  // namespace cbic
+
+using namespace cbic;
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));                    \
+      return CBIC_E_HIP;                                                           \
+    }                                                                              \
+  } while (0)
+
+namespace {
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+cbic_status check_opts(const cbic_solve_opts* o) {
+  if (!o) { set_error("opts is NULL"); return CBIC_E_INVALID; }
+  if (o->struct_size != sizeof(cbic_solve_opts)) {
+    set_error("opts.struct_size is %u, expected %zu", o->struct_size, sizeof(cbic_solve_opts));
+    return CBIC_E_INVALID;
+  }
+  if (o->max_iter < 0) { set_error("max_iter must be >= 0"); return CBIC_E_INVALID; }
+  if (!(o->psd_eps >= 0.0) || !std::isfinite(o->psd_eps)) { set_error("psd_eps must be finite and >= 0"); return CBIC_E_INVALID; }
+  if (o->ls_max_trials < 0) { set_error("ls_max_trials must be >= 0"); return CBIC_E_INVALID; }
+  if (!(o->ls_beta > 0.0 && o->ls_beta < 1.0)) { set_error("ls_beta must be in (0,1)"); return CBIC_E_INVALID; }
+  if (o->stop_mode != 0 && o->stop_mode != 1) { set_error("stop_mode must be 0 or 1"); return CBIC_E_INVALID; }
+  if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) { set_error("rtol must be finite and >= 0"); return CBIC_E_INVALID; }
+  if (o->precision != CBIC_FP64 && o->precision != CBIC_MIXED) { set_error("precision must be 0 or 1"); return CBIC_E_INVALID; }
+  if (o->schedule < 0 || o->schedule > CBIC_SCHED_GROUP) { set_error("unknown schedule %d", o->schedule); return CBIC_E_INVALID; }
+  return CBIC_OK;
+}
+
+size_t sort_bytes(int B, int Tmax) {
+  return ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256 + (size_t(B) * 4 + 255) / 256 * 256;
+}
+
+cbic_status ensure_ws(cbic_context* ctx, size_t need) {
+  if (need <= ctx->ws_bytes) return CBIC_OK;
+  if (ctx->cap && need > ctx->cap) {
+    set_error("workspace of %zu bytes exceeds the context cap of %zu bytes", need, ctx->cap);
+    return CBIC_E_OOM;
+  }
+  if (ctx->ws) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&ctx->ws, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws = nullptr;
+    set_error("hipMalloc of %zu workspace bytes failed: %s", need, hipGetErrorString(e));
+    return CBIC_E_OOM;
+  }
+  ctx->ws_bytes = need;
+  // cached graphs refer to the old workspace
+  for (auto& kv : ctx->graphs) {
+    if (kv.second.ge) (void)hipGraphExecDestroy(kv.second.ge);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+  }
+  ctx->graphs.clear();
+  return CBIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cbic_last_error(void) { return last_error(); }
+
+int32_t cbic_version(void) { return 10000; }
+
+cbic_status cbic_opts_default(cbic_solve_opts* o) {
+  if (!o) { set_error("opts is NULL"); return CBIC_E_INVALID; }
+  std::memset(o, 0, sizeof *o);
+  o->struct_size = sizeof(cbic_solve_opts);
+  o->max_iter = 50;
+  o->psd_eps = 1e-6;
+  o->ls_max_trials = 16;
+  o->ls_beta = 0.5;
+  o->stop_mode = 0;
+  o->rtol = 1e-10;
+  o->lookahead_K = 0;
+  o->precision = CBIC_FP64;
+  o->schedule = 0;
+  o->iters_per_launch = 0;
+  o->flags = 0;
+  return CBIC_OK;
+}
+
+cbic_status cbic_context_create(int hip_device, size_t cap, cbic_context** out) {
+  if (!out) { set_error("out is NULL"); return CBIC_E_INVALID; }
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (hip_device < 0 || hip_device >= ndev) {
+    set_error("device %d out of range (%d devices)", hip_device, ndev);
+    return CBIC_E_INVALID;
+  }
+  HIP_TRY(hipSetDevice(hip_device));
+  cbic_context* c = new (std::nothrow) cbic_context();
+  if (!c) { set_error("out of host memory"); return CBIC_E_OOM; }
+  c->device = hip_device;
+  c->cap = cap;
+  hipError_t e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    delete c;
+    set_error("hipEventCreate failed: %s", hipGetErrorString(e));
+    return CBIC_E_HIP;
+  }
+  *out = c;
+  return CBIC_OK;
+}
+
+cbic_status cbic_context_destroy(cbic_context* ctx) {
+  if (!ctx) { set_error("ctx is NULL"); return CBIC_E_INVALID; }
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->graphs) {
+    if (kv.second.ge) (void)hipGraphExecDestroy(kv.second.ge);
+    if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+  }
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->done_ev) (void)hipEventDestroy(ctx->done_ev);
+  delete ctx;
+  return CBIC_OK;
+}
+
+cbic_status cbic_system_create(cbic_context* ctx, cbic_system_kind kind, const double* h_params, size_t np,
+                               cbic_system** out) {
+  if (!out) { set_error("out is NULL"); return CBIC_E_INVALID; }
+  *out = nullptr;
+  int n = 0, m = 0;
+  if (!validate_params(int(kind), h_params, np, &n, &m)) return CBIC_E_INVALID;
+  cbic_system* s = new (std::nothrow) cbic_system();
+  if (!s) { set_error("out of host memory"); return CBIC_E_OOM; }
+  s->kind = int(kind);
+  s->n = n;
+  s->m = m;
+  s->params.assign(h_params, h_params + np);
+  s->ctx = ctx;
+  if (!make_device_block(s, 1e-6)) {
+    delete s;
+    set_error("cannot build the device parameter block");
+    return CBIC_E_INVALID;
+  }
+  s->dev_eps = 1e-6;
+  if (ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess) e = hipMalloc(&s->d_prm, s->dev.size() * sizeof(double));
+    if (e == hipSuccess)
+      e = hipMemcpy(s->d_prm, s->dev.data(), s->dev.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (s->d_prm) (void)hipFree(s->d_prm);
+      delete s;
+      set_error("uploading system parameters failed: %s", hipGetErrorString(e));
+      return CBIC_E_HIP;
+    }
+  }
+  *out = s;
+  return CBIC_OK;
+}
+
+cbic_status cbic_system_dims(const cbic_system* s, int32_t* n, int32_t* m) {
+  if (!s || !n || !m) { set_error("NULL argument"); return CBIC_E_INVALID; }
+  *n = s->n;
+  *m = s->m;
+  return CBIC_OK;
+}
+
+cbic_status cbic_system_destroy(cbic_system* s) {
+  if (!s) { set_error("sys is NULL"); return CBIC_E_INVALID; }
+  if (s->d_prm) {
+    (void)hipSetDevice(s->ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(s->d_prm);
+  }
+  delete s;
+  return CBIC_OK;
+}
+
+cbic_status cbic_workspace_size(const cbic_system* s, int32_t B, int32_t Tmax, const cbic_solve_opts* opts,
+                                size_t* bytes) {
+  if (!s || !bytes) { set_error("NULL argument"); return CBIC_E_INVALID; }
+  if (B < 1 || Tmax < 1) { set_error("B and T_max must be >= 1"); return CBIC_E_INVALID; }
+  cbic_status st = check_opts(opts);
+  if (st) return st;
+  const Launcher* L = find_launcher(s->kind, s->n, s->m, opts->precision, opts->schedule);
+  if (!L) {
+    set_error("no kernel for system kind %d (n=%d, m=%d), precision %d, schedule %d", s->kind, s->n, s->m,
+              opts->precision, opts->schedule);
+    return CBIC_E_UNSUPPORTED;
+  }
+  *bytes = L->ws_bytes(B, Tmax) + sort_bytes(B, Tmax);
+  return CBIC_OK;
+}
+
+cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t Tmax,
+                             const int32_t* d_T, const double* d_x0, const double* d_U0,
+                             const cbic_solve_opts* opts, const cbic_outputs* out, void* stream_v) {
+  if (!ctx || !sys) { set_error("ctx and sys are required"); return CBIC_E_INVALID; }
+  if (sys->ctx != ctx || !sys->d_prm) { set_error("sys was not created on this context"); return CBIC_E_INVALID; }
+  if (B < 1 || Tmax < 1) { set_error("B and T_max must be >= 1 (got %d, %d)", B, Tmax); return CBIC_E_INVALID; }
+  if (!d_x0) { set_error("d_x0 is required"); return CBIC_E_INVALID; }
+  if (!out || !out->X || !out->U || !out->J || !out->iters || !out->status) {
+    set_error("outputs X, U, J, iters and status are required");
+    return CBIC_E_INVALID;
+  }
+  const void* ptrs[] = {d_T, d_x0, d_U0, out->X, out->U, out->J, out->iters, out->status,
+                        out->Vbar, out->Vx, out->xK, out->cost_trace, out->work};
+  for (const void* p : ptrs)
+    if (p && !aligned8(p) && p != d_T && p != out->iters && p != out->status && p != out->work) {
+      set_error("device pointers must be 8-byte aligned");
+      return CBIC_E_INVALID;
+    }
+  if ((d_T && (reinterpret_cast<uintptr_t>(d_T) & 3u)) || (reinterpret_cast<uintptr_t>(out->iters) & 3u) ||
+      (reinterpret_cast<uintptr_t>(out->status) & 3u) || (out->work && (reinterpret_cast<uintptr_t>(out->work) & 3u))) {
+    set_error("int32 device pointers must be 4-byte aligned");
+    return CBIC_E_INVALID;
+  }
+  cbic_status st = check_opts(opts);
+  if (st) return st;
+  const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, opts->schedule);
+  if (!L) {
+    set_error("no kernel for system kind %d (n=%d, m=%d), precision %d, schedule %d", sys->kind, sys->n,
+              sys->m, opts->precision, opts->schedule);
+    return CBIC_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t stream = static_cast<hipStream_t>(stream_v);
+  HIP_TRY(hipSetDevice(ctx->device));
+  cbic_system* ms = const_cast<cbic_system*>(sys);
+  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != opts->psd_eps) {
+    // the LQ Hessians are constant; their clip is refreshed for a new eps
+    HIP_TRY(hipDeviceSynchronize());
+    make_device_block(ms, opts->psd_eps);
+    HIP_TRY(hipMemcpy(ms->d_prm, ms->dev.data(), ms->dev.size() * sizeof(double), hipMemcpyHostToDevice));
+    ms->dev_eps = opts->psd_eps;
+  }
+  const size_t ws_main = L->ws_bytes(B, Tmax);
+  st = ensure_ws(ctx, ws_main + sort_bytes(B, Tmax));
+  if (st) return st;
+  if (ctx->have_last && ctx->last_stream != stream) HIP_TRY(hipStreamWaitEvent(stream, ctx->done_ev, 0));
+
+  char* base = static_cast<char*>(ctx->ws);
+  int32_t* hist = reinterpret_cast<int32_t*>(base + ws_main);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + ws_main + ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256);
+  if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
+  else perm = nullptr;
+
+  HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
+                  out->cost_trace, stream));
+  SolveParamsH sp{opts->max_iter, opts->ls_max_trials, opts->stop_mode, opts->lookahead_K,
+                  opts->psd_eps, opts->ls_beta, opts->rtol};
+  if (opts->max_iter > 0) {
+    const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
+    const int chunks = (opts->max_iter + G - 1) / G;
+    const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
+    if (!graph) {
+      for (int c = 0; c < chunks; ++c)
+        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, out->cost_trace, stream));
+    } else {
+      char key[256];
+      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p", (const void*)L,
+                    (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, sp.max_iter, sp.ls_trials,
+                    sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace);
+      auto it = ctx->graphs.find(key);
+      if (it == ctx->graphs.end()) {
+        cbic_context::GraphEntry ge;
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < chunks && e == hipSuccess; ++c)
+          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, out->cost_trace, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+          return CBIC_E_HIP;
+        }
+        ge.g = g;
+        HIP_TRY(hipGraphInstantiate(&ge.ge, g, nullptr, nullptr, 0));
+        it = ctx->graphs.emplace(key, ge).first;
+      }
+      HIP_TRY(hipGraphLaunch(it->second.ge, stream));
+    }
+  }
+  FinalOutH fo{out->X, out->U, out->J, out->iters, out->status, out->Vbar, out->Vx, out->xK, out->cost_trace,
+               out->work};
+  HIP_TRY(L->finalize(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
+  HIP_TRY(hipEventRecord(ctx->done_ev, stream));
+  ctx->last_stream = stream;
+  ctx->have_last = true;
+  return CBIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// Device-side helpers shared by the solver kernels: precision traits, small
+// fixed-size linear algebra (Cholesky of Q_uu, triangular solves) and the
+// eigenvalue clip of paper Sec. IV-B eq. 7 for 2x2 and 3x3 symmetric blocks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+// Model and small linear-algebra helpers are pure arithmetic: they compile for
+// the device and, for host-side tests of the same code, for the host.
+#define CBIC_HD __host__ __device__
+
+namespace cbic {
+
+enum : uint32_t {
+  ST_CONVERGED = 1u,
+  ST_MAX_ITER = 2u,
+  ST_LS_FAILED = 4u,
+  ST_NONFINITE = 8u,
+  ST_CHOL_FAIL = 16u,
+  ST_BAD_INPUT = 32u,
+};
+
+// ---------------------------------------------------------------- math by precision
+CBIC_HD __forceinline__ double dexp(double v) { return exp(v); }
+CBIC_HD __forceinline__ float dexp(float v) { return expf(v); }
+CBIC_HD __forceinline__ double dsin(double v) { return sin(v); }
+CBIC_HD __forceinline__ float dsin(float v) { return sinf(v); }
+CBIC_HD __forceinline__ double dcos(double v) { return cos(v); }
+CBIC_HD __forceinline__ float dcos(float v) { return cosf(v); }
+CBIC_HD __forceinline__ void dsincos(double v, double* s, double* c) { sincos(v, s, c); }
+CBIC_HD __forceinline__ void dsincos(float v, float* s, float* c) { sincosf(v, s, c); }
+CBIC_HD __forceinline__ double dsqrt(double v) { return sqrt(v); }
+CBIC_HD __forceinline__ float dsqrt(float v) { return sqrtf(v); }
+CBIC_HD __forceinline__ bool dfinite(double v) { return isfinite(v); }
+CBIC_HD __forceinline__ bool dfinite(float v) { return isfinite(v); }
+
+template <class R>
+CBIC_HD __forceinline__ R dmax(R a, R b) { return a > b ? a : b; }
+
+// Squared relative off-diagonal size at which Jacobi rotations stop.
+template <class R> struct JacobiTol;
+template <> struct JacobiTol<double> { static constexpr double v = 1e-32; };
+template <> struct JacobiTol<float> { static constexpr float v = 4e-15f; };
+
+// ---------------------------------------------------------------- eigenvalue clip
+// Clip of a symmetric 2x2 [[a,b],[b,c]]: eigenvalues below eps are raised to
+// eps and the matrix is rebuilt.  Written as H + sum_{mu_i<eps} (eps-mu_i) v_i v_i^T,
+// which leaves H bit-for-bit unchanged when no eigenvalue is clipped.
+template <class R>
+CBIC_HD __forceinline__ void clip_sym2(R& a, R& b, R& c, R eps) {
+  if (b == R(0)) {
+    a = dmax(a, eps);
+    c = dmax(c, eps);
+    return;
+  }
+  const R half_tr = R(0.5) * (a + c);
+  const R dh = R(0.5) * (a - c);
+  const R rad = dsqrt(dh * dh + b * b);
+  const R mu_lo = half_tr - rad, mu_hi = half_tr + rad;
+  if (mu_lo >= eps) return;
+  if (mu_hi < eps) {
+    a = eps;
+    b = R(0);
+    c = eps;
+    return;
+  }
+  // unit eigenvector of mu_lo, from the better-conditioned of two candidates
+  R v0 = b, v1 = mu_lo - a;
+  R w0 = mu_lo - c, w1 = b;
+  if (v0 * v0 + v1 * v1 < w0 * w0 + w1 * w1) {
+    v0 = w0;
+    v1 = w1;
+  }
+  const R inv = R(1) / (v0 * v0 + v1 * v1);
+  const R d = (eps - mu_lo) * inv;
+  a += d * v0 * v0;
+  b += d * v0 * v1;
+  c += d * v1 * v1;
+}
+
+// Clip of a symmetric 3x3 (row-major h[9]).  Fast path: if H - eps I is
+// positive definite (Cholesky succeeds) no eigenvalue is below eps and H is
+// returned unchanged.  Otherwise cyclic Jacobi rotations give H = W S W^T and
+// the clipped spectrum is recombined.
+template <class R>
+CBIC_HD __forceinline__ void clip_sym3(R h[9], R eps) {
+  {
+    const R a00 = h[0] - eps, a11 = h[4] - eps, a22 = h[8] - eps;
+    bool pd = a00 > R(0);
+    if (pd) {
+      const R l10 = h[3] / a00, l20 = h[6] / a00;
+      const R d1 = a11 - l10 * h[3];
+      pd = d1 > R(0);
+      if (pd) {
+        const R l21 = (h[7] - l20 * h[3]) / d1;
+        const R d2 = a22 - l20 * h[6] - l21 * (h[7] - l20 * h[3]);
+        pd = d2 > R(0);
+      }
+    }
+    if (pd) return;
+  }
+  R a[3][3] = {{h[0], R(0.5) * (h[1] + h[3]), R(0.5) * (h[2] + h[6])},
+               {R(0), h[4], R(0.5) * (h[5] + h[7])},
+               {R(0), R(0), h[8]}};
+  a[1][0] = a[0][1];
+  a[2][0] = a[0][2];
+  a[2][1] = a[1][2];
+  R w[3][3] = {{R(1), R(0), R(0)}, {R(0), R(1), R(0)}, {R(0), R(0), R(1)}};
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const R off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const R dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > JacobiTol<R>::v * dia)) break;
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      const int p = pr == 2 ? 1 : 0;
+      const int q = pr == 0 ? 1 : 2;
+      const R apq = a[p][q];
+      if (apq == R(0)) continue;
+      const R tau = (a[q][q] - a[p][p]) / (R(2) * apq);
+      const R t = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + dsqrt(R(1) + tau * tau));
+      const R cs = R(1) / dsqrt(R(1) + t * t), sn = t * cs;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const R akp = a[k][p], akq = a[k][q];
+        a[k][p] = cs * akp - sn * akq;
+        a[k][q] = sn * akp + cs * akq;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const R apk = a[p][k], aqk = a[q][k];
+        a[p][k] = cs * apk - sn * aqk;
+        a[q][k] = sn * apk + cs * aqk;
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const R wkp = w[k][p], wkq = w[k][q];
+        w[k][p] = cs * wkp - sn * wkq;
+        w[k][q] = sn * wkp + cs * wkq;
+      }
+    }
+  }
+  const R s0 = dmax(a[0][0], eps), s1 = dmax(a[1][1], eps), s2 = dmax(a[2][2], eps);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const R v = w[i][0] * s0 * w[j][0] + w[i][1] * s1 * w[j][1] + w[i][2] * s2 * w[j][2];
+      h[i * 3 + j] = v;
+      h[j * 3 + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------- Cholesky (FP64)
+// In-place lower Cholesky of the M x M symmetric matrix held in the upper
+// triangle of a (a[i][j], j >= i).  Returns false on a non-positive or
+// non-finite pivot.  L is returned in l[i][j], j <= i; diag holds 1/L_ii.
+template <int M>
+CBIC_HD __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], double inv_diag[M]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    double d = a[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= l[j][k] * l[j][k];
+    ok = ok && (d > 0.0) && isfinite(d);
+    const double ljj = sqrt(d);
+    const double inv = 1.0 / ljj;
+    l[j][j] = ljj;
+    inv_diag[j] = inv;
+#pragma unroll
+    for (int i = j + 1; i < M; ++i) {
+      double v = a[j][i];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= l[i][k] * l[j][k];
+      l[i][j] = v * inv;
+    }
+  }
+  return ok;
+}
+
+// Solve (L L^T) y = b in place.
+template <int M>
+CBIC_HD __forceinline__ void chol_solve_fp64(const double l[M][M], const double inv_diag[M], double b[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= l[i][k] * b[k];
+    b[i] = v * inv_diag[i];
+  }
+#pragma unroll
+  for (int i = M - 1; i >= 0; --i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = i + 1; k < M; ++k) v -= l[k][i] * b[k];
+    b[i] = v * inv_diag[i];
+  }
+}
+
+}  // namespace cbic

@@ -1,0 +1,579 @@
+// Lane-per-instance batched iLQR (paper Sec. II and IV): every lane of a
+// 64-wide wavefront owns one TO instance and runs its whole solve with the
+// small per-instance matrices (P, A, B, gains) in registers.  Trajectories and
+// gains live in HBM in a step-major layout [k][slot][component], so that for
+// a fixed step the 64 lanes of a wave touch one contiguous span: every load
+// and store of the sweeps is coalesced across the batch.
+//
+// Three kernels share per-slot state in a workspace:
+//   lane_init     warm start (U0 or zeros) and the initial rollout, J^0;
+//   lane_iterate  up to G iLQR iterations (backward Riccati sweep with the
+//                 eigenvalue-clipped Hessians of eq. 7 and a Cholesky of Q_uu,
+//                 then the backtracking line search); resumable, so the same
+//                 kernel serves one fused launch or a chain of G-iteration
+//                 launches (graph-captured loops, serving);
+//   lane_final    status, the critic targets of Sec. II (K-step cost-to-go,
+//                 costate V_x, state after K steps) and the caller's AoS outputs.
+//
+// Precision R: double for the plain form; float for the mixed form, where the
+// rollouts, derivatives and Riccati products run in FP32 while the Q_uu
+// Cholesky, the gain solves, the cost sums and the line-search comparison stay
+// in FP64.
+#pragma once
+#include "dev_common.hpp"
+
+namespace cbic {
+
+template <class R>
+struct LaneState {
+  // per-slot state, all [Bcap]
+  int32_t* T;        // horizon
+  int32_t* inst;     // caller's instance index of this slot
+  double* J;         // current total cost
+  int32_t* iters;    // accepted iterations
+  uint32_t* status;  // status bits; nonzero = frozen
+  int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
+  int32_t* work;     // [Bcap][2]: backward sweeps, line-search trials
+  // trajectories and gains, step-major
+  R* X;   // [2][Tcap+1][Bcap][N]
+  R* U;   // [2][Tcap][Bcap][M]
+  R* K;   // [Tcap][Bcap][M][N]
+  R* kf;  // [Tcap][Bcap][M]
+  int Bcap, Tcap;
+};
+
+struct SolveParams {
+  int32_t max_iter;
+  int32_t ls_trials;
+  int32_t stop_mode;
+  int32_t lookahead;
+  double eps;
+  double beta;
+  double rtol;
+};
+
+template <class Sys, class R>
+struct Lane {
+  static constexpr int N = Sys::N, M = Sys::M;
+  using Model = typename Sys::template Model<R>;
+
+  __device__ static __forceinline__ R* xp(const LaneState<R>& w, int buf, int k, int s) {
+    return w.X + ((size_t(buf) * (w.Tcap + 1) + k) * w.Bcap + s) * N;
+  }
+  __device__ static __forceinline__ R* up(const LaneState<R>& w, int buf, int k, int s) {
+    return w.U + ((size_t(buf) * w.Tcap + k) * w.Bcap + s) * M;
+  }
+  __device__ static __forceinline__ R* Kp(const LaneState<R>& w, int k, int s) {
+    return w.K + (size_t(k) * w.Bcap + s) * (M * N);
+  }
+  __device__ static __forceinline__ R* kp(const LaneState<R>& w, int k, int s) {
+    return w.kf + (size_t(k) * w.Bcap + s) * M;
+  }
+
+  template <int L>
+  __device__ static __forceinline__ void ld(R (&dst)[L], const R* src) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) dst[i] = src[i];
+  }
+  template <int L>
+  __device__ static __forceinline__ void st(R* dst, const R (&src)[L]) {
+#pragma unroll
+    for (int i = 0; i < L; ++i) dst[i] = src[i];
+  }
+
+  // ------------------------------------------------------------------ backward
+  // One Riccati sweep over the iterate in buffer `buf`.  Writes K_k, k_k.
+  // Returns 0 or the status bit that freezes the instance.
+  __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf,
+                                      R eps) {
+    R P[N][N], p[N];
+    {
+      R xT[N];
+      ld(xT, xp(w, buf, T, s));
+      mdl.term_derivs(xT, p, P, eps, true);
+    }
+    uint32_t bad = 0;
+    // software prefetch of the next step's (x, u)
+    R xn[N], un[M];
+    ld(xn, xp(w, buf, T - 1, s));
+    ld(un, up(w, buf, T - 1, s));
+    for (int k = T - 1; k >= 0; --k) {
+      R x[N], u[M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = xn[i];
+#pragma unroll
+      for (int i = 0; i < M; ++i) u[i] = un[i];
+      if (k > 0) {
+        ld(xn, xp(w, buf, k - 1, s));
+        ld(un, up(w, buf, k - 1, s));
+      }
+      R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
+      mdl.jac(x, u, A, B);
+      mdl.cost_derivs(x, u, lx, lu, Qc, Rc, eps, true);
+
+      // PA = P A, PB = P B  (structural zeros of A, B skipped at compile time)
+      R PA[N][N], PB[N][M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          R v = R(0);
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::a_nz(t, j)) v += P[i][t] * A[t][j];
+          PA[i][j] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          R v = R(0);
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::b_nz(t, j)) v += P[i][t] * B[t][j];
+          PB[i][j] = v;
+        }
+      }
+      R Qx[N], Qu[M], Qxx[N][N], Qux[M][N];
+      double Quu[M][M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R v = lx[i];
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::a_nz(t, i)) v += A[t][i] * p[t];
+        Qx[i] = v;
+#pragma unroll
+        for (int j = i; j < N; ++j) {
+          R q = Qc[i][j];
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::a_nz(t, i)) q += A[t][i] * PA[t][j];
+          Qxx[i][j] = q;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        R v = lu[i];
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::b_nz(t, i)) v += B[t][i] * p[t];
+        Qu[i] = v;
+#pragma unroll
+        for (int j = i; j < M; ++j) {
+          R q = Rc[i][j];
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::b_nz(t, i)) q += B[t][i] * PB[t][j];
+          Quu[i][j] = double(q);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          R q = R(0);
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::b_nz(t, i)) q += B[t][i] * PA[t][j];
+          Qux[i][j] = q;
+        }
+      }
+      // Cholesky of Q_uu and the gains, in FP64
+      double Lc[M][M], invd[M];
+      const bool ok = chol_fp64<M>(Quu, Lc, invd);
+      if (!ok) {
+        bad = ST_CHOL_FAIL;
+        break;
+      }
+      R Kk[M][N], kk[M];
+      bool fin = true;
+      {
+        double col[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
+        chol_solve_fp64<M>(Lc, invd, col);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          kk[i] = R(-col[i]);
+          fin = fin && isfinite(col[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+#pragma unroll
+          for (int i = 0; i < M; ++i) col[i] = double(Qux[i][j]);
+          chol_solve_fp64<M>(Lc, invd, col);
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            Kk[i][j] = R(-col[i]);
+            fin = fin && isfinite(col[i]);
+          }
+        }
+      }
+      if (!fin) {
+        bad = ST_NONFINITE;
+        break;
+      }
+      {
+        R* dK = Kp(w, k, s);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+          for (int j = 0; j < N; ++j) dK[i * N + j] = Kk[i][j];
+        st(kp(w, k, s), kk);
+      }
+      // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R v = Qx[i];
+#pragma unroll
+        for (int t = 0; t < M; ++t) v += Qux[t][i] * kk[t];
+        p[i] = v;
+#pragma unroll
+        for (int j = i; j < N; ++j) {
+          R q = Qxx[i][j];
+#pragma unroll
+          for (int t = 0; t < M; ++t) q += Qux[t][i] * Kk[t][j];
+          P[i][j] = q;
+          P[j][i] = q;
+        }
+      }
+    }
+    return bad;
+  }
+
+  // ------------------------------------------------------------------ line search trial
+  // Closed-loop rollout with step alpha from the iterate in `buf` into the
+  // other buffer; returns J_hat in FP64 (NaN-propagating).  With non-negative
+  // costs a trial stops as soon as its partial sum reaches J: its total could
+  // only be larger, so the accept/reject decision is unchanged.
+  __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R alpha,
+                                 double Jcur) {
+    const int nb = buf ^ 1;
+    R xh[N];
+    ld(xh, xp(w, buf, 0, s));
+    double Jh = 0.0;
+    R xa[N], ua[M], Ka[M * N], ka[M];
+    ld(xa, xp(w, buf, 0, s));
+    ld(ua, up(w, buf, 0, s));
+    ld(Ka, Kp(w, 0, s));
+    ld(ka, kp(w, 0, s));
+    bool cut = false;
+    for (int k = 0; k < T; ++k) {
+      R x[N], u[M], Kk[M * N], kk[M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = xa[i];
+#pragma unroll
+      for (int i = 0; i < M; ++i) u[i] = ua[i];
+#pragma unroll
+      for (int i = 0; i < M * N; ++i) Kk[i] = Ka[i];
+#pragma unroll
+      for (int i = 0; i < M; ++i) kk[i] = ka[i];
+      if (k + 1 < T) {
+        ld(xa, xp(w, buf, k + 1, s));
+        ld(ua, up(w, buf, k + 1, s));
+        ld(Ka, Kp(w, k + 1, s));
+        ld(ka, kp(w, k + 1, s));
+      }
+      R dx[N], uh[M];
+#pragma unroll
+      for (int i = 0; i < N; ++i) dx[i] = xh[i] - x[i];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        R v = u[i] + alpha * kk[i];
+#pragma unroll
+        for (int j = 0; j < N; ++j) v += Kk[i * N + j] * dx[j];
+        uh[i] = v;
+      }
+      Jh += double(mdl.cost(xh, uh));
+      st(up(w, nb, k, s), uh);
+      R xn[N];
+      mdl.dyn(xh, uh, xn);
+#pragma unroll
+      for (int i = 0; i < N; ++i) xh[i] = xn[i];
+      st(xp(w, nb, k + 1, s), xh);
+      if (Sys::kNonNegCost && !(Jh < Jcur)) {
+        cut = true;
+        break;
+      }
+    }
+    if (cut) return Jh;
+    Jh += double(mdl.term(xh));
+    return Jh;
+  }
+};
+
+// ====================================================================== kernels
+template <class Sys, class R>
+__global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, LaneState<R> w, int nthreads,
+                                                const int32_t* __restrict__ slots, int Tmax,
+                                                const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
+                                                const double* __restrict__ x0, const double* __restrict__ U0,
+                                                int max_iter, double* __restrict__ trace) {
+  // thread t initialises slot slots[t] (or t) from caller instance perm[t] (or t).
+  using LN = Lane<Sys, R>;
+  constexpr int N = Sys::N, M = Sys::M;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nthreads) return;
+  const int s = slots ? slots[tid] : tid;
+  const typename LN::Model mdl{prm};
+  const int b = perm ? perm[tid] : tid;
+  const int Tr = Tin ? Tin[b] : Tmax;
+  const bool badT = Tr < 1 || Tr > Tmax || Tr > w.Tcap;
+  const int T = badT ? 0 : Tr;  // an out-of-range horizon is never used as an index
+  R x[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = R(x0[size_t(b) * N + i]);
+  LN::st(LN::xp(w, 0, 0, s), x);
+  LN::st(LN::xp(w, 1, 0, s), x);
+  double J = 0.0;
+  for (int k = 0; k < T; ++k) {
+    R u[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) u[i] = U0 ? R(U0[(size_t(b) * Tmax + k) * M + i]) : R(0);
+    LN::st(LN::up(w, 0, k, s), u);
+    J += double(mdl.cost(x, u));
+    R xn[N];
+    mdl.dyn(x, u, xn);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = xn[i];
+    LN::st(LN::xp(w, 0, k + 1, s), x);
+  }
+  J += double(mdl.term(x));
+  uint32_t st = isfinite(J) ? 0u : ST_NONFINITE;
+  if (badT) {
+    st = ST_BAD_INPUT;
+    J = __builtin_nan("");
+  }
+  if (st == 0 && max_iter <= 0) st = ST_MAX_ITER;
+  w.T[s] = T;
+  w.inst[s] = slots ? s : b;  // outputs of slot-addressed solves are indexed by slot
+  w.J[s] = J;
+  w.iters[s] = 0;
+  w.status[s] = st;
+  w.cur[s] = 0;
+  w.work[2 * s] = 0;
+  w.work[2 * s + 1] = 0;
+  if (trace) trace[size_t(slots ? s : b) * (max_iter + 1)] = J;
+}
+
+// G iterations for every active slot.  `slots` (optional) maps the thread
+// index to a slot, for the serving path's sparse slot sets.
+template <class Sys, class R>
+__global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
+                                                   int nslots, const int32_t* __restrict__ slots,
+                                                   SolveParams sp, int G, double* __restrict__ trace) {
+  using LN = Lane<Sys, R>;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nslots) return;
+  const int s = slots ? slots[tid] : tid;
+  uint32_t st = w.status[s];
+  if (st) return;
+  const typename LN::Model mdl{prm};
+  const int T = w.T[s];
+  const int b = w.inst[s];
+  double J = w.J[s];
+  int iters = w.iters[s];
+  int buf = w.cur[s];
+  int nsweep = w.work[2 * s], ntrial = w.work[2 * s + 1];
+  const R eps = R(sp.eps);
+  for (int g = 0; g < G && st == 0; ++g) {
+    if (iters >= sp.max_iter) {
+      st = ST_MAX_ITER;
+      break;
+    }
+    ++nsweep;
+    const uint32_t bad = LN::backward(mdl, w, s, T, buf, eps);
+    if (bad) {
+      st = bad;
+      break;
+    }
+    double alpha = 1.0;
+    int acc = -1;
+    double Jn = J;
+    for (int j = 0; j < sp.ls_trials; ++j) {
+      ++ntrial;
+      const double Jh = LN::trial(mdl, w, s, T, buf, R(alpha), J);
+      if (isfinite(Jh) && Jh < J) {
+        acc = j;
+        Jn = Jh;
+        break;
+      }
+      alpha *= sp.beta;
+    }
+    if (acc < 0) {
+      st = ST_LS_FAILED;
+      break;
+    }
+    buf ^= 1;
+    const double Jold = J;
+    J = Jn;
+    ++iters;
+    if (trace) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
+    if (sp.stop_mode == 1 && (Jold - J) <= sp.rtol * fabs(Jold)) {
+      st = ST_CONVERGED;
+      break;
+    }
+    if (iters >= sp.max_iter) st = ST_MAX_ITER;
+  }
+  w.J[s] = J;
+  w.iters[s] = iters;
+  w.status[s] = st;
+  w.cur[s] = buf;
+  w.work[2 * s] = nsweep;
+  w.work[2 * s + 1] = ntrial;
+}
+
+struct FinalOut {
+  double* X;      // [B][Tmax+1][N]
+  double* U;      // [B][Tmax][M]
+  double* J;      // [B]
+  int32_t* iters;
+  uint32_t* status;
+  double* Vbar;   // [B][Tmax+1] or null
+  double* Vx;     // [B][Tmax+1][N] or null
+  double* xK;     // [B][Tmax+1][N] or null
+  double* trace;  // [B][max_iter+1] or null
+  int32_t* work;  // [B][2] or null
+};
+
+template <class Sys, class R>
+__global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
+                                                 const int32_t* __restrict__ slots, int Tmax, int max_iter,
+                                                 int lookahead, FinalOut o) {
+  using LN = Lane<Sys, R>;
+  constexpr int N = Sys::N, M = Sys::M;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= nslots) return;
+  const int s = slots ? slots[tid] : tid;
+  const typename LN::Model mdl{prm};
+  const int b = w.inst[s];
+  const int buf = w.cur[s];
+  uint32_t st = w.status[s];
+  if (st == 0) st = ST_MAX_ITER;  // iteration budget ended without freezing
+  // an instance with an invalid horizon gets all-zero trajectory outputs
+  const int T = (st & ST_BAD_INPUT) ? -1 : w.T[s];
+  const double J = w.J[s];
+  const int iters = w.iters[s];
+  o.J[b] = J;
+  o.iters[b] = iters;
+  o.status[b] = st;
+  if (o.work) {
+    o.work[2 * b] = w.work[2 * s];
+    o.work[2 * b + 1] = w.work[2 * s + 1];
+  }
+  if (o.trace)
+    for (int i = iters + 1; i <= max_iter; ++i) o.trace[size_t(b) * (max_iter + 1) + i] = J;
+  double* Xo = o.X + size_t(b) * (Tmax + 1) * N;
+  double* Uo = o.U + size_t(b) * Tmax * M;
+  for (int k = 0; k <= Tmax; ++k) {
+    if (k <= T) {
+      const R* xs = LN::xp(w, buf, k, s);
+#pragma unroll
+      for (int i = 0; i < N; ++i) Xo[k * N + i] = double(xs[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) Xo[k * N + i] = 0.0;
+    }
+    if (k < Tmax) {
+      if (k < T) {
+        const R* us = LN::up(w, buf, k, s);
+#pragma unroll
+        for (int i = 0; i < M; ++i) Uo[k * M + i] = double(us[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i) Uo[k * M + i] = 0.0;
+      }
+    }
+  }
+  const int K = lookahead <= 0 ? T : lookahead;
+  if (o.xK) {
+    double* xo = o.xK + size_t(b) * (Tmax + 1) * N;
+    for (int k = 0; k <= Tmax; ++k) {
+      if (k <= T) {
+        const int t = k + K < T ? k + K : T;
+        const R* xs = LN::xp(w, buf, t, s);
+#pragma unroll
+        for (int i = 0; i < N; ++i) xo[k * N + i] = double(xs[i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) xo[k * N + i] = 0.0;
+      }
+    }
+  }
+  if (T < 0) {
+    if (o.Vbar)
+      for (int k = 0; k <= Tmax; ++k) o.Vbar[size_t(b) * (Tmax + 1) + k] = 0.0;
+    if (o.Vx)
+      for (int k = 0; k <= Tmax; ++k)
+#pragma unroll
+        for (int i = 0; i < N; ++i) o.Vx[(size_t(b) * (Tmax + 1) + k) * N + i] = 0.0;
+    return;
+  }
+  if (!o.Vbar && !o.Vx) return;
+  // backward pass over the final trajectory: stage costs and costate
+  // lambda_T = d l_T/dx, lambda_k = l_x + A_k^T lambda_{k+1}  (unclipped first derivatives)
+  double* Vo = o.Vbar ? o.Vbar + size_t(b) * (Tmax + 1) : nullptr;
+  double* Lo = o.Vx ? o.Vx + size_t(b) * (Tmax + 1) * N : nullptr;
+  R lam[N];
+  R xT[N];
+  LN::ld(xT, LN::xp(w, buf, T, s));
+  {
+    R Qd[N][N];
+    mdl.term_derivs(xT, lam, Qd, R(0), false);
+  }
+  const double cT = double(mdl.term(xT));
+  if (Vo) Vo[T] = cT;
+  if (Lo) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) Lo[size_t(T) * N + i] = double(lam[i]);
+  }
+  for (int k = T - 1; k >= 0; --k) {
+    R x[N], u[M];
+    LN::ld(x, LN::xp(w, buf, k, s));
+    LN::ld(u, LN::up(w, buf, k, s));
+    if (Vo) {
+      Vo[k] = double(mdl.cost(x, u));  // stage cost, turned into window sums below
+    }
+    if (Lo) {
+      R A[N][N], B[N][M], lx[N], lu[M], Qd[N][N], Rd[M][M];
+      mdl.jac(x, u, A, B);
+      mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
+      R ln[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R v = lx[i];
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::a_nz(t, i)) v += A[t][i] * lam[t];
+        ln[i] = v;
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        lam[i] = ln[i];
+        Lo[size_t(k) * N + i] = double(ln[i]);
+      }
+    }
+  }
+  if (Vo) {
+    if (K >= T) {
+      // full cost-to-go: suffix sums
+      double acc = cT;
+      for (int k = T - 1; k >= 0; --k) {
+        acc = Vo[k] + acc;
+        Vo[k] = acc;
+      }
+    } else {
+      // K-step window: V_k = sum_{j=k}^{min(k+K,T)-1} c_j + [k+K >= T] c_T, in index order
+      for (int k = 0; k < T; ++k) {
+        const int end = k + K < T ? k + K : T;
+        double v = 0.0;
+        for (int j = k; j < end; ++j) v += Vo[j];
+        if (k + K >= T) v += cT;
+        Vo[k] = v;  // reads only indices >= k, which still hold stage costs
+      }
+    }
+    for (int k = T + 1; k <= Tmax; ++k) Vo[k] = 0.0;
+  }
+  if (Lo)
+    for (int k = T + 1; k <= Tmax; ++k)
+#pragma unroll
+      for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = 0.0;
+}
+
+}  // namespace cbic

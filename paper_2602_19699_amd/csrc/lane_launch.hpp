@@ -1,0 +1,84 @@
+// Host launchers for the lane-per-instance kernels of one (system, precision).
+#pragma once
+#include "ilqr_lane.hpp"
+#include "runtime.hpp"
+
+namespace cbic {
+
+template <class R>
+inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap) {
+  const LaneLayout L = lane_layout(N, M, int(sizeof(R)), Bcap, Tcap);
+  char* b = static_cast<char*>(base);
+  LaneState<R> w;
+  w.T = reinterpret_cast<int32_t*>(b + L.T);
+  w.inst = reinterpret_cast<int32_t*>(b + L.inst);
+  w.J = reinterpret_cast<double*>(b + L.J);
+  w.iters = reinterpret_cast<int32_t*>(b + L.iters);
+  w.status = reinterpret_cast<uint32_t*>(b + L.status);
+  w.cur = reinterpret_cast<int32_t*>(b + L.cur);
+  w.work = reinterpret_cast<int32_t*>(b + L.work);
+  w.X = reinterpret_cast<R*>(b + L.X);
+  w.U = reinterpret_cast<R*>(b + L.U);
+  w.K = reinterpret_cast<R*>(b + L.K);
+  w.kf = reinterpret_cast<R*>(b + L.kf);
+  w.Bcap = Bcap;
+  w.Tcap = Tcap;
+  return w;
+}
+
+inline SolveParams to_dev(const SolveParamsH& h) {
+  SolveParams s;
+  s.max_iter = h.max_iter;
+  s.ls_trials = h.ls_trials;
+  s.stop_mode = h.stop_mode;
+  s.lookahead = h.lookahead;
+  s.eps = h.eps;
+  s.beta = h.beta;
+  s.rtol = h.rtol;
+  return s;
+}
+
+template <class Sys, class R>
+struct LaneLaunch {
+  static constexpr int N = Sys::N, M = Sys::M;
+  static constexpr int WG = 64;
+
+  static size_t ws_bytes(int Bcap, int Tcap) { return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total; }
+
+  static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
+                         int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
+                         int max_iter, double* trace, hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    hipLaunchKernelGGL((lane_init<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
+                       slots, Tmax, Tin, perm, x0, U0, max_iter, trace);
+    return hipGetLastError();
+  }
+
+  static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                            const int32_t* slots, const SolveParamsH& sp, int G, double* trace, hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    hipLaunchKernelGGL((lane_iterate<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w,
+                       nthreads, slots, to_dev(sp), G, trace);
+    return hipGetLastError();
+  }
+
+  static hipError_t finalize(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                             const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
+                             hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
+    hipLaunchKernelGGL((lane_final<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
+                       slots, Tmax, max_iter, lookahead, fo);
+    return hipGetLastError();
+  }
+
+  static const Launcher* get() {
+    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_LANE, &ws_bytes, &init, &iterate, &finalize};
+    return &L;
+  }
+};
+
+}  // namespace cbic

@@ -1,0 +1,100 @@
+// Host-side runtime of the solver library: contexts, systems, workspace
+// layout and the table of kernel launchers per (system, precision).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cbic.h"
+
+namespace cbic {
+
+void set_error(const char* fmt, ...);
+
+struct SolveParams;  // ilqr_lane.hpp
+
+// Byte offsets of the per-slot state, trajectories and gains inside one
+// workspace allocation (lane schedule).  All sub-arrays are 256-byte aligned.
+struct LaneLayout {
+  size_t T, inst, J, iters, status, cur, work;
+  size_t X, U, K, kf;
+  size_t total;
+};
+LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap);
+
+// Group schedule (one workgroup per instance) for large systems.
+struct GroupLayout {
+  size_t T, inst, J, iters, status, cur, work;
+  size_t X, U, K, kf;
+  size_t total;
+};
+GroupLayout group_layout(int N, int M, int elem, int Bcap, int Tcap);
+
+struct SolveParamsH {
+  int32_t max_iter, ls_trials, stop_mode, lookahead;
+  double eps, beta, rtol;
+};
+
+struct FinalOutH {
+  double *X, *U, *J;
+  int32_t* iters;
+  uint32_t* status;
+  double *Vbar, *Vx, *xK, *trace;
+  int32_t* work;
+};
+
+// Launchers for one (system, precision).  `base` is the workspace; `slots`
+// (optional) lists the slots to work on; `perm` (optional) maps a thread to
+// the caller's instance index when initialising from caller arrays.
+struct Launcher {
+  int N, M, elem;
+  int schedule;  // CBIC_SCHED_*
+  size_t (*ws_bytes)(int Bcap, int Tcap);
+  hipError_t (*init)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
+                     int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
+                     int max_iter, double* trace, hipStream_t st);
+  hipError_t (*iterate)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
+                        const SolveParamsH& sp, int G, double* trace, hipStream_t st);
+  hipError_t (*finalize)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                         const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
+                         hipStream_t st);
+};
+
+const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);
+
+// horizon sort (longest first) of B instances -> perm (device)
+hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st);
+
+}  // namespace cbic
+
+struct cbic_context {
+  int device = 0;
+  size_t cap = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t last_stream = nullptr;
+  bool have_last = false;
+  hipEvent_t done_ev = nullptr;
+  std::mutex mu;
+  // graph cache for the iteration chain
+  struct GraphEntry {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+  };
+  std::map<std::string, GraphEntry> graphs;
+};
+
+struct cbic_system {
+  int kind = -1;
+  int n = 0, m = 0;
+  std::vector<double> params;  // user's vector
+  std::vector<double> dev;     // derived device block
+  double dev_eps = 1e-6;       // eps the LQ block was clipped with
+  cbic_context* ctx = nullptr;
+  double* d_prm = nullptr;     // device copy of `dev`
+};
