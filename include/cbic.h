@@ -115,6 +115,8 @@ typedef struct {
   int32_t precision;     /* cbic_precision; default CBIC_FP64                                */
   int32_t schedule;      /* 0 = automatic (tuned table), else a schedule id (see below)      */
   int32_t iters_per_launch; /* G: iterations per kernel launch; <= 0 = all in one launch     */
+  int32_t group_lanes;   /* lane schedule: lanes per instance (1,2,4,8,16; they split the
+                            line-search trials); 0 = automatic                               */
   uint32_t flags;        /* CBIC_FLAG_* bits                                                 */
 } cbic_solve_opts;
 
@@ -123,15 +125,18 @@ typedef struct {
 #define CBIC_SCHED_GROUP 2 /* a workgroup per instance, matrices in LDS (37-dim system)   */
 
 /* flags */
-#define CBIC_FLAG_GRAPH 1u /* launch the iteration chain through a captured HIP graph */
+#define CBIC_FLAG_GRAPH 1u  /* launch the iteration chain through a captured HIP graph      */
+#define CBIC_FLAG_TIMING 2u /* record HIP events around init / iterations / finalisation on
+                               the solve's stream; read them with cbic_phase_times          */
 
 /* Output buffers: caller-owned DEVICE pointers, AoS per instance, padded to
  * T_max; entries past an instance's horizon are written as zero.
  * Required: X[B][T_max+1][n], U[B][T_max][m], J[B] (double), iters[B] (int32),
  * status[B] (uint32).  Optional (NULL = not computed): Vbar[B][T_max+1],
  * Vx[B][T_max+1][n], xK[B][T_max+1][n], cost_trace[B][max_iter+1] (J after each
- * accepted iteration, then repeated), work[B][2] (int32: backward sweeps and
- * line-search trials that instance ran). */
+ * accepted iteration, then repeated), work[B][4] (int32: backward sweeps,
+ * line-search rollout passes, rollout steps read, rollout steps written -- the
+ * traffic that instance caused; lanes sharing an instance share its reads). */
 typedef struct {
   double* X;
   double* U;
@@ -185,6 +190,25 @@ cbic_status cbic_workspace_size(const cbic_system* sys, int32_t B, int32_t T_max
 cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max,
                              const int32_t* d_T, const double* d_x0, const double* d_U0,
                              const cbic_solve_opts* opts, const cbic_outputs* out, void* stream);
+
+/* Autotune the lane schedule for one problem class: solve the given batch
+ * (same arguments as cbic_solve_batch) once per lanes-per-instance width
+ * 1, 2, 4, 8, 16, time each on `stream`, and remember the fastest in the
+ * context for solves of the same system kind, precision, stop rule, iteration
+ * budget, batch size (rounded up to a power of two) and T_max whose
+ * group_lanes is 0.  Blocks until done; allocates scratch outputs.  The width
+ * does not change results (the line-search rule picks the same step).
+ * *best_group / *best_ms (may be NULL) receive the choice and its time. */
+cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max, const int32_t* d_T,
+                          const double* d_x0, const double* d_U0, const cbic_solve_opts* opts, void* stream,
+                          int32_t* best_group, double* best_ms);
+
+/* Milliseconds spent by the last solve on this context that was launched with
+ * CBIC_FLAG_TIMING in its three phases: ms[0] warm start and initial rollout,
+ * ms[1] the iteration kernels (backward sweeps and line searches), ms[2]
+ * finalisation (status, critic targets, outputs).  Waits for that solve's
+ * stream work to finish.  CBIC_E_INVALID if no timed solve was launched. */
+cbic_status cbic_phase_times(cbic_context* ctx, double* ms3);
 
 /* ---------------------------------------------------------------- serving
  * A continuous-batching request loop.  Requests (one TO instance each, any

@@ -750,6 +750,34 @@ void costate(const Sys& s, int T, const double* X, const double* U, double* lam,
   }
 }
 
+// Critic targets of one trajectory (X, U): stage costs c_k and c_T, the
+// K-step partial cost-to-go V_k = sum_{j=k}^{min(k+K,T)-1} c_j + [k+K >= T] c_T
+// summed in index order, its gradient V_x,k = lambda_k (costate of the full
+// tail cost), and x_{min(k+K,T)}.
+void extract(const Sys& s, int T, const double* X, const double* U, int lookahead, double* Vbar, double* Vx,
+             double* xK) {
+  const int n = s.n, m = s.m;
+  const int K = (lookahead <= 0) ? T : lookahead;
+  if (Vbar) {
+    std::vector<double> c(T + 1);
+    for (int k = 0; k < T; ++k) c[k] = cost<double>(s, X + k * n, U + k * m);
+    c[T] = term<double>(s, X + T * n);
+    for (int k = 0; k <= T; ++k) {
+      const int end = std::min(k + K, T);
+      double v = 0.0;
+      for (int t = k; t < end; ++t) v += c[t];
+      if (k + K >= T) v += c[T];
+      Vbar[k] = v;
+    }
+  }
+  if (Vx) costate(s, T, X, U, Vx, nullptr);
+  if (xK)
+    for (int k = 0; k <= T; ++k) {
+      const int t = std::min(k + K, T);
+      for (int i = 0; i < n; ++i) xK[k * n + i] = X[t * n + i];
+    }
+}
+
 struct Out {
   double* X;       // (T+1) x n
   double* U;       // T x m
@@ -941,26 +969,7 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
   *r.iters = iters;
   *r.status = status;
 
-  // ---- critic targets on the final trajectory
-  const int K = (o.lookahead <= 0) ? T : o.lookahead;
-  if (r.Vbar) {
-    std::vector<double> c(T + 1);
-    for (int k = 0; k < T; ++k) c[k] = cost<double>(s, X.data() + k * n, U.data() + k * m);
-    c[T] = term<double>(s, X.data() + T * n);
-    for (int k = 0; k <= T; ++k) {
-      const int end = std::min(k + K, T);
-      double v = 0.0;
-      for (int t = k; t < end; ++t) v += c[t];
-      if (k + K >= T) v += c[T];
-      r.Vbar[k] = v;
-    }
-  }
-  if (r.Vx) costate(s, T, X.data(), U.data(), r.Vx, nullptr);
-  if (r.xK)
-    for (int k = 0; k <= T; ++k) {
-      const int t = std::min(k + K, T);
-      for (int i = 0; i < n; ++i) r.xK[k * n + i] = X[t * n + i];
-    }
+  extract(s, T, X.data(), U.data(), o.lookahead, r.Vbar, r.Vx, r.xK);
 }
 
 thread_local char g_err[256];
@@ -1137,5 +1146,36 @@ int orc_solve_batch(int kind, const double* p, int np, int B, int Tmax, const in
 }
 
 int orc_max_threads() { return omp_get_max_threads(); }
+
+// Critic targets (V-bar[T+1], V-bar_x[T+1][n], x_K[T+1][n]) of a given
+// trajectory, without re-simulating it.
+int orc_extract(int kind, const double* p, int np, int T, const double* X, const double* U, int lookahead,
+                double* Vbar, double* Vx, double* xK) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s) || T < 1) return -1;
+  extract(s, T, X, U, lookahead, Vbar, Vx, xK);
+  return 0;
+}
+
+// Per-step dynamics residual max_i |x_{k+1,i} - f(x_k,u_k)_i| / (1 + |x_{k+1,i}|)
+// and the total cost of a given trajectory (summed in index order).
+int orc_check_trajectory(int kind, const double* p, int np, int T, const double* X, const double* U,
+                         double* defect, double* J) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s) || T < 1) return -1;
+  const int n = s.n, m = s.m;
+  std::vector<double> xn(n);
+  double d = 0.0, c = 0.0;
+  for (int k = 0; k < T; ++k) {
+    dyn<double>(s, X + k * n, U + k * m, xn.data());
+    for (int i = 0; i < n; ++i)
+      d = std::max(d, std::fabs(X[(k + 1) * n + i] - xn[i]) / (1.0 + std::fabs(X[(k + 1) * n + i])));
+    c += cost<double>(s, X + k * n, U + k * m);
+  }
+  c += term<double>(s, X + T * n);
+  *defect = d;
+  *J = c;
+  return 0;
+}
 
 }  // extern "C"

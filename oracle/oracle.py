@@ -227,3 +227,23 @@ def solve_batch(kind, params, x0, T_max, T=None, U0=None, opts: Options | None =
 
 def max_threads() -> int:
     return lib().orc_max_threads()
+
+
+def extract(kind, params, X, U, lookahead=0):
+    """(V-bar, V-bar_x, x_K) of the given trajectory X (T+1, n), U (T, m)."""
+    params = _f64(params)
+    X, U = _f64(X), _f64(U)
+    T, n = U.shape[0], X.shape[1]
+    Vb, Vx, xK = np.zeros(T + 1), np.zeros((T + 1, n)), np.zeros((T + 1, n))
+    if lib().orc_extract(kind, _p(params), len(params), T, _p(X), _p(U), lookahead, _p(Vb), _p(Vx), _p(xK)) != 0:
+        raise ValueError("bad arguments")
+    return Vb, Vx, xK
+
+
+def check_trajectory(kind, params, X, U):
+    """(max per-step relative dynamics residual, total cost) of a given trajectory."""
+    params = _f64(params)
+    X, U = _f64(X), _f64(U)
+    d, J = C.c_double(), C.c_double()
+    lib().orc_check_trajectory(kind, _p(params), len(params), U.shape[0], _p(X), _p(U), C.byref(d), C.byref(J))
+    return d.value, J.value

@@ -22,6 +22,7 @@ SYS_LQ, SYS_POINT_MASS, SYS_PLANAR3, SYS_QUAD_SYNTH = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SCHED_AUTO, SCHED_LANE, SCHED_GROUP = 0, 1, 2
 FLAG_GRAPH = 1
+FLAG_TIMING = 2
 
 
 class CbicError(RuntimeError):
@@ -34,7 +35,8 @@ class _Opts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("max_iter", C.c_int32), ("psd_eps", C.c_double),
                 ("ls_max_trials", C.c_int32), ("ls_beta", C.c_double), ("stop_mode", C.c_int32),
                 ("rtol", C.c_double), ("lookahead_K", C.c_int32), ("precision", C.c_int32),
-                ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("flags", C.c_uint32)]
+                ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("group_lanes", C.c_int32),
+                ("flags", C.c_uint32)]
 
 
 class _Outputs(C.Structure):
@@ -68,6 +70,9 @@ _SIGS = {
     "cbic_workspace_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "cbic_solve_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_phase_times": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "cbic_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_opts_default": (C.c_int32, [C.c_void_p]),
     "cbic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -112,13 +117,14 @@ class Options:
     precision: int = FP64
     schedule: int = SCHED_AUTO
     iters_per_launch: int = 0
+    group_lanes: int = 0
     flags: int = 0
 
     def c(self) -> _Opts:
         o = _Opts()
         _check(lib().cbic_opts_default(C.byref(o)))
         for f in ("max_iter", "psd_eps", "ls_max_trials", "ls_beta", "stop_mode", "rtol", "lookahead_K",
-                  "precision", "schedule", "iters_per_launch", "flags"):
+                  "precision", "schedule", "iters_per_launch", "group_lanes", "flags"):
             setattr(o, f, getattr(self, f))
         return o
 
@@ -128,6 +134,12 @@ class Context:
         self.h = C.c_void_p()
         _check(lib().cbic_context_create(device, workspace_cap, C.byref(self.h)))
         self.device = device
+
+    def phase_times(self):
+        """(init, iterations, finalisation) milliseconds of the last timed solve."""
+        ms = (C.c_double * 3)()
+        _check(lib().cbic_phase_times(self.h, ms))
+        return tuple(ms)
 
     def close(self):
         if self.h:
@@ -197,7 +209,7 @@ class Outputs:
             Vx=torch.empty(B, T_max + 1, n, **f64) if targets else None,
             xK=torch.empty(B, T_max + 1, n, **f64) if targets else None,
             cost_trace=torch.empty(B, trace_iters + 1, **f64) if trace_iters is not None else None,
-            work=torch.empty(B, 2, **i32) if work else None)
+            work=torch.empty(B, 4, **i32) if work else None)
 
     def c(self) -> _Outputs:
         o = _Outputs()
@@ -233,6 +245,24 @@ def solve_batch(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts
                                   C.byref(oc), st))
     out._keep = (x0, T, U0)  # keep inputs alive until the caller synchronises
     return out
+
+
+def autotune(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts: Options | None = None,
+             stream=None):
+    """Time every lanes-per-instance width on this problem; the context keeps
+    the fastest for later solves with group_lanes=0.  Returns (width, ms)."""
+    import torch
+    opts = opts or Options()
+    dev = torch.device("cuda", ctx.device)
+    x0 = x0.to(device=dev, dtype=torch.float64).contiguous()
+    T = None if T is None else T.to(device=dev, dtype=torch.int32).contiguous()
+    U0 = None if U0 is None else U0.to(device=dev, dtype=torch.float64).contiguous()
+    o = opts.c()
+    g, ms = C.c_int32(), C.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().cbic_autotune(ctx.h, sys.h, x0.shape[0], T_max, _dptr(T), x0.data_ptr(), _dptr(U0), C.byref(o),
+                               st, C.byref(g), C.byref(ms)))
+    return g.value, ms.value
 
 
 # ---------------------------------------------------------------- serving

@@ -43,6 +43,11 @@ cbic_status check_opts(const cbic_solve_opts* o) {
   if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) { set_error("rtol must be finite and >= 0"); return CBIC_E_INVALID; }
   if (o->precision != CBIC_FP64 && o->precision != CBIC_MIXED) { set_error("precision must be 0 or 1"); return CBIC_E_INVALID; }
   if (o->schedule < 0 || o->schedule > CBIC_SCHED_GROUP) { set_error("unknown schedule %d", o->schedule); return CBIC_E_INVALID; }
+  if (o->group_lanes != 0 && o->group_lanes != 1 && o->group_lanes != 2 && o->group_lanes != 4 &&
+      o->group_lanes != 8 && o->group_lanes != 16) {
+    set_error("group_lanes must be 0, 1, 2, 4, 8 or 16");
+    return CBIC_E_INVALID;
+  }
   return CBIC_OK;
 }
 
@@ -101,6 +106,7 @@ cbic_status cbic_opts_default(cbic_solve_opts* o) {
   o->precision = CBIC_FP64;
   o->schedule = 0;
   o->iters_per_launch = 0;
+  o->group_lanes = 0;
   o->flags = 0;
   return CBIC_OK;
 }
@@ -120,6 +126,7 @@ cbic_status cbic_context_create(int hip_device, size_t cap, cbic_context** out) 
   c->device = hip_device;
   c->cap = cap;
   hipError_t e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->phase_ev[i]);
   if (e != hipSuccess) {
     delete c;
     set_error("hipEventCreate failed: %s", hipGetErrorString(e));
@@ -139,6 +146,8 @@ cbic_status cbic_context_destroy(cbic_context* ctx) {
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->done_ev) (void)hipEventDestroy(ctx->done_ev);
+  for (int i = 0; i < 4; ++i)
+    if (ctx->phase_ev[i]) (void)hipEventDestroy(ctx->phase_ev[i]);
   delete ctx;
   return CBIC_OK;
 }
@@ -265,29 +274,37 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
   if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
   else perm = nullptr;
 
+  const bool timing = (opts->flags & CBIC_FLAG_TIMING) != 0;
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[0], stream));
   HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, stream));
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
   SolveParamsH sp{opts->max_iter, opts->ls_max_trials, opts->stop_mode, opts->lookahead_K,
                   opts->psd_eps, opts->ls_beta, opts->rtol};
+  int group = opts->group_lanes;
+  if (group <= 0) {
+    auto it = ctx->tuned.find(tune_key(sys, B, Tmax, opts));
+    group = it != ctx->tuned.end() ? it->second : default_group(sys->kind, B, opts->precision);
+  }
   if (opts->max_iter > 0) {
     const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
     const int chunks = (opts->max_iter + G - 1) / G;
     const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
     if (!graph) {
       for (int c = 0; c < chunks; ++c)
-        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, out->cost_trace, stream));
+        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream));
     } else {
       char key[256];
-      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p", (const void*)L,
-                    (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, sp.max_iter, sp.ls_trials,
-                    sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace);
+      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p", (const void*)L,
+                    (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group, sp.max_iter,
+                    sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace);
       auto it = ctx->graphs.find(key);
       if (it == ctx->graphs.end()) {
         cbic_context::GraphEntry ge;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int c = 0; c < chunks && e == hipSuccess; ++c)
-          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, out->cost_trace, stream);
+          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -302,12 +319,28 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
       HIP_TRY(hipGraphLaunch(it->second.ge, stream));
     }
   }
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[2], stream));
   FinalOutH fo{out->X, out->U, out->J, out->iters, out->status, out->Vbar, out->Vx, out->xK, out->cost_trace,
                out->work};
   HIP_TRY(L->finalize(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[3], stream));
+  ctx->timed = ctx->timed || timing;
   HIP_TRY(hipEventRecord(ctx->done_ev, stream));
   ctx->last_stream = stream;
   ctx->have_last = true;
+  return CBIC_OK;
+}
+
+cbic_status cbic_phase_times(cbic_context* ctx, double* ms3) {
+  if (!ctx || !ms3) { set_error("NULL argument"); return CBIC_E_INVALID; }
+  if (!ctx->timed) { set_error("no solve with CBIC_FLAG_TIMING was launched on this context"); return CBIC_E_INVALID; }
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipEventSynchronize(ctx->phase_ev[3]));
+  for (int i = 0; i < 3; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ctx->phase_ev[i], ctx->phase_ev[i + 1]));
+    ms3[i] = ms;
+  }
   return CBIC_OK;
 }
 

@@ -33,7 +33,7 @@ struct LaneState {
   int32_t* iters;    // accepted iterations
   uint32_t* status;  // status bits; nonzero = frozen
   int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
-  int32_t* work;     // [Bcap][2]: backward sweeps, line-search trials
+  int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
   // trajectories and gains, step-major
   R* X;   // [2][Tcap+1][Bcap][N]
   R* U;   // [2][Tcap][Bcap][M]
@@ -85,7 +85,7 @@ struct Lane {
   // One Riccati sweep over the iterate in buffer `buf`.  Writes K_k, k_k.
   // Returns 0 or the status bit that freezes the instance.
   __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf,
-                                      R eps) {
+                                      R eps, bool store) {
     R P[N][N], p[N];
     {
       R xT[N];
@@ -209,7 +209,7 @@ struct Lane {
         bad = ST_NONFINITE;
         break;
       }
-      {
+      if (store) {
         R* dK = Kp(w, k, s);
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -238,12 +238,13 @@ struct Lane {
   }
 
   // ------------------------------------------------------------------ line search trial
-  // Closed-loop rollout with step alpha from the iterate in `buf` into the
-  // other buffer; returns J_hat in FP64 (NaN-propagating).  With non-negative
-  // costs a trial stops as soon as its partial sum reaches J: its total could
-  // only be larger, so the accept/reject decision is unchanged.
+  // Closed-loop rollout with step alpha from the iterate in `buf`; returns
+  // J_hat in FP64 (NaN-propagating).  With `write` the trial trajectory goes to
+  // the other buffer.  With non-negative costs a trial stops as soon as its
+  // partial sum reaches J: its total could only be larger, so the
+  // accept/reject decision is unchanged.
   __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R alpha,
-                                 double Jcur) {
+                                 double Jcur, bool write, int& steps) {
     const int nb = buf ^ 1;
     R xh[N];
     ld(xh, xp(w, buf, 0, s));
@@ -281,18 +282,22 @@ struct Lane {
         uh[i] = v;
       }
       Jh += double(mdl.cost(xh, uh));
-      st(up(w, nb, k, s), uh);
       R xn[N];
       mdl.dyn(xh, uh, xn);
 #pragma unroll
       for (int i = 0; i < N; ++i) xh[i] = xn[i];
-      st(xp(w, nb, k + 1, s), xh);
+      if (write) {
+        st(up(w, nb, k, s), uh);
+        st(xp(w, nb, k + 1, s), xh);
+      }
       if (Sys::kNonNegCost && !(Jh < Jcur)) {
         cut = true;
+        steps = k + 1;
         break;
       }
     }
     if (cut) return Jh;
+    steps = T;
     Jh += double(mdl.term(xh));
     return Jh;
   }
@@ -347,76 +352,119 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   w.iters[s] = 0;
   w.status[s] = st;
   w.cur[s] = 0;
-  w.work[2 * s] = 0;
-  w.work[2 * s + 1] = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w.work[4 * s + i] = 0;
   if (trace) trace[size_t(slots ? s : b) * (max_iter + 1)] = J;
 }
 
-// G iterations for every active slot.  `slots` (optional) maps the thread
-// index to a slot, for the serving path's sparse slot sets.
-template <class Sys, class R>
+// Up to `iters` iterations for every active slot, with GL lanes per instance.
+// The GL lanes of a group run the backward sweep redundantly (identical
+// arithmetic on identical data; one lane stores the gains) and split the line
+// search: in round q lane r tries alpha_j, j = q*GL + r.  The first j whose
+// J_hat < J is taken (a wave ballot over the group), which is exactly the
+// sequential rule; the accepted step is then rolled out once more to write
+// it, unless it was alpha = 1, whose lane wrote while it ran.  `slots`
+// (optional) maps the group index to a slot, for sparse slot sets.
+template <class Sys, class R, int GL>
 __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
                                                    int nslots, const int32_t* __restrict__ slots,
-                                                   SolveParams sp, int G, double* __restrict__ trace) {
+                                                   SolveParams sp, int iters_this_launch,
+                                                   double* __restrict__ trace) {
   using LN = Lane<Sys, R>;
+  static_assert(GL >= 1 && GL <= 16 && (GL & (GL - 1)) == 0, "group width must be a power of two <= 16");
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nslots) return;
-  const int s = slots ? slots[tid] : tid;
+  const int gi = tid / GL;
+  const int r = tid & (GL - 1);
+  if (gi >= nslots) return;  // whole groups leave together
+  const int s = slots ? slots[gi] : gi;
   uint32_t st = w.status[s];
   if (st) return;
+  const bool lead = (r == 0);
+  const int gbase = (threadIdx.x & 63) & ~(GL - 1);  // first lane of this group in the wave
   const typename LN::Model mdl{prm};
   const int T = w.T[s];
   const int b = w.inst[s];
   double J = w.J[s];
   int iters = w.iters[s];
   int buf = w.cur[s];
-  int nsweep = w.work[2 * s], ntrial = w.work[2 * s + 1];
+  int nsweep = w.work[4 * s], npass = w.work[4 * s + 1], nread = w.work[4 * s + 2], nwrite = w.work[4 * s + 3];
   const R eps = R(sp.eps);
-  for (int g = 0; g < G && st == 0; ++g) {
+  for (int g = 0; g < iters_this_launch && st == 0; ++g) {
     if (iters >= sp.max_iter) {
       st = ST_MAX_ITER;
       break;
     }
     ++nsweep;
-    const uint32_t bad = LN::backward(mdl, w, s, T, buf, eps);
+    const uint32_t bad = LN::backward(mdl, w, s, T, buf, eps, lead);
     if (bad) {
       st = bad;
       break;
     }
-    double alpha = 1.0;
     int acc = -1;
     double Jn = J;
-    for (int j = 0; j < sp.ls_trials; ++j) {
-      ++ntrial;
-      const double Jh = LN::trial(mdl, w, s, T, buf, R(alpha), J);
-      if (isfinite(Jh) && Jh < J) {
-        acc = j;
-        Jn = Jh;
-        break;
+    for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += GL) {
+      const int j = j0 + r;
+      double Jh = __builtin_nan("");
+      int steps = 0;
+      if (j < sp.ls_trials) {
+        double alpha = 1.0;
+        for (int q = 0; q < j; ++q) alpha *= sp.beta;
+        // alpha = 1 (j == 0) is written while it runs, as is every trial of a
+        // one-lane group; other accepted steps are rolled out again below
+        Jh = LN::trial(mdl, w, s, T, buf, R(alpha), J, j == 0 || GL == 1, steps);
       }
-      alpha *= sp.beta;
+      // the lanes of a group read the same data: a round moves as many steps
+      // as its longest trial; only the alpha = 1 trial (or every trial of a
+      // one-lane group) writes
+      if (j0 == 0 || GL == 1) nwrite += __shfl(steps, gbase, 64);
+      int longest = steps;
+#pragma unroll
+      for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+      nread += longest;
+      ++npass;
+      const bool ok = isfinite(Jh) && Jh < J;
+      unsigned long long bits = __ballot(ok);
+      bits = (bits >> gbase) & ((GL == 64) ? ~0ull : ((1ull << GL) - 1));
+      if (bits) {
+        const int rs = __ffsll(bits) - 1;
+        acc = j0 + rs;
+        Jn = __shfl(Jh, gbase + rs, 64);
+      }
     }
     if (acc < 0) {
       st = ST_LS_FAILED;
       break;
     }
+    if (acc > 0 && GL > 1) {
+      double alpha = 1.0;
+      for (int q = 0; q < acc; ++q) alpha *= sp.beta;
+      int steps = 0;
+      Jn = LN::trial(mdl, w, s, T, buf, R(alpha), __builtin_inf(), lead, steps);
+      ++npass;
+      nread += steps;
+      nwrite += steps;
+    }
     buf ^= 1;
     const double Jold = J;
     J = Jn;
     ++iters;
-    if (trace) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
+    if (trace && lead) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
     if (sp.stop_mode == 1 && (Jold - J) <= sp.rtol * fabs(Jold)) {
       st = ST_CONVERGED;
       break;
     }
     if (iters >= sp.max_iter) st = ST_MAX_ITER;
   }
-  w.J[s] = J;
-  w.iters[s] = iters;
-  w.status[s] = st;
-  w.cur[s] = buf;
-  w.work[2 * s] = nsweep;
-  w.work[2 * s + 1] = ntrial;
+  if (lead) {
+    w.J[s] = J;
+    w.iters[s] = iters;
+    w.status[s] = st;
+    w.cur[s] = buf;
+    w.work[4 * s] = nsweep;
+    w.work[4 * s + 1] = npass;
+    w.work[4 * s + 2] = nread;
+    w.work[4 * s + 3] = nwrite;
+  }
 }
 
 struct FinalOut {
@@ -453,10 +501,9 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
   o.J[b] = J;
   o.iters[b] = iters;
   o.status[b] = st;
-  if (o.work) {
-    o.work[2 * b] = w.work[2 * s];
-    o.work[2 * b + 1] = w.work[2 * s + 1];
-  }
+  if (o.work)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o.work[4 * b + i] = w.work[4 * s + i];
   if (o.trace)
     for (int i = iters + 1; i <= max_iter; ++i) o.trace[size_t(b) * (max_iter + 1) + i] = J;
   double* Xo = o.X + size_t(b) * (Tmax + 1) * N;

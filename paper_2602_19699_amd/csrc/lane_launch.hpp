@@ -55,13 +55,29 @@ struct LaneLaunch {
     return hipGetLastError();
   }
 
+  template <int GL>
+  static hipError_t iterate_g(const double* prm, const LaneState<R>& w, int nthreads, const int32_t* slots,
+                              const SolveParams& sp, int G, double* trace, hipStream_t st) {
+    const long total = long(nthreads) * GL;
+    hipLaunchKernelGGL((lane_iterate<Sys, R, GL>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
+                       nthreads, slots, sp, G, trace);
+    return hipGetLastError();
+  }
+
   static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
-                            const int32_t* slots, const SolveParamsH& sp, int G, double* trace, hipStream_t st) {
+                            const int32_t* slots, const SolveParamsH& sp, int G, int group, double* trace,
+                            hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap);
-    hipLaunchKernelGGL((lane_iterate<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                       nthreads, slots, to_dev(sp), G, trace);
-    return hipGetLastError();
+    const SolveParams d = to_dev(sp);
+    switch (group) {
+      case 1: return iterate_g<1>(prm, w, nthreads, slots, d, G, trace, st);
+      case 2: return iterate_g<2>(prm, w, nthreads, slots, d, G, trace, st);
+      case 4: return iterate_g<4>(prm, w, nthreads, slots, d, G, trace, st);
+      case 8: return iterate_g<8>(prm, w, nthreads, slots, d, G, trace, st);
+      case 16: return iterate_g<16>(prm, w, nthreads, slots, d, G, trace, st);
+      default: return hipErrorInvalidValue;
+    }
   }
 
   static hipError_t finalize(const double* prm, void* base, int Bcap, int Tcap, int nthreads,

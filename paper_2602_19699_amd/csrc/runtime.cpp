@@ -38,7 +38,7 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap) {
   L.iters = o; o = align256(o + 4 * B);
   L.status = o; o = align256(o + 4 * B);
   L.cur = o; o = align256(o + 4 * B);
-  L.work = o; o = align256(o + 8 * B);
+  L.work = o; o = align256(o + 16 * B);
   L.X = o; o = align256(o + size_t(elem) * 2 * (Tcap + 1) * B * N);
   L.U = o; o = align256(o + size_t(elem) * 2 * Tcap * B * M);
   L.K = o; o = align256(o + size_t(elem) * Tcap * B * M * N);
@@ -58,6 +58,14 @@ const Launcher* find_launcher(int kind, int n, int m, int precision, int schedul
   }
   if (L && schedule != 0 && L->schedule != schedule) return nullptr;
   return L;
+}
+
+int default_group(int kind, int B, int precision) {
+  (void)kind;
+  (void)precision;
+  int g = 1;
+  while (g < 16 && long(B) * g * 2 <= 65536) g *= 2;
+  return g;
 }
 
 // ------------------------------------------------------------------ host Jacobi (LQ Hessians)

@@ -59,13 +59,21 @@ struct Launcher {
                      int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
                      int max_iter, double* trace, hipStream_t st);
   hipError_t (*iterate)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
-                        const SolveParamsH& sp, int G, double* trace, hipStream_t st);
+                        const SolveParamsH& sp, int G, int group, double* trace, hipStream_t st);
   hipError_t (*finalize)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
                          const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
                          hipStream_t st);
 };
 
 const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);
+
+// lanes per instance of the lane schedule when the caller leaves it to the
+// library: enough groups to give every SIMD of the chip a wave or two
+int default_group(int kind, int B, int precision);
+
+// key of the autotuning table for a solve (system kind and size, precision,
+// stop rule, batch rounded up to a power of two, horizon capacity)
+std::string tune_key(const cbic_system* sys, int B, int Tmax, const cbic_solve_opts* o);
 
 // horizon sort (longest first) of B instances -> perm (device)
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st);
@@ -80,6 +88,8 @@ struct cbic_context {
   hipStream_t last_stream = nullptr;
   bool have_last = false;
   hipEvent_t done_ev = nullptr;
+  hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};  // timing events
+  bool timed = false;
   std::mutex mu;
   // graph cache for the iteration chain
   struct GraphEntry {
@@ -87,6 +97,8 @@ struct cbic_context {
     hipGraphExec_t ge = nullptr;
   };
   std::map<std::string, GraphEntry> graphs;
+  // autotuned lanes per instance, keyed by problem class (see autotune.cpp)
+  std::map<std::string, int> tuned;
 };
 
 struct cbic_system {

@@ -24,26 +24,31 @@ def ctx():
 
 
 def _targets(g, r, idx, label, kind, p, x0, T_max, T=None, K=0):
-    """Critic targets.  (a) Exact: the oracle replays the GPU's final controls
-    (zero iterations, so it only rolls out and extracts) and must reproduce
-    V-bar, V-bar_x and x_{k+K} to rounding.  (b) Against the oracle's own
-    solution the trajectories agree only to the flatness of the optimum:
+    """Critic targets.  (a) Exact: on the GPU's own final trajectory the
+    oracle's extraction (no re-simulation) must reproduce V-bar, V-bar_x and
+    x_{k+K} to rounding, every step must satisfy the dynamics to rounding and
+    the returned J must be that trajectory's cost.  (b) Against the oracle's
+    own solution the trajectories agree only to the flatness of the optimum:
     cost differences of ~1e-15 J allow state differences of ~sqrt(1e-15 J / lambda)."""
     idx = np.asarray(idx)
-    Tb = None if T is None else np.asarray(T)[idx]
-    rr = orc.solve_batch(kind, p, x0[idx], T_max, T=Tb, U0=g["U"][idx], opts=oracle_opts(max_iter=0, lookahead_K=K))
-    scale = np.abs(rr.Vbar).max(axis=1, keepdims=True) + 1e-300
-    assert np.all(np.abs(g["Vbar"][idx] - rr.Vbar) <= 1e-12 * scale), f"{label}: Vbar (exact)"
-    sx = np.abs(rr.Vx).max(axis=(1, 2), keepdims=True) + 1e-300
-    assert np.all(np.abs(g["Vx"][idx] - rr.Vx) <= 1e-10 * sx), f"{label}: Vx (exact)"
-    assert np.all(np.abs(g["xK"][idx] - rr.xK) <= 1e-12 * (1 + np.abs(rr.xK))), f"{label}: xK (exact)"
-    assert np.all(np.abs(g["J"][idx] - rr.J) <= 1e-12 * np.abs(rr.J)), f"{label}: J of returned trajectory"
-    # (b) against the oracle's solution
-    scale = np.abs(r.Vbar).max(axis=1, keepdims=True) + 1e-300
-    assert np.all(np.abs(g["Vbar"][idx] - r.Vbar) <= 1e-6 * scale), f"{label}: Vbar"
-    sx = np.abs(r.Vx).max(axis=(1, 2), keepdims=True) + 1.0
-    assert np.all(np.abs(g["Vx"][idx] - r.Vx) <= 1e-5 * sx), f"{label}: Vx"
-    assert np.all(np.abs(g["xK"][idx] - r.xK) <= 1e-5 * (1 + np.abs(r.xK))), f"{label}: xK"
+    for j, b in enumerate(idx):
+        Tb = T_max if T is None else int(np.asarray(T)[b])
+        X, U = g["X"][b, :Tb + 1], g["U"][b, :Tb]
+        Vb, Vx, xK = orc.extract(kind, p, X, U, K)
+        sc = np.abs(Vb).max()
+        assert np.abs(g["Vbar"][b, :Tb + 1] - Vb).max() <= 1e-12 * sc, f"{label}: Vbar (exact) #{b}"
+        assert np.abs(g["Vx"][b, :Tb + 1] - Vx).max() <= 1e-10 * (np.abs(Vx).max() + 1e-300), f"{label}: Vx #{b}"
+        assert np.array_equal(g["xK"][b, :Tb + 1], xK), f"{label}: xK #{b}"
+        d, J = orc.check_trajectory(kind, p, X, U)
+        assert d <= 1e-12, f"{label}: dynamics residual {d:.2e} #{b}"
+        assert abs(g["J"][b] - J) <= 1e-12 * abs(J), f"{label}: J of returned trajectory #{b}"
+        assert np.array_equal(X[0], x0[b])
+    # (b) against the oracle's solution (r holds the whole batch)
+    scale = np.abs(r.Vbar[idx]).max(axis=1, keepdims=True) + 1e-300
+    assert np.all(np.abs(g["Vbar"][idx] - r.Vbar[idx]) <= 1e-6 * scale), f"{label}: Vbar"
+    sx = np.abs(r.Vx[idx]).max(axis=(1, 2), keepdims=True) + 1.0
+    assert np.all(np.abs(g["Vx"][idx] - r.Vx[idx]) <= 1e-5 * sx), f"{label}: Vx"
+    assert np.all(np.abs(g["xK"][idx] - r.xK[idx]) <= 1e-5 * (1 + np.abs(r.xK[idx]))), f"{label}: xK"
 
 
 def test_point_mass_64_fp64(ctx):
@@ -129,9 +134,12 @@ def test_arm_ragged_fp64(ctx):
 
 
 def _replay_all(g, kind, p, x0, T_max, T):
-    # every returned trajectory is the rollout of its controls with the returned cost
-    rr = orc.solve_batch(kind, p, x0, T_max, T=T, U0=g["U"], opts=oracle_opts(max_iter=0))
-    assert np.all(rel(g["J"], rr.J) <= 1e-11)
+    # every returned trajectory satisfies the dynamics step by step and has the returned cost
+    for b in range(len(x0)):
+        Tb = T_max if T is None else int(T[b])
+        d, J = orc.check_trajectory(kind, p, g["X"][b, :Tb + 1], g["U"][b, :Tb])
+        assert d <= 1e-12 and abs(J - g["J"][b]) <= 1e-12 * abs(J), f"instance {b}: residual {d:.2e}"
+        assert np.array_equal(g["X"][b, 0], x0[b])
 
 
 def test_arm_4k_sampled(ctx):
@@ -194,3 +202,18 @@ def test_batch_independence(ctx):
         one = gpu_solve(ctx, P3, p, x0[[b]], int(T[b]), max_iter=10)
         assert one["J"][0] == full["J"][b]
         np.testing.assert_array_equal(one["X"][0], full["X"][b, : T[b] + 1])
+
+
+@pytest.mark.parametrize("kind", [PM, P3], ids=["pm", "arm"])
+def test_group_widths_give_identical_results(ctx, kind):
+    # lanes of a group split the line-search trials; the first accepted step is
+    # the same as in the sequential rule, so results are bitwise identical
+    if kind == PM:
+        p, x0, T, Tb = I.point_mass_params(0), I.point_mass_x0(150, 5), 100, None
+    else:
+        p, x0, T, Tb = I.planar3_params(0), I.planar3_x0(90, 6), 120, I.horizons(90, 30, 120, seed=3)
+    ref = gpu_solve(ctx, kind, p, x0, T, T=Tb, max_iter=15, group_lanes=1)
+    for gl in (2, 4, 8, 16):
+        g = gpu_solve(ctx, kind, p, x0, T, T=Tb, max_iter=15, group_lanes=gl)
+        for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"):
+            np.testing.assert_array_equal(ref[k], g[k], err_msg=f"group_lanes={gl} field {k}")
