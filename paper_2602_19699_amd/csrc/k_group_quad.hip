@@ -1,8 +1,842 @@
-// Workgroup-per-instance solver for the 37-state synthetic quadruped.
-#include "runtime.hpp"
+// Workgroup-per-instance iLQR for the 37-state synthetic quadruped
+// (q in R^19, v in R^18, u in R^12; paper Sec. II eq. 1 and Sec. IV).
+//
+// One 256-thread workgroup owns one instance.  The backward Riccati sweep
+// keeps P, f_x, P f_x, f_u, P f_u, the gains and Q_ux in LDS and forms the
+// products with block-tiled GEMM-lets (a 16 x 16 thread grid, register tiles);
+// Q_uu is factored in FP64 (wave 0, rows held by lanes, columns exchanged by
+// lane shuffles) in both precisions.  The dynamics step needs a Cholesky of
+// the 18 x 18 mass matrix M(q) = A^T A + diag(1 + 0.1 sin q); a wave does it
+// with its lanes holding the rows.  Line-search trials run one per wave: in
+// round r wave w tries alpha_j with j = 4 r + w, and the first accepted j is
+// taken, as in the sequential rule.  Trajectories and gains use the same
+// step-major workspace as the lane schedule.
+#include "lane_launch.hpp"
 
 namespace cbic {
+namespace quad {
 
-const Launcher* launcher_quad(int) { return nullptr; }
+constexpr int NQ = 19, NV = 18, N = 37, M = 12;
+constexpr int LD = 40;   // row stride of 37-wide LDS matrices
+constexpr int LDB = 13;  // row stride of 12-wide LDS matrices
+constexpr int NT = 256;  // threads per workgroup
+constexpr int NW = NT / 64;
+
+// device block: [dt, w_u, w_T, w_q, w_v, M0 = A^T A (18x18), W1, W2, e(18), x_nom(37)]
+constexpr int O_DT = 0, O_WU = 1, O_WT = 2, O_WQ = 3, O_WV = 4, O_M0 = 5, O_W1 = O_M0 + 324,
+              O_W2 = O_W1 + 324, O_E = O_W2 + 324, O_XN = O_E + 18, NPRM = O_XN + 37;
+
+template <class R>
+struct WaveScratch {
+  R L[NV][NV + 1];  // Cholesky factor of M(q), lower, row-major
+  R x[LD];          // state of this wave's rollout
+  R xn[LD];         // next state
+  R u[16];          // control
+  R dx[LD];
+  R s[NV], c[NV];   // sin, cos of q[0:18]
+  R a[NV];          // acceleration M^-1 (S u - b)
+  R w2c[NV];        // W2 cos q
+};
+
+template <class R>
+struct Smem {
+  R M0[NV][NV + 1];
+  R W1[NV][NV + 1];
+  R W2[NV][NV + 1];
+  R e[NV];
+  R xnom[LD];
+  R P[N][LD];   // value Hessian; Q_xx; the updated P
+  R A[N][LD];   // f_x
+  R PA[N][LD];  // P f_x; right-hand sides of the Jacobian solves; scratch
+  R Bm[N][LDB]; // f_u
+  R PB[N][LDB]; // P f_u
+  R Kg[M][LD];  // feedback gain (m x n)
+  R Qux[M][LD];
+  R p[LD], Qx[LD], lx[LD];
+  R Qu[16], kk[16], lu[16];
+  double Quu[M][M + 1];
+  double Lq[M][M + 1];
+  double wJ[NW];
+  int wok[NW];
+  int flag;
+  WaveScratch<R> wv[NW];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------ constants
+template <class R>
+__device__ void stage_constants(Smem<R>& sm, const double* __restrict__ prm, int tid) {
+  for (int i = tid; i < NV * NV; i += NT) {
+    const int r = i / NV, c = i % NV;
+    sm.M0[r][c] = R(prm[O_M0 + i]);
+    sm.W1[r][c] = R(prm[O_W1 + i]);
+    sm.W2[r][c] = R(prm[O_W2 + i]);
+  }
+  if (tid < NV) sm.e[tid] = R(prm[O_E + tid]);
+  if (tid < N) sm.xnom[tid] = R(prm[O_XN + tid]);
+}
+
+// ------------------------------------------------------------------ wave-level dynamics
+// One semi-implicit Euler step for wave scratch ws: reads ws.x and ws.u,
+// writes ws.xn; leaves L (factor of M), a, sin/cos and W2 cos q in ws.
+template <class R>
+__device__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) {
+  if (lane < NV) {
+    R sn, cs;
+    dsincos(ws.x[lane], &sn, &cs);
+    ws.s[lane] = sn;
+    ws.c[lane] = cs;
+  }
+  wave_sync();
+  const bool row = lane < NV;
+  const int ri = row ? lane : 0;
+  R m[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) m[j] = row ? sm.M0[ri][j] : R(0);
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    if (j == lane) m[j] += R(1) + R(0.1) * ws.s[ri];
+  // Cholesky, rows on lanes
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const R piv = __shfl(m[j], j, 64);
+    const R ljj = dsqrt(piv);
+    const R inv = R(1) / ljj;
+    const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
+    m[j] = lij;
+#pragma unroll
+    for (int k = j + 1; k < NV; ++k) {
+      const R lkj = __shfl(lij, k, 64);
+      m[k] -= lij * lkj;
+    }
+  }
+  if (row)
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j <= lane) ws.L[ri][j] = m[j];
+  // bias forces and right-hand side r = S u - b
+  R y = R(0);
+  if (row) {
+    R b1 = R(0), b2 = R(0);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      b1 += sm.W1[ri][j] * ws.s[j];
+      b2 += sm.W2[ri][j] * ws.c[j];
+    }
+    ws.w2c[ri] = b2;
+    const R b = b1 + b2 * ws.x[NQ + ri];
+    y = (ri >= 6 ? ws.u[ri - 6] : R(0)) - b;
+  }
+  wave_sync();
+  // L z = r (rows on lanes)
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    const R t = y / m[j];
+    const R yj = __shfl(t, j, 64);
+    if (lane == j) y = yj;
+    else if (lane > j) y -= m[j] * yj;
+  }
+  // L^T a = z
+#pragma unroll
+  for (int j = NV - 1; j >= 0; --j) {
+    const R t = y / m[j];
+    const R zj = __shfl(t, j, 64);
+    if (lane == j) y = zj;
+    else if (lane < j) y -= ws.L[j][ri] * zj;
+  }
+  R ev = R(0);
+  if (row) {
+    ws.a[ri] = y;
+    const R vn = ws.x[NQ + ri] + dt * y;
+    ws.xn[NQ + ri] = vn;
+    ws.xn[ri] = ws.x[ri] + dt * vn;
+    ev = sm.e[ri] * vn;
+  }
+  ev = wave_sum(ev);
+  if (lane == 0) ws.xn[NV] = ws.x[NV] + dt * ev;
+  wave_sync();
+}
+
+// running cost l(x, u) of the wave's (x, u); the same value in every lane
+template <class R>
+__device__ R wave_cost(const Smem<R>& sm, const R* x, const R* u, const double* __restrict__ prm, int lane,
+                       bool terminal) {
+  R v = R(0);
+  if (lane < N) {
+    const R d = x[lane] - sm.xnom[lane];
+    v = (lane < NQ ? R(prm[O_WQ]) : R(prm[O_WV])) * d * d;
+    if (terminal) v *= R(prm[O_WT]);
+  } else if (!terminal && lane < N + M) {
+    const R uu = u[lane - N];
+    v = R(prm[O_WU]) * uu * uu;
+  }
+  return wave_sum(v);
+}
+
+// ------------------------------------------------------------------ block GEMM
+// C = Cin + op(A) op(B) over an Mr x Nc output with inner size Kd, on a 16 x 16
+// thread grid with register tiles; op(A)(i,k) = TA ? A[k][i] : A[i][k].
+template <int Mr, int Nc, int Kd, bool TA, bool TB, class R>
+__device__ __forceinline__ void blk_gemm(R* C, int ldc, const R* A, int lda, const R* Bp, int ldb, const R* Cin,
+                                         int ldcin, int tid) {
+  constexpr int RT = (Mr + 15) / 16, CT = (Nc + 15) / 16;
+  const int tr = tid >> 4, tc = tid & 15;
+  R acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      acc[a][b] = (Cin && i < Mr && j < Nc) ? Cin[i * ldcin + j] : R(0);
+    }
+  for (int k = 0; k < Kd; ++k) {
+    R av[RT], bv[CT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int i = tr + 16 * a;
+      av[a] = i < Mr ? (TA ? A[k * lda + i] : A[i * lda + k]) : R(0);
+    }
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int j = tc + 16 * b;
+      bv[b] = j < Nc ? (TB ? Bp[j * ldb + k] : Bp[k * ldb + j]) : R(0);
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) acc[a][b] += av[a] * bv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int i = tr + 16 * a, j = tc + 16 * b;
+      if (i < Mr && j < Nc) C[i * ldc + j] = acc[a][b];
+    }
+}
+
+// ------------------------------------------------------------------ Jacobians
+// f_x into sm.A and f_u into sm.Bm at (wv[0].x, wv[0].u); wave 0 must have run
+// wave_dyn on that point (L, a, sin/cos, W2 cos q in wv[0]).  All threads.
+template <class R>
+__device__ void jacobians(Smem<R>& sm, R dt, int tid) {
+  const WaveScratch<R>& ws = sm.wv[0];
+  R* Z = &sm.PA[0][0];  // 18 x 48 right-hand sides, row stride 48
+  // RHS columns: 0..17 -dD/dq (a and v held), 18..35 -dD/dv, 36..47 S
+  for (int idx = tid; idx < NV * 48; idx += NT) {
+    const int i = idx / 48, col = idx % 48;
+    R v;
+    if (col < NV) {
+      const int j = col;
+      v = -(sm.W1[i][j] * ws.c[j] - ws.x[NQ + i] * sm.W2[i][j] * ws.s[j]);
+      if (i == j) v -= R(0.1) * ws.c[i] * ws.a[i];
+    } else if (col < 2 * NV) {
+      v = (col - NV == i) ? -ws.w2c[i] : R(0);
+    } else {
+      v = (col - 2 * NV + 6 == i) ? R(1) : R(0);
+    }
+    Z[i * 48 + col] = v;
+  }
+  __syncthreads();
+  if (tid < 48) {  // column solves with L L^T
+    R y[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) y[i] = Z[i * 48 + tid];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      R v = y[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= ws.L[i][k] * y[k];
+      y[i] = v / ws.L[i][i];
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+      R v = y[i];
+#pragma unroll
+      for (int k = i + 1; k < NV; ++k) v -= ws.L[k][i] * y[k];
+      y[i] = v / ws.L[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) Z[i * 48 + tid] = y[i];
+  }
+  __syncthreads();
+  // d v+/d x and d v+/d u, then q rows: q+ = q + dt E v+
+  for (int idx = tid; idx < N * (N + M); idx += NT) {
+    const int r = idx / (N + M), col = idx % (N + M);
+    auto dv = [&](int i) -> R {  // d v+_i / d (x, u)_col
+      if (col < NV) return dt * Z[i * 48 + col];
+      if (col == NV) return R(0);
+      if (col < N) return ((col - NQ) == i ? R(1) : R(0)) + dt * Z[i * 48 + NV + (col - NQ)];
+      return dt * Z[i * 48 + 2 * NV + (col - N)];
+    };
+    R v;
+    const R id = (col < N && col == r) ? R(1) : R(0);
+    if (r >= NQ) v = dv(r - NQ);
+    else if (r < NV) v = id + dt * dv(r);
+    else {
+      R s = R(0);
+#pragma unroll
+      for (int i = 0; i < NV; ++i) s += sm.e[i] * dv(i);
+      v = id + dt * s;
+    }
+    if (col < N) sm.A[r][col] = v;
+    else sm.Bm[r][col - N] = v;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ FP64 Cholesky of Q_uu and the gains
+// Wave 0 factors Quu (rows on lanes); threads 0..37 solve for [K k].
+template <class R>
+__device__ bool gains(Smem<R>& sm, int tid) {
+  if (tid < 64) {
+    const int lane = tid;
+    const bool row = lane < M;
+    const int ri = row ? lane : 0;
+    double m[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) m[j] = row ? sm.Quu[min(ri, j)][max(ri, j)] : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const double piv = __shfl(m[j], j, 64);
+      ok = ok && (piv > 0.0) && isfinite(piv);
+      const double ljj = sqrt(piv);
+      const double inv = 1.0 / ljj;
+      const double lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : 0.0);
+      m[j] = lij;
+#pragma unroll
+      for (int k = j + 1; k < M; ++k) m[k] -= lij * __shfl(lij, k, 64);
+    }
+    if (row)
+#pragma unroll
+      for (int j = 0; j < M; ++j) sm.Lq[ri][j] = m[j];
+    if (lane == 0) sm.flag = ok ? 0 : 1;
+  }
+  __syncthreads();
+  if (sm.flag) return false;
+  if (tid <= N) {  // column tid of [Q_ux | Q_u]
+    double y[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) y[i] = double(tid < N ? sm.Qux[i][tid] : sm.Qu[i]);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double v = y[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= sm.Lq[i][k] * y[k];
+      y[i] = v / sm.Lq[i][i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+      double v = y[i];
+#pragma unroll
+      for (int k = i + 1; k < M; ++k) v -= sm.Lq[k][i] * y[k];
+      y[i] = v / sm.Lq[i][i];
+    }
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < M; ++i) fin = fin && isfinite(y[i]);
+    if (!fin) sm.flag = 2;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      if (tid < N) sm.Kg[i][tid] = R(-y[i]);
+      else sm.kk[i] = R(-y[i]);
+    }
+  }
+  __syncthreads();
+  return sm.flag == 0;
+}
+
+template <class R>
+struct QW {  // workspace accessors (same layout as the lane schedule)
+  static __device__ __forceinline__ R* xp(const LaneState<R>& w, int buf, int k, int s) {
+    return w.X + ((size_t(buf) * (w.Tcap + 1) + k) * w.Bcap + s) * N;
+  }
+  static __device__ __forceinline__ R* up(const LaneState<R>& w, int buf, int k, int s) {
+    return w.U + ((size_t(buf) * w.Tcap + k) * w.Bcap + s) * M;
+  }
+  static __device__ __forceinline__ R* Kp(const LaneState<R>& w, int k, int s) {
+    return w.K + (size_t(k) * w.Bcap + s) * (M * N);
+  }
+  static __device__ __forceinline__ R* kp(const LaneState<R>& w, int k, int s) {
+    return w.kf + (size_t(k) * w.Bcap + s) * M;
+  }
+};
+
+// ------------------------------------------------------------------ backward sweep
+template <class R>
+__device__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
+                             int buf, R eps, int tid) {
+  using Q = QW<R>;
+  const R dt = R(prm[O_DT]);
+  const R wq = R(prm[O_WQ]), wv = R(prm[O_WV]), wu = R(prm[O_WU]), wT = R(prm[O_WT]);
+  WaveScratch<R>& w0 = sm.wv[0];
+  // terminal: P = clip(l_T,xx) (diagonal), p = l_T,x
+  for (int i = tid; i < N * LD; i += NT) (&sm.P[0][0])[i] = R(0);
+  __syncthreads();
+  if (tid < N) {
+    const R xv = Q::xp(w, buf, T, s)[tid];
+    const R wi = (tid < NQ ? wq : wv) * wT;
+    sm.p[tid] = R(2) * wi * (xv - sm.xnom[tid]);
+    sm.P[tid][tid] = dmax(R(2) * wi, eps);
+  }
+  __syncthreads();
+  for (int k = T - 1; k >= 0; --k) {
+    if (tid < N) w0.x[tid] = Q::xp(w, buf, k, s)[tid];
+    if (tid < M) w0.u[tid] = Q::up(w, buf, k, s)[tid];
+    __syncthreads();
+    if (tid < 64) wave_dyn(sm, w0, dt, tid);
+    __syncthreads();
+    jacobians(sm, dt, tid);
+    // cost derivatives (diagonal Hessians)
+    if (tid < N) sm.lx[tid] = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
+    if (tid < M) sm.lu[tid] = R(2) * wu * w0.u[tid];
+    // PA = P A, PB = P B
+    blk_gemm<N, N, N, false, false>(&sm.PA[0][0], LD, &sm.P[0][0], LD, &sm.A[0][0], LD, (const R*)nullptr, 0, tid);
+    blk_gemm<N, M, N, false, false>(&sm.PB[0][0], LDB, &sm.P[0][0], LD, &sm.Bm[0][0], LDB, (const R*)nullptr, 0, tid);
+    __syncthreads();
+    // Q_x = l_x + A^T p, Q_u = l_u + B^T p (before P is overwritten)
+    if (tid < N + M) {
+      R v;
+      if (tid < N) {
+        v = sm.lx[tid];
+        for (int t = 0; t < N; ++t) v += sm.A[t][tid] * sm.p[t];
+      } else {
+        const int c = tid - N;
+        v = sm.lu[c];
+        for (int t = 0; t < N; ++t) v += sm.Bm[t][c] * sm.p[t];
+      }
+      if (tid < N) sm.Qx[tid] = v;
+      else sm.Qu[tid - N] = v;
+    }
+    __syncthreads();
+    // Q_xx = clip(l_xx) + A^T (P A) into P; Q_uu = clip(l_uu) + B^T (P B); Q_ux = B^T (P A)
+    blk_gemm<N, N, N, true, false>(&sm.P[0][0], LD, &sm.A[0][0], LD, &sm.PA[0][0], LD, (const R*)nullptr, 0, tid);
+    blk_gemm<M, N, N, true, false>(&sm.Qux[0][0], LD, &sm.Bm[0][0], LDB, &sm.PA[0][0], LD, (const R*)nullptr, 0, tid);
+    if (tid < M * M) {
+      const int i = tid / M, j = tid % M;
+      R v = R(0);
+      for (int t = 0; t < N; ++t) v += sm.Bm[t][i] * sm.PB[t][j];
+      sm.Quu[i][j] = double(v) + (i == j ? double(dmax(R(2) * wu, eps)) : 0.0);
+    }
+    __syncthreads();
+    if (tid < N) sm.P[tid][tid] += dmax(R(2) * (tid < NQ ? wq : wv), eps);
+    if (!gains(sm, tid)) return sm.flag == 1 ? ST_CHOL_FAIL : ST_NONFINITE;
+    // store the gains
+    {
+      R* dK = Q::Kp(w, k, s);
+      for (int i = tid; i < M * N; i += NT) dK[i] = sm.Kg[i / N][i % N];
+      if (tid < M) Q::kp(w, k, s)[tid] = sm.kk[tid];
+    }
+    // C = Q_xx + Q_ux^T K into PA, p = Q_x + Q_ux^T k
+    blk_gemm<N, N, M, true, false>(&sm.PA[0][0], LD, &sm.Qux[0][0], LD, &sm.Kg[0][0], LD, &sm.P[0][0], LD, tid);
+    if (tid < N) {
+      R v = sm.Qx[tid];
+      for (int t = 0; t < M; ++t) v += sm.Qux[t][tid] * sm.kk[t];
+      sm.p[tid] = v;
+    }
+    __syncthreads();
+    // P = sym(C)
+    for (int idx = tid; idx < N * N; idx += NT) {
+      const int i = idx / N, j = idx % N;
+      sm.P[i][j] = R(0.5) * (sm.PA[i][j] + sm.PA[j][i]);
+    }
+    __syncthreads();
+  }
+  return 0;
+}
+
+// ------------------------------------------------------------------ line-search trial (one wave)
+// Closed-loop rollout of wave `wid` with step alpha; writes the trajectory
+// when `write`; early stop once the partial cost reaches Jcur (costs >= 0).
+template <class R>
+__device__ double wave_trial(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
+                             int buf, R alpha, double Jcur, bool write, int lane, int wid, int& steps) {
+  using Q = QW<R>;
+  WaveScratch<R>& ws = sm.wv[wid];
+  const R dt = R(prm[O_DT]);
+  const int nb = buf ^ 1;
+  if (lane < N) ws.x[lane] = Q::xp(w, buf, 0, s)[lane];
+  wave_sync();
+  double Jh = 0.0;
+  steps = T;
+  for (int k = 0; k < T; ++k) {
+    if (lane < N) ws.dx[lane] = ws.x[lane] - Q::xp(w, buf, k, s)[lane];
+    wave_sync();
+    {
+      const int c = lane >> 2, part = lane & 3;
+      R acc = R(0);
+      if (c < M) {
+        const R* Kr = Q::Kp(w, k, s) + c * N;
+        for (int j = part; j < N; j += 4) acc += Kr[j] * ws.dx[j];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (c < M && part == 0) ws.u[c] = Q::up(w, buf, k, s)[c] + alpha * Q::kp(w, k, s)[c] + acc;
+    }
+    wave_sync();
+    Jh += double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
+    wave_dyn(sm, ws, dt, lane);
+    if (write) {
+      if (lane < M) Q::up(w, nb, k, s)[lane] = ws.u[lane];
+      if (lane < N) Q::xp(w, nb, k + 1, s)[lane] = ws.xn[lane];
+    }
+    if (lane < N) ws.x[lane] = ws.xn[lane];
+    wave_sync();
+    if (!(Jh < Jcur)) {
+      steps = k + 1;
+      return Jh;
+    }
+  }
+  Jh += double(wave_cost(sm, ws.x, ws.u, prm, lane, true));
+  return Jh;
+}
+
+// ------------------------------------------------------------------ kernels
+template <class R>
+__global__ void __launch_bounds__(NT) quad_init(const double* __restrict__ prm, LaneState<R> w, int nthreads,
+                                                 const int32_t* __restrict__ slots, int Tmax,
+                                                 const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ x0, const double* __restrict__ U0,
+                                                 int max_iter, double* __restrict__ trace) {
+  using Q = QW<R>;
+  __shared__ Smem<R> sm;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  if (g >= nthreads) return;
+  const int s = slots ? slots[g] : g;
+  const int b = perm ? perm[g] : g;
+  const int Tr = Tin ? Tin[b] : Tmax;
+  const bool badT = Tr < 1 || Tr > Tmax || Tr > w.Tcap;
+  const int T = badT ? 0 : Tr;
+  stage_constants(sm, prm, tid);
+  __syncthreads();
+  if (tid >= 64) return;
+  const int lane = tid;
+  WaveScratch<R>& ws = sm.wv[0];
+  const R dt = R(prm[O_DT]);
+  if (lane < N) {
+    const R v = R(x0[size_t(b) * N + lane]);
+    ws.x[lane] = v;
+    Q::xp(w, 0, 0, s)[lane] = v;
+    Q::xp(w, 1, 0, s)[lane] = v;
+  }
+  wave_sync();
+  double J = 0.0;
+  for (int k = 0; k < T; ++k) {
+    if (lane < M) {
+      const R v = U0 ? R(U0[(size_t(b) * Tmax + k) * M + lane]) : R(0);
+      ws.u[lane] = v;
+      Q::up(w, 0, k, s)[lane] = v;
+    }
+    wave_sync();
+    J += double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
+    wave_dyn(sm, ws, dt, lane);
+    if (lane < N) {
+      ws.x[lane] = ws.xn[lane];
+      Q::xp(w, 0, k + 1, s)[lane] = ws.xn[lane];
+    }
+    wave_sync();
+  }
+  J += double(wave_cost(sm, ws.x, ws.u, prm, lane, true));
+  if (lane == 0) {
+    uint32_t st = isfinite(J) ? 0u : ST_NONFINITE;
+    if (st == 0 && max_iter <= 0) st = ST_MAX_ITER;
+    if (badT) {
+      st = ST_BAD_INPUT;
+      J = __builtin_nan("");
+    }
+    w.T[s] = T;
+    w.inst[s] = slots ? s : b;
+    w.J[s] = J;
+    w.iters[s] = 0;
+    w.status[s] = st;
+    w.cur[s] = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w.work[4 * s + i] = 0;
+    if (trace) trace[size_t(slots ? s : b) * (max_iter + 1)] = J;
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(NT) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
+                                                    const int32_t* __restrict__ slots, SolveParams sp,
+                                                    int iters_this_launch, double* __restrict__ trace) {
+  __shared__ Smem<R> sm;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  if (g >= nslots) return;
+  const int s = slots ? slots[g] : g;
+  uint32_t st = w.status[s];
+  if (st) return;  // uniform over the workgroup
+  const int lane = tid & 63, wid = tid >> 6;
+  stage_constants(sm, prm, tid);
+  __syncthreads();
+  const int T = w.T[s];
+  const int b = w.inst[s];
+  double J = w.J[s];
+  int iters = w.iters[s];
+  int buf = w.cur[s];
+  int nsweep = w.work[4 * s], npass = w.work[4 * s + 1], nread = w.work[4 * s + 2], nwrite = w.work[4 * s + 3];
+  const R eps = R(sp.eps);
+  for (int it = 0; it < iters_this_launch && st == 0; ++it) {
+    if (iters >= sp.max_iter) {
+      st = ST_MAX_ITER;
+      break;
+    }
+    ++nsweep;
+    const uint32_t bad = backward(sm, prm, w, s, T, buf, eps, tid);
+    if (bad) {
+      st = bad;
+      break;
+    }
+    int acc = -1;
+    double Jn = J;
+    for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += NW) {
+      const int j = j0 + wid;
+      double Jh = __builtin_nan("");
+      int steps = 0;
+      if (j < sp.ls_trials) {
+        double alpha = 1.0;
+        for (int q = 0; q < j; ++q) alpha *= sp.beta;
+        Jh = wave_trial(sm, prm, w, s, T, buf, R(alpha), J, j == 0, lane, wid, steps);
+      }
+      if (lane == 0) {
+        sm.wJ[wid] = Jh;
+        sm.wok[wid] = steps;
+      }
+      __syncthreads();
+      int longest = 0;
+      for (int q = 0; q < NW; ++q) {
+        longest = max(longest, sm.wok[q]);
+        const double v = sm.wJ[q];
+        if (acc < 0 && j0 + q < sp.ls_trials && isfinite(v) && v < J) {
+          acc = j0 + q;
+          Jn = v;
+        }
+      }
+      if (j0 == 0) nwrite += sm.wok[0];
+      nread += longest;
+      ++npass;
+      __syncthreads();
+    }
+    if (acc < 0) {
+      st = ST_LS_FAILED;
+      break;
+    }
+    if (acc > 0) {
+      double alpha = 1.0;
+      for (int q = 0; q < acc; ++q) alpha *= sp.beta;
+      int steps = 0;
+      if (wid == 0) {
+        const double Jc = wave_trial(sm, prm, w, s, T, buf, R(alpha), __builtin_inf(), true, lane, 0, steps);
+        if (lane == 0) sm.wJ[0] = Jc;
+      }
+      __syncthreads();
+      Jn = sm.wJ[0];
+      ++npass;
+      nread += T;
+      nwrite += T;
+      __syncthreads();
+    }
+    buf ^= 1;
+    const double Jold = J;
+    J = Jn;
+    ++iters;
+    if (trace && tid == 0) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
+    if (sp.stop_mode == 1 && (Jold - J) <= sp.rtol * fabs(Jold)) {
+      st = ST_CONVERGED;
+      break;
+    }
+    if (iters >= sp.max_iter) st = ST_MAX_ITER;
+  }
+  if (tid == 0) {
+    w.J[s] = J;
+    w.iters[s] = iters;
+    w.status[s] = st;
+    w.cur[s] = buf;
+    w.work[4 * s] = nsweep;
+    w.work[4 * s + 1] = npass;
+    w.work[4 * s + 2] = nread;
+    w.work[4 * s + 3] = nwrite;
+  }
+}
+
+template <class R>
+__global__ void __launch_bounds__(NT) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
+                                                  const int32_t* __restrict__ slots, int Tmax, int max_iter,
+                                                  int lookahead, FinalOut o) {
+  using Q = QW<R>;
+  __shared__ Smem<R> sm;
+  const int g = blockIdx.x, tid = threadIdx.x;
+  if (g >= nslots) return;
+  const int s = slots ? slots[g] : g;
+  const int b = w.inst[s];
+  const int buf = w.cur[s];
+  uint32_t st = w.status[s];
+  if (st == 0) st = ST_MAX_ITER;
+  const int T = (st & ST_BAD_INPUT) ? -1 : w.T[s];
+  const double J = w.J[s];
+  const int iters = w.iters[s];
+  if (tid == 0) {
+    o.J[b] = J;
+    o.iters[b] = iters;
+    o.status[b] = st;
+    if (o.work)
+      for (int i = 0; i < 4; ++i) o.work[4 * b + i] = w.work[4 * s + i];
+  }
+  if (o.trace)
+    for (int i = iters + 1 + tid; i <= max_iter; i += NT) o.trace[size_t(b) * (max_iter + 1) + i] = J;
+  double* Xo = o.X + size_t(b) * (Tmax + 1) * N;
+  double* Uo = o.U + size_t(b) * Tmax * M;
+  for (int idx = tid; idx < (Tmax + 1) * N; idx += NT) {
+    const int k = idx / N, i = idx % N;
+    Xo[idx] = k <= T ? double(Q::xp(w, buf, k, s)[i]) : 0.0;
+  }
+  for (int idx = tid; idx < Tmax * M; idx += NT) {
+    const int k = idx / M, i = idx % M;
+    Uo[idx] = k < T ? double(Q::up(w, buf, k, s)[i]) : 0.0;
+  }
+  const int K = lookahead <= 0 ? T : lookahead;
+  if (o.xK) {
+    double* xo = o.xK + size_t(b) * (Tmax + 1) * N;
+    for (int idx = tid; idx < (Tmax + 1) * N; idx += NT) {
+      const int k = idx / N, i = idx % N;
+      xo[idx] = k <= T ? double(Q::xp(w, buf, (k + K < T ? k + K : T), s)[i]) : 0.0;
+    }
+  }
+  double* Vo = o.Vbar ? o.Vbar + size_t(b) * (Tmax + 1) : nullptr;
+  double* Lo = o.Vx ? o.Vx + size_t(b) * (Tmax + 1) * N : nullptr;
+  if (T < 0) {
+    if (Vo)
+      for (int k = tid; k <= Tmax; k += NT) Vo[k] = 0.0;
+    if (Lo)
+      for (int idx = tid; idx < (Tmax + 1) * N; idx += NT) Lo[idx] = 0.0;
+    return;
+  }
+  if (!Vo && !Lo) return;
+  stage_constants(sm, prm, tid);
+  __syncthreads();
+  const R dt = R(prm[O_DT]);
+  const R wq = R(prm[O_WQ]), wv = R(prm[O_WV]), wT = R(prm[O_WT]);
+  WaveScratch<R>& w0 = sm.wv[0];
+  // lambda_T = d l_T / dx
+  if (tid < N) {
+    w0.x[tid] = Q::xp(w, buf, T, s)[tid];
+    const R wi = (tid < NQ ? wq : wv) * wT;
+    sm.p[tid] = R(2) * wi * (w0.x[tid] - sm.xnom[tid]);
+    if (Lo) Lo[size_t(T) * N + tid] = double(sm.p[tid]);
+  }
+  __syncthreads();
+  if (Vo && tid < 64) {
+    const double cT = double(wave_cost(sm, w0.x, w0.u, prm, tid, true));
+    if (tid == 0) Vo[T] = cT;
+  }
+  __syncthreads();
+  for (int k = T - 1; k >= 0; --k) {
+    if (tid < N) w0.x[tid] = Q::xp(w, buf, k, s)[tid];
+    if (tid < M) w0.u[tid] = Q::up(w, buf, k, s)[tid];
+    __syncthreads();
+    if (tid < 64) {
+      const double c = double(wave_cost(sm, w0.x, w0.u, prm, tid, false));
+      if (Vo && tid == 0) Vo[k] = c;
+      if (Lo) wave_dyn(sm, w0, dt, tid);
+    }
+    __syncthreads();
+    if (Lo) {
+      jacobians(sm, dt, tid);
+      R v = R(0);
+      if (tid < N) {
+        v = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
+        for (int t = 0; t < N; ++t) v += sm.A[t][tid] * sm.p[t];
+      }
+      __syncthreads();
+      if (tid < N) {
+        sm.p[tid] = v;
+        Lo[size_t(k) * N + tid] = double(v);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (Vo && tid == 0) {
+    const double cT = Vo[T];
+    if (K >= T) {
+      double acc = cT;
+      for (int k = T - 1; k >= 0; --k) {
+        acc = Vo[k] + acc;
+        Vo[k] = acc;
+      }
+    } else {
+      for (int k = 0; k < T; ++k) {
+        const int end = k + K < T ? k + K : T;
+        double v = 0.0;
+        for (int j = k; j < end; ++j) v += Vo[j];
+        if (k + K >= T) v += cT;
+        Vo[k] = v;
+      }
+    }
+    for (int k = T + 1; k <= Tmax; ++k) Vo[k] = 0.0;
+  }
+  if (Lo)
+    for (int idx = (T + 1) * N + tid; idx < (Tmax + 1) * N; idx += NT) Lo[idx] = 0.0;
+}
+
+template <class R>
+struct QuadLaunch {
+  static size_t ws_bytes(int Bcap, int Tcap) { return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total; }
+
+  static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
+                         int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
+                         int max_iter, double* trace, hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,
+                       x0, U0, max_iter, trace);
+    return hipGetLastError();
+  }
+
+  static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                            const int32_t* slots, const SolveParamsH& sp, int G, int, double* trace,
+                            hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    hipLaunchKernelGGL(quad_iterate<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, to_dev(sp), G,
+                       trace);
+    return hipGetLastError();
+  }
+
+  static hipError_t finalize(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                             const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
+                             hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
+    hipLaunchKernelGGL(quad_final<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, max_iter,
+                       lookahead, fo);
+    return hipGetLastError();
+  }
+
+  static const Launcher* get() {
+    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_GROUP, &ws_bytes, &init, &iterate, &finalize};
+    return &L;
+  }
+};
+
+}  // namespace quad
+
+const Launcher* launcher_quad(int precision) {
+  return precision ? quad::QuadLaunch<float>::get() : quad::QuadLaunch<double>::get();
+}
 
 }  // namespace cbic

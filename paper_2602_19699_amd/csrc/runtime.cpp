@@ -179,7 +179,16 @@ bool make_device_block(cbic_system* s, double eps) {
       return true;
     }
     case CBIC_SYS_QUAD_SYNTH: {
-      d = p;  // the quadruped kernels read the user layout directly
+      // same layout as the user's vector with A replaced by the constant part
+      // of the mass matrix, A^T A
+      d = p;
+      const double* A = p.data() + 5;
+      for (int a = 0; a < 18; ++a)
+        for (int b = 0; b < 18; ++b) {
+          double v = 0.0;
+          for (int k = 0; k < 18; ++k) v += A[k * 18 + a] * A[k * 18 + b];
+          d[5 + a * 18 + b] = v;
+        }
       return true;
     }
     default:
