@@ -47,6 +47,25 @@ def alg_bytes(work, T, n, m, elem):
     return float(words.sum() * elem)
 
 
+def serving(ctx, rates, seconds):
+    """Open-loop Poisson serving: requests drawn 50/30/20 from the point mass,
+    the arm and the quadruped, horizons uniform on 20..200, FP64 with the
+    relative-decrease stop, 32 GiB admission cap, 4 iterations per launch."""
+    from paper_2602_19699_amd import cbic, loadgen
+    mix = loadgen.Mix(ctx, precision=cbic.FP64, stop_mode=1, rtol=1e-10)
+    srv = cbic.Server(ctx, mem_cap=32 << 30, slots_per_class=4096, t_max=200, iters_per_launch=4)
+    loadgen.run_poisson(srv, mix, rate=1000.0, n=200, seed=1)  # warm-up: pools, code objects
+    out = {"workload": "Poisson arrivals, mix 50/30/20 point mass / arm / quadruped, T~U{20..200}, FP64 "
+                       "tolerance stop 1e-10, cap 32 GiB, G=4 iterations per launch", "rates": []}
+    for i, rate in enumerate(rates):
+        n = int(rate * seconds)
+        st, _, _ = loadgen.run_poisson(srv, mix, rate=float(rate), n=n, seed=100 + i)
+        out["rates"].append({k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()})
+    out["server_stats"] = srv.stats()
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +74,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only", default=None, help="time only this form (for profiler runs)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-sweep", action="store_true",
+                    help="only the serving workload: Poisson rates 1k..50k/s, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the instances are independent and a "
@@ -67,6 +89,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = cbic.Context(0)
+    if args.serving_sweep:
+        print(json.dumps(serving(ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=2.0)))
+        return
     kind, params, x0, T, _ = I.workload("pm16k")
     B = len(x0)
     sysm = cbic.System(ctx, kind, params)
@@ -149,6 +174,9 @@ def main():
                          f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed 50 iterations'}, "
                          f"{threads} OpenMP threads, {dt:.2f} s"}
 
+ 
+    serve = None if (args.no_serving or args.only) else serving(ctx, rates=(2000, 10000), seconds=1.5)
+
     line = {
         "metric": "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latency",
         "value": round(h["converged_solves_per_s"], 1),
@@ -169,6 +197,7 @@ def main():
                   for k, v in results.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(line))
 

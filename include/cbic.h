@@ -252,6 +252,17 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
 /* CBIC_OK with *out filled once the ticket is done (the ticket is then
  * released), CBIC_NOT_READY while pending, CBIC_E_INVALID for an unknown ticket. */
 cbic_status cbic_server_poll(cbic_server* srv, uint64_t ticket, cbic_result* out);
+/* Counters of a server (host-side bookkeeping; no device work). */
+typedef struct {
+  uint64_t submitted, completed, rounds;
+  size_t inflight_bytes;      /* footprint of the requests resident now          */
+  size_t peak_inflight_bytes; /* largest footprint resident at once so far        */
+  size_t pool_bytes;          /* device memory held by the slot pools             */
+  int32_t classes;            /* (system, precision) pools created                */
+  int32_t max_resident;       /* most requests resident at once                   */
+} cbic_server_stats;
+cbic_status cbic_server_get_stats(cbic_server* srv, cbic_server_stats* out);
+
 /* Server clock in seconds (the time base of cbic_result's t_* fields). */
 double cbic_server_clock(const cbic_server* srv);
 /* Block until every submitted request is done. */

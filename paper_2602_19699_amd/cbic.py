@@ -55,6 +55,12 @@ class _Result(C.Structure):
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
+class _ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rounds", C.c_uint64),
+                ("inflight_bytes", C.c_size_t), ("peak_inflight_bytes", C.c_size_t), ("pool_bytes", C.c_size_t),
+                ("classes", C.c_int32), ("max_resident", C.c_int32)]
+
+
 _lib = None
 
 # every entry point of include/cbic.h with its ctypes signature
@@ -79,6 +85,7 @@ _SIGS = {
                                        C.c_void_p, C.c_void_p]),
     "cbic_server_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.c_void_p]),
     "cbic_server_clock": (C.c_double, [C.c_void_p]),
+    "cbic_server_get_stats": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "cbic_server_drain": (C.c_int32, [C.c_void_p]),
     "cbic_server_destroy": (C.c_int32, [C.c_void_p]),
 }
@@ -308,6 +315,11 @@ class Server:
 
     def clock(self) -> float:
         return lib().cbic_server_clock(self.h)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().cbic_server_get_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServerStats._fields_}
 
     def drain(self):
         _check(lib().cbic_server_drain(self.h))

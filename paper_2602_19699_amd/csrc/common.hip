@@ -55,6 +55,31 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+// dst[i] = src[idx[i]]  (status words of a slot list, for the serving loop)
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const int32_t* __restrict__ idx, int n,
+                             uint32_t* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// inst[slots[i]] = i: finished slots write their outputs to compact rows 0..n-1
+__global__ void k_set_index(const int32_t* __restrict__ slots, int n, int32_t* __restrict__ inst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) inst[slots[i]] = i;
+}
+
+hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int n, uint32_t* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_u32, dim3((n + 255) / 256), dim3(256), 0, st, src, idx, n, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_index(const int32_t* slots, int n, int32_t* inst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_index, dim3((n + 255) / 256), dim3(256), 0, st, slots, n, inst);
+  return hipGetLastError();
+}
+
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st) {
   const int nb = Tmax + 1;
   const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;

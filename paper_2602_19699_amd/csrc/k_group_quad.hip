@@ -56,6 +56,7 @@ struct Smem {
   R Qu[16], kk[16], lu[16];
   double Quu[M][M + 1];
   double Lq[M][M + 1];
+  double Yq[M][N + 1];  // [K k] solves
   double wJ[NW];
   int wok[NW];
   int flag;
@@ -77,7 +78,7 @@ __device__ __forceinline__ R wave_sum(R v) {
 
 // ------------------------------------------------------------------ constants
 template <class R>
-__device__ void stage_constants(Smem<R>& sm, const double* __restrict__ prm, int tid) {
+__device__ __forceinline__ void stage_constants(Smem<R>& sm, const double* __restrict__ prm, int tid) {
   for (int i = tid; i < NV * NV; i += NT) {
     const int r = i / NV, c = i % NV;
     sm.M0[r][c] = R(prm[O_M0 + i]);
@@ -92,7 +93,7 @@ __device__ void stage_constants(Smem<R>& sm, const double* __restrict__ prm, int
 // One semi-implicit Euler step for wave scratch ws: reads ws.x and ws.u,
 // writes ws.xn; leaves L (factor of M), a, sin/cos and W2 cos q in ws.
 template <class R>
-__device__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) {
+__device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) {
   if (lane < NV) {
     R sn, cs;
     dsincos(ws.x[lane], &sn, &cs);
@@ -102,35 +103,29 @@ __device__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) 
   wave_sync();
   const bool row = lane < NV;
   const int ri = row ? lane : 0;
-  R m[NV];
-#pragma unroll
-  for (int j = 0; j < NV; ++j) m[j] = row ? sm.M0[ri][j] : R(0);
-#pragma unroll
-  for (int j = 0; j < NV; ++j)
-    if (j == lane) m[j] += R(1) + R(0.1) * ws.s[ri];
-  // Cholesky, rows on lanes
-#pragma unroll
-  for (int j = 0; j < NV; ++j) {
-    const R piv = __shfl(m[j], j, 64);
-    const R ljj = dsqrt(piv);
-    const R inv = R(1) / ljj;
-    const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
-    m[j] = lij;
-#pragma unroll
-    for (int k = j + 1; k < NV; ++k) {
-      const R lkj = __shfl(lij, k, 64);
-      m[k] -= lij * lkj;
-    }
+  // M = A^T A + diag(1 + 0.1 sin q) into L (rows on lanes), then an in-place
+  // right-looking Cholesky with the matrix in LDS (few live registers)
+  if (row) {
+    for (int j = 0; j <= ri; ++j) ws.L[ri][j] = sm.M0[ri][j];
+    ws.L[ri][ri] += R(1) + R(0.1) * ws.s[ri];
   }
-  if (row)
-#pragma unroll
-    for (int j = 0; j < NV; ++j)
-      if (j <= lane) ws.L[ri][j] = m[j];
+  wave_sync();
+  for (int j = 0; j < NV; ++j) {
+    const R ljj = dsqrt(ws.L[j][j]);
+    wave_sync();
+    if (row && ri >= j) ws.L[ri][j] = (ri == j) ? ljj : ws.L[ri][j] / ljj;
+    wave_sync();
+    if (row && ri > j) {
+      const R lij = ws.L[ri][j];
+      for (int k = j + 1; k <= ri; ++k) ws.L[ri][k] -= lij * ws.L[k][j];
+    }
+    wave_sync();
+  }
   // bias forces and right-hand side r = S u - b
   R y = R(0);
   if (row) {
     R b1 = R(0), b2 = R(0);
-#pragma unroll
+#pragma unroll 3
     for (int j = 0; j < NV; ++j) {
       b1 += sm.W1[ri][j] * ws.s[j];
       b2 += sm.W2[ri][j] * ws.c[j];
@@ -139,20 +134,15 @@ __device__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) 
     const R b = b1 + b2 * ws.x[NQ + ri];
     y = (ri >= 6 ? ws.u[ri - 6] : R(0)) - b;
   }
-  wave_sync();
-  // L z = r (rows on lanes)
-#pragma unroll
+  const R lii = row ? ws.L[ri][ri] : R(1);
+  // L z = r and L^T a = z (rows on lanes, the solved entry broadcast by a shuffle)
   for (int j = 0; j < NV; ++j) {
-    const R t = y / m[j];
-    const R yj = __shfl(t, j, 64);
+    const R yj = __shfl(y / lii, j, 64);
     if (lane == j) y = yj;
-    else if (lane > j) y -= m[j] * yj;
+    else if (row && lane > j) y -= ws.L[ri][j] * yj;
   }
-  // L^T a = z
-#pragma unroll
   for (int j = NV - 1; j >= 0; --j) {
-    const R t = y / m[j];
-    const R zj = __shfl(t, j, 64);
+    const R zj = __shfl(y / lii, j, 64);
     if (lane == j) y = zj;
     else if (lane < j) y -= ws.L[j][ri] * zj;
   }
@@ -171,7 +161,7 @@ __device__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) 
 
 // running cost l(x, u) of the wave's (x, u); the same value in every lane
 template <class R>
-__device__ R wave_cost(const Smem<R>& sm, const R* x, const R* u, const double* __restrict__ prm, int lane,
+__device__ __forceinline__ R wave_cost(const Smem<R>& sm, const R* x, const R* u, const double* __restrict__ prm, int lane,
                        bool terminal) {
   R v = R(0);
   if (lane < N) {
@@ -201,6 +191,7 @@ __device__ __forceinline__ void blk_gemm(R* C, int ldc, const R* A, int lda, con
       const int i = tr + 16 * a, j = tc + 16 * b;
       acc[a][b] = (Cin && i < Mr && j < Nc) ? Cin[i * ldcin + j] : R(0);
     }
+#pragma unroll 2
   for (int k = 0; k < Kd; ++k) {
     R av[RT], bv[CT];
 #pragma unroll
@@ -231,10 +222,11 @@ __device__ __forceinline__ void blk_gemm(R* C, int ldc, const R* A, int lda, con
 // f_x into sm.A and f_u into sm.Bm at (wv[0].x, wv[0].u); wave 0 must have run
 // wave_dyn on that point (L, a, sin/cos, W2 cos q in wv[0]).  All threads.
 template <class R>
-__device__ void jacobians(Smem<R>& sm, R dt, int tid) {
+__device__ __forceinline__ void jacobians(Smem<R>& sm, R dt, int tid) {
   const WaveScratch<R>& ws = sm.wv[0];
   R* Z = &sm.PA[0][0];  // 18 x 48 right-hand sides, row stride 48
   // RHS columns: 0..17 -dD/dq (a and v held), 18..35 -dD/dv, 36..47 S
+#pragma unroll 1
   for (int idx = tid; idx < NV * 48; idx += NT) {
     const int i = idx / 48, col = idx % 48;
     R v;
@@ -250,29 +242,22 @@ __device__ void jacobians(Smem<R>& sm, R dt, int tid) {
     Z[i * 48 + col] = v;
   }
   __syncthreads();
-  if (tid < 48) {  // column solves with L L^T
-    R y[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) y[i] = Z[i * 48 + tid];
-#pragma unroll
+  if (tid < 48) {  // column solves with L L^T, in place in LDS
+    R* zc = Z + tid;
     for (int i = 0; i < NV; ++i) {
-      R v = y[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= ws.L[i][k] * y[k];
-      y[i] = v / ws.L[i][i];
+      R v = zc[i * 48];
+      for (int k = 0; k < i; ++k) v -= ws.L[i][k] * zc[k * 48];
+      zc[i * 48] = v / ws.L[i][i];
     }
-#pragma unroll
     for (int i = NV - 1; i >= 0; --i) {
-      R v = y[i];
-#pragma unroll
-      for (int k = i + 1; k < NV; ++k) v -= ws.L[k][i] * y[k];
-      y[i] = v / ws.L[i][i];
+      R v = zc[i * 48];
+      for (int k = i + 1; k < NV; ++k) v -= ws.L[k][i] * zc[k * 48];
+      zc[i * 48] = v / ws.L[i][i];
     }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) Z[i * 48 + tid] = y[i];
   }
   __syncthreads();
   // d v+/d x and d v+/d u, then q rows: q+ = q + dt E v+
+#pragma unroll 1
   for (int idx = tid; idx < N * (N + M); idx += NT) {
     const int r = idx / (N + M), col = idx % (N + M);
     auto dv = [&](int i) -> R {  // d v+_i / d (x, u)_col
@@ -287,7 +272,7 @@ __device__ void jacobians(Smem<R>& sm, R dt, int tid) {
     else if (r < NV) v = id + dt * dv(r);
     else {
       R s = R(0);
-#pragma unroll
+#pragma unroll 2
       for (int i = 0; i < NV; ++i) s += sm.e[i] * dv(i);
       v = id + dt * s;
     }
@@ -300,7 +285,7 @@ __device__ void jacobians(Smem<R>& sm, R dt, int tid) {
 // ------------------------------------------------------------------ FP64 Cholesky of Q_uu and the gains
 // Wave 0 factors Quu (rows on lanes); threads 0..37 solve for [K k].
 template <class R>
-__device__ bool gains(Smem<R>& sm, int tid) {
+__device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
   if (tid < 64) {
     const int lane = tid;
     const bool row = lane < M;
@@ -327,33 +312,25 @@ __device__ bool gains(Smem<R>& sm, int tid) {
   }
   __syncthreads();
   if (sm.flag) return false;
-  if (tid <= N) {  // column tid of [Q_ux | Q_u]
-    double y[M];
-#pragma unroll
-    for (int i = 0; i < M; ++i) y[i] = double(tid < N ? sm.Qux[i][tid] : sm.Qu[i]);
-#pragma unroll
+  if (tid <= N) {  // column tid of [Q_ux | Q_u], solved in place in LDS
+    double* yc = &sm.Yq[0][tid];
+    for (int i = 0; i < M; ++i) yc[i * (N + 1)] = double(tid < N ? sm.Qux[i][tid] : sm.Qu[i]);
     for (int i = 0; i < M; ++i) {
-      double v = y[i];
-#pragma unroll
-      for (int k = 0; k < i; ++k) v -= sm.Lq[i][k] * y[k];
-      y[i] = v / sm.Lq[i][i];
-    }
-#pragma unroll
-    for (int i = M - 1; i >= 0; --i) {
-      double v = y[i];
-#pragma unroll
-      for (int k = i + 1; k < M; ++k) v -= sm.Lq[k][i] * y[k];
-      y[i] = v / sm.Lq[i][i];
+      double v = yc[i * (N + 1)];
+      for (int k = 0; k < i; ++k) v -= sm.Lq[i][k] * yc[k * (N + 1)];
+      yc[i * (N + 1)] = v / sm.Lq[i][i];
     }
     bool fin = true;
-#pragma unroll
-    for (int i = 0; i < M; ++i) fin = fin && isfinite(y[i]);
-    if (!fin) sm.flag = 2;
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
-      if (tid < N) sm.Kg[i][tid] = R(-y[i]);
-      else sm.kk[i] = R(-y[i]);
+    for (int i = M - 1; i >= 0; --i) {
+      double v = yc[i * (N + 1)];
+      for (int k = i + 1; k < M; ++k) v -= sm.Lq[k][i] * yc[k * (N + 1)];
+      v /= sm.Lq[i][i];
+      yc[i * (N + 1)] = v;
+      fin = fin && isfinite(v);
+      if (tid < N) sm.Kg[i][tid] = R(-v);
+      else sm.kk[i] = R(-v);
     }
+    if (!fin) sm.flag = 2;
   }
   __syncthreads();
   return sm.flag == 0;
@@ -377,7 +354,7 @@ struct QW {  // workspace accessors (same layout as the lane schedule)
 
 // ------------------------------------------------------------------ backward sweep
 template <class R>
-__device__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
+__device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
                              int buf, R eps, int tid) {
   using Q = QW<R>;
   const R dt = R(prm[O_DT]);
@@ -462,7 +439,7 @@ __device__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const 
 // Closed-loop rollout of wave `wid` with step alpha; writes the trajectory
 // when `write`; early stop once the partial cost reaches Jcur (costs >= 0).
 template <class R>
-__device__ double wave_trial(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
+__device__ __forceinline__ double wave_trial(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
                              int buf, R alpha, double Jcur, bool write, int lane, int wid, int& steps) {
   using Q = QW<R>;
   WaveScratch<R>& ws = sm.wv[wid];
@@ -570,7 +547,7 @@ __global__ void __launch_bounds__(NT) quad_init(const double* __restrict__ prm, 
 }
 
 template <class R>
-__global__ void __launch_bounds__(NT) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
+__global__ void __launch_bounds__(NT, 1) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                     const int32_t* __restrict__ slots, SolveParams sp,
                                                     int iters_this_launch, double* __restrict__ trace) {
   __shared__ Smem<R> sm;
@@ -600,22 +577,36 @@ __global__ void __launch_bounds__(NT) quad_iterate(const double* __restrict__ pr
       st = bad;
       break;
     }
+    // line search: rounds of NW parallel trials, then (if the accepted step
+    // is not alpha = 1, which wave 0 wrote while trying it) one commit rollout;
+    // a single call site keeps the kernel's register footprint down
     int acc = -1;
     double Jn = J;
-    for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += NW) {
-      const int j = j0 + wid;
+    bool commit = false;
+    for (int j0 = 0;;) {
+      const int j = commit ? acc : j0 + wid;
+      const bool run = commit ? (wid == 0) : (j < sp.ls_trials);
       double Jh = __builtin_nan("");
       int steps = 0;
-      if (j < sp.ls_trials) {
+      if (run) {
         double alpha = 1.0;
         for (int q = 0; q < j; ++q) alpha *= sp.beta;
-        Jh = wave_trial(sm, prm, w, s, T, buf, R(alpha), J, j == 0, lane, wid, steps);
+        Jh = wave_trial(sm, prm, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, commit || j == 0, lane,
+                        wid, steps);
       }
       if (lane == 0) {
         sm.wJ[wid] = Jh;
         sm.wok[wid] = steps;
       }
       __syncthreads();
+      ++npass;
+      if (commit) {
+        Jn = sm.wJ[0];
+        nread += T;
+        nwrite += T;
+        __syncthreads();
+        break;
+      }
       int longest = 0;
       for (int q = 0; q < NW; ++q) {
         longest = max(longest, sm.wok[q]);
@@ -627,27 +618,14 @@ __global__ void __launch_bounds__(NT) quad_iterate(const double* __restrict__ pr
       }
       if (j0 == 0) nwrite += sm.wok[0];
       nread += longest;
-      ++npass;
       __syncthreads();
+      j0 += NW;
+      if (acc == 0 || (acc < 0 && j0 >= sp.ls_trials)) break;
+      if (acc > 0) commit = true;
     }
     if (acc < 0) {
       st = ST_LS_FAILED;
       break;
-    }
-    if (acc > 0) {
-      double alpha = 1.0;
-      for (int q = 0; q < acc; ++q) alpha *= sp.beta;
-      int steps = 0;
-      if (wid == 0) {
-        const double Jc = wave_trial(sm, prm, w, s, T, buf, R(alpha), __builtin_inf(), true, lane, 0, steps);
-        if (lane == 0) sm.wJ[0] = Jc;
-      }
-      __syncthreads();
-      Jn = sm.wJ[0];
-      ++npass;
-      nread += T;
-      nwrite += T;
-      __syncthreads();
     }
     buf ^= 1;
     const double Jold = J;
@@ -673,7 +651,7 @@ __global__ void __launch_bounds__(NT) quad_iterate(const double* __restrict__ pr
 }
 
 template <class R>
-__global__ void __launch_bounds__(NT) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
+__global__ void __launch_bounds__(NT, 1) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                   const int32_t* __restrict__ slots, int Tmax, int max_iter,
                                                   int lookahead, FinalOut o) {
   using Q = QW<R>;
