@@ -1,20 +1,22 @@
 """Benchmark: converged TO solves per second on one MI355X.
 
-Workload (one "step"): one batched solve of the 2-D point-mass OCP with 16384
-initial states, horizon 100, dt 0.01, three soft obstacles (seeded), through
-the C ABI, with inputs already resident in device memory.  Several forms of
-the solver are timed: plain FP64 with the fixed 50-iteration budget, plain
-FP64 with the relative-decrease stop, and the mixed FP32/FP64 form with the
+Headline workload (one "step"): one batched solve of the 2-D point-mass OCP with
+16384 initial states, horizon 100, dt 0.01, three soft obstacles (seeded),
+through the C ABI, inputs already resident in device memory.  Forms timed:
+plain FP64 with the fixed 50-iteration budget, plain FP64 with the
+relative-decrease stop, and the mixed FP32/FP64 form with the
 relative-decrease stop.  A solve counts as converged when its cost is within
 1e-4 relative of the plain FP64 fixed-budget GPU solve of the same instance;
 `value` is the converged solves per second of the fastest form.
 
-The JSON line also carries the roofline of the dominant kernel (the
-iteration kernel; HIP events on its stream, algorithmic bytes from the
-per-instance work counters) and the FP64 CPU oracle timed on a bounded sample
-on this host.
+The same run measures the other workloads (64 point-mass instances for
+latency, 4096 arm instances with horizons 50..200, 1024 quadruped-sized
+instances) and the serving loop, each with the roofline of its dominant
+kernel (HIP events around the iteration kernel on its stream; algorithmic
+bytes or flops from the per-instance work counters) and the FP64 CPU oracle
+timed on a bounded sample on this host.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
 from __future__ import annotations
 
@@ -30,21 +32,126 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "point-mass OCP (n=4, m=2), B=16384 initial states, T=100, dt=0.01, 3 soft obstacles"
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latency"
 
 
-def alg_bytes(work, T, n, m, elem):
-    """Algorithmic HBM bytes of the iteration kernel for the instances' work
+def riccati_flops(n, m):
+    """Dense, symmetry-unaware flop count of one backward Riccati step."""
+    return 4 * n ** 3 + 6 * n * n * m + 2 * m * m * n + 2 * m * m * (n + 1) + m ** 3 / 3 + 2 * n * n + 4 * n * m
+
+
+def alg_bytes(work, Tb, n, m, elem):
+    """Algorithmic HBM bytes of the iteration kernel from the instances' work
     counters: a backward sweep reads x_T and, per step, x_k, u_k and writes
     K_k (m x n), k_k (m); a line-search rollout step reads x_k, u_k, K_k, k_k
     and, when it writes, stores x_{k+1} and u_k."""
     work = work.astype(np.float64)
     sweeps, reads, writes = work[:, 0], work[:, 2], work[:, 3]
-    per_bwd_step = n + m + m * n + m
-    per_read = n + m + m * n + m
-    per_write = n + m
-    words = sweeps * (T * per_bwd_step + n) + reads * per_read + writes * per_write
+    per_step = n + m + m * n + m
+    words = sweeps * (Tb * per_step + n) + reads * per_step + writes * (n + m)
     return float(words.sum() * elem)
+
+
+def alg_flops(work, Tb, n, m):
+    """Algorithmic flops of the backward sweeps (dense Riccati count per step)."""
+    return float((work[:, 0].astype(np.float64) * Tb).sum() * riccati_flops(n, m))
+
+
+def time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup, autotune=True):
+    import torch
+    from paper_2602_19699_amd import cbic
+    dev = x0d.device
+    B = x0d.shape[0]
+    out = cbic.Outputs.allocate(B, T, sysm.n, sysm.m, dev, targets=True)
+    width = None
+    if autotune and sysm.kind != 3:  # the quadruped has one schedule (a workgroup per instance)
+        width, _ = cbic.autotune(ctx, sysm, x0d, T, T=Td, opts=opts)
+    for _ in range(warmup):
+        cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=opts, out=out)
+    torch.cuda.synchronize(dev)
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=opts, out=out)
+        e1.record(stream)
+    torch.cuda.synchronize(dev)
+    wall = (time.perf_counter() - t0) / steps
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    topts = cbic.Options(**{**opts.__dict__, "flags": opts.flags | cbic.FLAG_TIMING})
+    cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=topts, out=out)
+    ph = ctx.phase_times()
+    torch.cuda.synchronize(dev)
+    return out, wall * 1e3, lat, ph, width
+
+
+def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, quick=False):
+    import torch
+    from paper_2602_19699_amd import cbic, inputs as I
+    dev = torch.device("cuda", 0)
+    kind, params, x0, T, Tb = I.workload(name)
+    B = len(x0)
+    sysm = cbic.System(ctx, kind, params)
+    x0d = torch.as_tensor(x0, device=dev)
+    Td = None if Tb is None else torch.as_tensor(Tb, device=dev)
+    Tvec = np.full(B, T) if Tb is None else Tb.astype(np.int64)
+    ref = cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=cbic.Options(max_iter=50), targets=False)
+    torch.cuda.synchronize(dev)
+    Jref = ref.J.cpu().numpy()
+    n, m = sysm.n, sysm.m
+    results = {}
+    for fname, opts in forms.items():
+        out, ms, lat, ph, width = time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup)
+        J = out.J.cpu().numpy()
+        work = out.work.cpu().numpy()
+        rel = np.abs(J - Jref) / np.abs(Jref)
+        conv = int(np.sum(rel <= 1e-4))
+        elem = 8 if opts.precision == cbic.FP64 else 4
+        nb = alg_bytes(work, Tvec, n, m, elem)
+        nf = alg_flops(work, Tvec, n, m)
+        results[fname] = dict(
+            ms_per_step=ms, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+            converged=conv, converged_frac=conv / B, solves_per_s=B / (ms / 1e3),
+            converged_solves_per_s=conv / (ms / 1e3), max_rel_cost_vs_fp64=float(np.nanmax(rel)),
+            iterate_ms=ph[1], init_ms=ph[0], final_ms=ph[2], iterate_alg_bytes=nb,
+            iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
+            iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
+            mean_sweeps=float(work[:, 0].mean()), lanes_per_instance=width)
+    best = max(results, key=lambda k: results[k]["converged_solves_per_s"])
+    cpu = None
+    if cpu_sample and not quick:
+        from oracle import oracle as orc
+        ns = min(cpu_sample, B)
+        threads = orc.max_threads()
+        fo = forms[cpu_opts_form]
+        oo = orc.Options(max_iter=fo.max_iter, stop_mode=fo.stop_mode, rtol=max(fo.rtol, 1e-10))
+        t0 = time.perf_counter()
+        orc.solve_batch(kind, params, x0[:ns], T, T=None if Tb is None else Tb[:ns], opts=oo, nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": round(ns / dt, 2), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"{'all' if ns == B else 'first %d of the' % ns} {B} instances, FP64, "
+                         f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed %d iterations' % oo.max_iter}"
+                         f", {threads} OpenMP threads, {dt:.2f} s"}
+    sysm.close()
+    return results, best, cpu
+
+
+def roofline_for(name, res, form_opts):
+    if name == "quad1k":
+        peak = FP64_PEAK_TFLOPS if form_opts.precision == 0 else FP32_PEAK_TFLOPS
+        return {"bound": "alu", "achieved": round(res["iterate_TFLOPs"], 4), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(res["iterate_TFLOPs"] / peak, 5), "traffic": None,
+                "kernel": f"quad_iterate<{'double' if form_opts.precision == 0 else 'float'}>",
+                "alg_flops_per_launch": res["iterate_alg_flops"], "iterate_ms": round(res["iterate_ms"], 4)}
+    sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
+    return {"bound": "hbm", "achieved": round(res["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": None,
+            "kernel": f"lane_iterate<{sysname},{'double' if form_opts.precision == 0 else 'float'},"
+                      f"{res['lanes_per_instance']}>",
+            "alg_bytes_per_launch": res["iterate_alg_bytes"], "iterate_ms": round(res["iterate_ms"], 4)}
 
 
 def serving(ctx, rates, seconds):
@@ -56,7 +163,7 @@ def serving(ctx, rates, seconds):
     srv = cbic.Server(ctx, mem_cap=32 << 30, slots_per_class=4096, t_max=200, iters_per_launch=4)
     loadgen.run_poisson(srv, mix, rate=1000.0, n=200, seed=1)  # warm-up: pools, code objects
     out = {"workload": "Poisson arrivals, mix 50/30/20 point mass / arm / quadruped, T~U{20..200}, FP64 "
-                       "tolerance stop 1e-10, cap 32 GiB, G=4 iterations per launch", "rates": []}
+                       "tolerance stop 1e-10, cap 32 GiB, 4 iterations per launch", "rates": []}
     for i, rate in enumerate(rates):
         n = int(rate * seconds)
         st, _, _ = loadgen.run_poisson(srv, mix, rate=float(rate), n=n, seed=100 + i)
@@ -66,15 +173,18 @@ def serving(ctx, rates, seconds):
     return out
 
 
+def fmt(d):
+    return {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in d.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=16384)
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline, no serving")
     ap.add_argument("--only", default=None, help="time only this form (for profiler runs)")
-    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--workload", default=None, help="time only this workload (pm16k, pm64, arm4k, quad1k)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving workload: Poisson rates 1k..50k/s, one JSON line")
     args = ap.parse_args()
@@ -84,119 +194,69 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2602_19699_amd import cbic, inputs as I
+    from paper_2602_19699_amd import cbic
 
-    dev = torch.device("cuda", 0)
     ctx = cbic.Context(0)
     if args.serving_sweep:
         print(json.dumps(serving(ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=2.0)))
         return
-    kind, params, x0, T, _ = I.workload("pm16k")
-    B = len(x0)
-    sysm = cbic.System(ctx, kind, params)
-    x0d = torch.as_tensor(x0, device=dev)
-    stream = torch.cuda.current_stream(dev)
 
-    # reference: plain FP64, fixed 50-iteration budget (untimed)
-    ref_opts = cbic.Options(max_iter=50, precision=cbic.FP64)
-    ref = cbic.solve_batch(ctx, sysm, x0d, T, opts=ref_opts, targets=True)
-    torch.cuda.synchronize(dev)
-    Jref = ref.J.cpu().numpy()
-
+    F = cbic.Options
     forms = {
-        "fp64_fixed50": cbic.Options(max_iter=50, precision=cbic.FP64),
-        "fp64_tol1e-10": cbic.Options(max_iter=50, precision=cbic.FP64, stop_mode=1, rtol=1e-10),
-        "mixed_tol1e-7": cbic.Options(max_iter=50, precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+        "pm16k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
+                  "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+        "pm64": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+        "arm4k": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+        "quad1k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
+                   "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
     }
+    cpu_cfg = {"pm16k": (16384, "fp64_fixed50"), "pm64": (64, "fp64_fixed50"), "arm4k": (512, "fp64_fixed50"),
+               "quad1k": (64, "fp64_tol1e-10")}
+    names = ["pm16k"] if args.quick else ["pm16k", "pm64", "arm4k", "quad1k"]
+    if args.workload:
+        names = [args.workload]
     if args.only:
-        forms = {args.only: forms[args.only]}
-    results = {}
-    for name, opts in forms.items():
-        out = cbic.Outputs.allocate(B, T, 4, 2, dev, targets=True)
-        # set-up (untimed): pick the lanes-per-instance width for this form
-        width, _ = cbic.autotune(ctx, sysm, x0d, T, opts=opts)
-        for _ in range(args.warmup):
-            cbic.solve_batch(ctx, sysm, x0d, T, opts=opts, out=out)
-        torch.cuda.synchronize(dev)
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        t0 = time.perf_counter()
-        for e0, e1 in evs:
-            e0.record(stream)
-            cbic.solve_batch(ctx, sysm, x0d, T, opts=opts, out=out)
-            e1.record(stream)
-        torch.cuda.synchronize(dev)
-        wall = (time.perf_counter() - t0) / args.steps
-        lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
-        # dominant kernel: one more solve with phase events around the iteration kernel
-        topts = cbic.Options(**{**opts.__dict__, "flags": opts.flags | cbic.FLAG_TIMING})
-        cbic.solve_batch(ctx, sysm, x0d, T, opts=topts, out=out)
-        ph = ctx.phase_times()
-        torch.cuda.synchronize(dev)
-        J = out.J.cpu().numpy()
-        work = out.work.cpu().numpy()
-        rel = np.abs(J - Jref) / np.abs(Jref)
-        conv = int(np.sum(rel <= 1e-4))
-        elem = 8 if opts.precision == cbic.FP64 else 4
-        nbytes = alg_bytes(work, T, 4, 2, elem)
-        ms = wall * 1e3
-        results[name] = dict(
-            ms_per_step=ms, ms_wall=wall * 1e3, p50_ms=float(np.percentile(lat, 50)),
-            p99_ms=float(np.percentile(lat, 99)), converged=conv, converged_frac=conv / B,
-            solves_per_s=B / (ms / 1e3), converged_solves_per_s=conv / (ms / 1e3),
-            max_rel_cost_vs_fp64=float(np.nanmax(rel)),
-            iterate_ms=ph[1], init_ms=ph[0], final_ms=ph[2], iterate_bytes=nbytes,
-            iterate_GBps=nbytes / (ph[1] / 1e3) / 1e9,
-            mean_iters=float(out.iters.float().mean().item()), lanes_per_instance=width)
-
-    head_name = max(results, key=lambda k: results[k]["converged_solves_per_s"])
-    h = results[head_name]
-    head_opts = forms[head_name]
-
-    roofline = {"bound": "hbm", "achieved": round(h["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(h["iterate_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"lane_iterate<PointMass,{'double' if head_opts.precision == 0 else 'float'},"
-                          f"{h['lanes_per_instance']}>",
-                "iterate_ms": round(h["iterate_ms"], 4), "alg_bytes_per_launch": h["iterate_bytes"]}
-
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as orc
-        ns = min(args.cpu_sample, B)
-        threads = orc.max_threads()
-        oo = orc.Options(max_iter=50, stop_mode=head_opts.stop_mode, rtol=max(head_opts.rtol, 1e-10))
-        t0 = time.perf_counter()
-        r = orc.solve_batch(kind, params, x0[:ns], T, opts=oo, nthreads=threads)
-        dt = time.perf_counter() - t0
-        cpu = {"value": round(ns / dt, 1), "unit": "solves/s", "cores": threads, "kind": "oracle",
-               "sample": f"{'all' if ns == B else 'first %d of the' % ns} {B} instances, FP64, "
-                         f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed 50 iterations'}, "
-                         f"{threads} OpenMP threads, {dt:.2f} s"}
-
- 
-    serve = None if (args.no_serving or args.only) else serving(ctx, rates=(2000, 10000), seconds=1.5)
-
+        for nme in names:
+            forms[nme] = {args.only: forms[nme][args.only]}
+    other = {}
+    head = None
+    for nme in names:
+        steps = args.steps if nme in ("pm16k", "pm64") else max(3, args.steps // 4)
+        res, best, cpu = workload_bench(ctx, nme, forms[nme], steps, args.warmup, cpu_cfg[nme][0],
+                                        cpu_cfg[nme][1], quick=args.quick or bool(args.only))
+        entry = {"best_form": best, "forms": {k: fmt(v) for k, v in res.items()},
+                 "roofline": roofline_for(nme, res[best], forms[nme][best]), "cpu_baseline": cpu,
+                 "steps": steps}
+        if head is None:
+            head = (nme, res, best, entry)
+        else:
+            other[nme] = entry
+    nme, res, best, entry = head
+    h = res[best]
+    wl = {"pm16k": "point-mass OCP (n=4, m=2), B=16384 initial states, T=100, dt=0.01, 3 soft obstacles",
+          "pm64": "point-mass OCP (n=4, m=2), B=64, T=100",
+          "arm4k": "planar 3-link arm (n=6, m=3), B=4096, T uniform 50..200",
+          "quad1k": "quadruped-sized system (n=37, m=12), B=1024, T=100"}[nme]
+    serve = None if (args.quick or args.only or args.workload) else serving(ctx, rates=(2000, 10000), seconds=1.5)
     line = {
-        "metric": "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latency",
+        "metric": METRIC,
         "value": round(h["converged_solves_per_s"], 1),
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": entry["steps"],
         "warmup": args.warmup,
         "ms_per_step": round(h["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head_opts.precision == 0 else "f32+f64",
-        "data": "synthetic (seeded point-mass parameters and initial states)",
-        "config": {"workload": WORKLOAD, "form": head_name, "batch": B, "horizon": T,
-                   "p50_ms": round(h["p50_ms"], 4), "p99_ms": round(h["p99_ms"], 4),
+        "dtype": "f64" if forms[nme][best].precision == 0 else "f32+f64",
+        "data": "synthetic (seeded system parameters and initial states)",
+        "config": {"workload": wl, "form": best, "p50_ms": round(h["p50_ms"], 4), "p99_ms": round(h["p99_ms"], 4),
                    "converged_frac": round(h["converged_frac"], 5)},
-        "forms": {k: {kk: (float(f"{vv:.6g}") if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                  for k, v in results.items()},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
+        "forms": entry["forms"],
+        "roofline": entry["roofline"],
+        "cpu_baseline": entry["cpu_baseline"],
+        "workloads": other,
         "serving": serve,
     }
     print(json.dumps(line))

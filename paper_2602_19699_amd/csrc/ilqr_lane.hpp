@@ -93,19 +93,29 @@ struct Lane {
       mdl.term_derivs(xT, p, P, eps, true);
     }
     uint32_t bad = 0;
-    // software prefetch of the next step's (x, u)
-    R xn[N], un[M];
+    // software prefetch of the next two steps' (x, u)
+    R xn[N], un[M], xn2[N], un2[M];
     ld(xn, xp(w, buf, T - 1, s));
     ld(un, up(w, buf, T - 1, s));
+    if (T > 1) {
+      ld(xn2, xp(w, buf, T - 2, s));
+      ld(un2, up(w, buf, T - 2, s));
+    }
     for (int k = T - 1; k >= 0; --k) {
       R x[N], u[M];
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = xn[i];
+      for (int i = 0; i < N; ++i) {
+        x[i] = xn[i];
+        xn[i] = xn2[i];
+      }
 #pragma unroll
-      for (int i = 0; i < M; ++i) u[i] = un[i];
-      if (k > 0) {
-        ld(xn, xp(w, buf, k - 1, s));
-        ld(un, up(w, buf, k - 1, s));
+      for (int i = 0; i < M; ++i) {
+        u[i] = un[i];
+        un[i] = un2[i];
+      }
+      if (k > 1) {
+        ld(xn2, xp(w, buf, k - 2, s));
+        ld(un2, up(w, buf, k - 2, s));
       }
       R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
       mdl.jac(x, u, A, B);
@@ -245,59 +255,59 @@ struct Lane {
   // accept/reject decision is unchanged.
   __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R alpha,
                                  double Jcur, bool write, int& steps) {
+    // step data (x_k, u_k, K_k, k_k) streams through a ring of PF register
+    // sets, PF steps ahead of the step being computed
+    constexpr int PF = Sys::N * (Sys::M + 2) <= 16 ? 2 : 2;
     const int nb = buf ^ 1;
     R xh[N];
     ld(xh, xp(w, buf, 0, s));
     double Jh = 0.0;
-    R xa[N], ua[M], Ka[M * N], ka[M];
-    ld(xa, xp(w, buf, 0, s));
-    ld(ua, up(w, buf, 0, s));
-    ld(Ka, Kp(w, 0, s));
-    ld(ka, kp(w, 0, s));
-    bool cut = false;
-    for (int k = 0; k < T; ++k) {
-      R x[N], u[M], Kk[M * N], kk[M];
+    R rx[PF][N], ru[PF][M], rK[PF][M * N], rk[PF][M];
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = xa[i];
-#pragma unroll
-      for (int i = 0; i < M; ++i) u[i] = ua[i];
-#pragma unroll
-      for (int i = 0; i < M * N; ++i) Kk[i] = Ka[i];
-#pragma unroll
-      for (int i = 0; i < M; ++i) kk[i] = ka[i];
-      if (k + 1 < T) {
-        ld(xa, xp(w, buf, k + 1, s));
-        ld(ua, up(w, buf, k + 1, s));
-        ld(Ka, Kp(w, k + 1, s));
-        ld(ka, kp(w, k + 1, s));
+    for (int r = 0; r < PF; ++r)
+      if (r < T) {
+        ld(rx[r], xp(w, buf, r, s));
+        ld(ru[r], up(w, buf, r, s));
+        ld(rK[r], Kp(w, r, s));
+        ld(rk[r], kp(w, r, s));
       }
-      R dx[N], uh[M];
+    steps = T;
+    for (int k0 = 0; k0 < T; k0 += PF) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) dx[i] = xh[i] - x[i];
+      for (int r = 0; r < PF; ++r) {
+        const int k = k0 + r;
+        if (k >= T) break;
+        R dx[N], uh[M];
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        R v = u[i] + alpha * kk[i];
+        for (int i = 0; i < N; ++i) dx[i] = xh[i] - rx[r][i];
 #pragma unroll
-        for (int j = 0; j < N; ++j) v += Kk[i * N + j] * dx[j];
-        uh[i] = v;
-      }
-      Jh += double(mdl.cost(xh, uh));
-      R xn[N];
-      mdl.dyn(xh, uh, xn);
+        for (int i = 0; i < M; ++i) {
+          R v = ru[r][i] + alpha * rk[r][i];
 #pragma unroll
-      for (int i = 0; i < N; ++i) xh[i] = xn[i];
-      if (write) {
-        st(up(w, nb, k, s), uh);
-        st(xp(w, nb, k + 1, s), xh);
-      }
-      if (Sys::kNonNegCost && !(Jh < Jcur)) {
-        cut = true;
-        steps = k + 1;
-        break;
+          for (int j = 0; j < N; ++j) v += rK[r][i * N + j] * dx[j];
+          uh[i] = v;
+        }
+        if (k + PF < T) {
+          ld(rx[r], xp(w, buf, k + PF, s));
+          ld(ru[r], up(w, buf, k + PF, s));
+          ld(rK[r], Kp(w, k + PF, s));
+          ld(rk[r], kp(w, k + PF, s));
+        }
+        Jh += double(mdl.cost(xh, uh));
+        R xn[N];
+        mdl.dyn(xh, uh, xn);
+#pragma unroll
+        for (int i = 0; i < N; ++i) xh[i] = xn[i];
+        if (write) {
+          st(up(w, nb, k, s), uh);
+          st(xp(w, nb, k + 1, s), xh);
+        }
+        if (Sys::kNonNegCost && !(Jh < Jcur)) {
+          steps = k + 1;
+          return Jh;
+        }
       }
     }
-    if (cut) return Jh;
-    steps = T;
     Jh += double(mdl.term(xh));
     return Jh;
   }
@@ -400,49 +410,54 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
       st = bad;
       break;
     }
+    // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
+    // whose lane wrote while trying it) one commit rollout that writes it; one
+    // call site of the rollout keeps the register footprint down
     int acc = -1;
     double Jn = J;
-    for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += GL) {
-      const int j = j0 + r;
+    bool commit = false;
+    for (int j0 = 0;;) {
+      const int j = commit ? acc : j0 + r;
       double Jh = __builtin_nan("");
       int steps = 0;
-      if (j < sp.ls_trials) {
+      if (commit || j < sp.ls_trials) {
         double alpha = 1.0;
         for (int q = 0; q < j; ++q) alpha *= sp.beta;
         // alpha = 1 (j == 0) is written while it runs, as is every trial of a
-        // one-lane group; other accepted steps are rolled out again below
-        Jh = LN::trial(mdl, w, s, T, buf, R(alpha), J, j == 0 || GL == 1, steps);
+        // one-lane group; the commit is written by the group's lead lane
+        const bool wr = commit ? lead : (j == 0 || GL == 1);
+        Jh = LN::trial(mdl, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, wr, steps);
+      }
+      ++npass;
+      if (commit) {
+        Jn = Jh;
+        nread += steps;
+        nwrite += steps;
+        break;
       }
       // the lanes of a group read the same data: a round moves as many steps
       // as its longest trial; only the alpha = 1 trial (or every trial of a
       // one-lane group) writes
-      if (j0 == 0 || GL == 1) nwrite += __shfl(steps, gbase, 64);
+      if (j0 == 0 || GL == 1) nwrite += (GL == 1) ? steps : __shfl(steps, gbase, 64);
       int longest = steps;
 #pragma unroll
       for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
       nread += longest;
-      ++npass;
       const bool ok = isfinite(Jh) && Jh < J;
       unsigned long long bits = __ballot(ok);
-      bits = (bits >> gbase) & ((GL == 64) ? ~0ull : ((1ull << GL) - 1));
+      bits = (bits >> gbase) & ((1ull << GL) - 1);
       if (bits) {
         const int rs = __ffsll(bits) - 1;
         acc = j0 + rs;
         Jn = __shfl(Jh, gbase + rs, 64);
       }
+      j0 += GL;
+      if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
+      if (acc > 0) commit = true;
     }
     if (acc < 0) {
       st = ST_LS_FAILED;
       break;
-    }
-    if (acc > 0 && GL > 1) {
-      double alpha = 1.0;
-      for (int q = 0; q < acc; ++q) alpha *= sp.beta;
-      int steps = 0;
-      Jn = LN::trial(mdl, w, s, T, buf, R(alpha), __builtin_inf(), lead, steps);
-      ++npass;
-      nread += steps;
-      nwrite += steps;
     }
     buf ^= 1;
     const double Jold = J;
