@@ -23,6 +23,9 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # fuse multiply-adds only within a source expression, so the rounding of a
+    # formula does not depend on the code it is inlined into
+    "-ffp-contract=on",
     # packed FP32 instructions stay off: plain FP32 code is compiled to scalar-lane ops
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

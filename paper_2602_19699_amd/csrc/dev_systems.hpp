@@ -106,6 +106,32 @@ struct PointMass {
       }
     }
 
+    // Per-step derivative block for the backward sweep, evaluated ahead of the
+    // serial recursion: l_x (2 nonzero), clipped position Hessian (3), l_u (2).
+    static constexpr int ND = 7;
+    CBIC_HD __forceinline__ void pack_derivs(const R* x, const R* u, R* D, R eps) const {
+      R lx[N], lu[M], Q[N][N], Ru[M][M];
+      cost_derivs(x, u, lx, lu, Q, Ru, eps, true);
+      D[0] = lx[0]; D[1] = lx[1];
+      D[2] = Q[0][0]; D[3] = Q[0][1]; D[4] = Q[1][1];
+      D[5] = lu[0]; D[6] = lu[1];
+    }
+    CBIC_HD __forceinline__ void unpack_derivs(const R* D, R A[N][N], R B[N][M], R lx[N], R lu[M], R Q[N][N],
+                                               R Ru[M][M], R eps) const {
+      jac(nullptr, nullptr, A, B);
+      lx[0] = D[0]; lx[1] = D[1]; lx[2] = R(0); lx[3] = R(0);
+      lu[0] = D[5]; lu[1] = D[6];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Q[i][j] = R(0);
+      Q[0][0] = D[2]; Q[0][1] = D[3]; Q[1][0] = D[3]; Q[1][1] = D[4];
+      Q[2][2] = dmax(R(0), eps);
+      Q[3][3] = dmax(R(0), eps);
+      const R ru = dmax(R(2) * R(p[1]), eps);
+      Ru[0][0] = ru; Ru[0][1] = R(0); Ru[1][0] = R(0); Ru[1][1] = ru;
+    }
+
     CBIC_HD __forceinline__ void term_derivs(const R* x, R lx[N], R Q[N][N], R eps, bool hess) const {
       const R w2 = R(2) * R(p[3]);
       lx[0] = w2 * (x[0] - R(p[5]));
@@ -376,6 +402,52 @@ struct Arm3 {
       }
     }
 
+    // Per-step derivative block: f_x (36), f_u (18), l_q (3), clipped q-block
+    // Hessian (6, upper triangle), l_u (3).
+    static constexpr int ND = 66;
+    CBIC_HD __forceinline__ void pack_derivs(const R* x, const R* u, R* D, R eps) const {
+      R A[N][N], B[N][M], lx[N], lu[M], Q[N][N], Ru[M][M];
+      jac(x, u, A, B);
+      cost_derivs(x, u, lx, lu, Q, Ru, eps, true);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) D[i * N + j] = A[i][j];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) D[36 + i * M + j] = B[i][j];
+      D[54] = lx[0]; D[55] = lx[1]; D[56] = lx[2];
+      D[57] = Q[0][0]; D[58] = Q[0][1]; D[59] = Q[0][2]; D[60] = Q[1][1]; D[61] = Q[1][2]; D[62] = Q[2][2];
+      D[63] = lu[0]; D[64] = lu[1]; D[65] = lu[2];
+    }
+    CBIC_HD __forceinline__ void unpack_derivs(const R* D, R A[N][N], R B[N][M], R lx[N], R lu[M], R Q[N][N],
+                                               R Ru[M][M], R eps) const {
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) A[i][j] = D[i * N + j];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) B[i][j] = D[36 + i * M + j];
+      lx[0] = D[54]; lx[1] = D[55]; lx[2] = D[56]; lx[3] = R(0); lx[4] = R(0); lx[5] = R(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) Q[i][j] = R(0);
+      Q[0][0] = D[57]; Q[0][1] = D[58]; Q[0][2] = D[59]; Q[1][1] = D[60]; Q[1][2] = D[61]; Q[2][2] = D[62];
+      Q[1][0] = D[58]; Q[2][0] = D[59]; Q[2][1] = D[61];
+      const R ev = dmax(R(0), eps);
+      Q[3][3] = ev; Q[4][4] = ev; Q[5][5] = ev;
+      lu[0] = D[63]; lu[1] = D[64]; lu[2] = D[65];
+      const R ru = dmax(R(2) * R(p[10]), eps);
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) Ru[i][j] = (i == j) ? ru : R(0);
+    }
+
     CBIC_HD __forceinline__ void term_derivs(const R* x, R lx[N], R Q[N][N], R eps, bool hess) const {
       Trig t;
       trig(x, t);
@@ -421,6 +493,9 @@ struct LinQuad {
   template <class R>
   struct Model {
     const double* __restrict__ p;
+    static constexpr int ND = 0;  // constant derivatives: nothing to stage
+    CBIC_HD __forceinline__ void pack_derivs(const R*, const R*, R*, R) const {}
+    CBIC_HD __forceinline__ void unpack_derivs(const R*, R[N][N], R[N][M], R[N], R[M], R[N][N], R[M][M], R) const {}
 
     CBIC_HD __forceinline__ void dyn(const R* x, const R* u, R* xn) const {
 #pragma unroll

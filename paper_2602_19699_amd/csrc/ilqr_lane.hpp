@@ -82,18 +82,181 @@ struct Lane {
   }
 
   // ------------------------------------------------------------------ backward
-  // One Riccati sweep over the iterate in buffer `buf`.  Writes K_k, k_k.
-  // Returns 0 or the status bit that freezes the instance.
-  __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf,
-                                      R eps, bool store) {
+  // One Riccati step at time k from the step's derivatives; updates (P, p)
+  // in place and writes K_k, k_k when `store`.  Returns 0 or the status bit
+  // that freezes the instance.
+  __device__ static __forceinline__ uint32_t riccati_step(const LaneState<R>& w, int s, int k, const R (&A)[N][N],
+                                                          const R (&B)[N][M], const R (&lx)[N], const R (&lu)[M],
+                                                          const R (&Qc)[N][N], const R (&Rc)[M][M], R (&P)[N][N],
+                                                          R (&p)[N], bool store) {
+    // PA = P A, PB = P B  (structural zeros of A, B skipped at compile time)
+    R PA[N][N], PB[N][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R v = R(0);
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::a_nz(t, j)) v += P[i][t] * A[t][j];
+        PA[i][j] = v;
+      }
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        R v = R(0);
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::b_nz(t, j)) v += P[i][t] * B[t][j];
+        PB[i][j] = v;
+      }
+    }
+    R Qx[N], Qu[M], Qxx[N][N], Qux[M][N];
+    double Quu[M][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R v = lx[i];
+#pragma unroll
+      for (int t = 0; t < N; ++t)
+        if (Sys::a_nz(t, i)) v += A[t][i] * p[t];
+      Qx[i] = v;
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        R q = Qc[i][j];
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::a_nz(t, i)) q += A[t][i] * PA[t][j];
+        Qxx[i][j] = q;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      R v = lu[i];
+#pragma unroll
+      for (int t = 0; t < N; ++t)
+        if (Sys::b_nz(t, i)) v += B[t][i] * p[t];
+      Qu[i] = v;
+#pragma unroll
+      for (int j = i; j < M; ++j) {
+        R q = Rc[i][j];
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::b_nz(t, i)) q += B[t][i] * PB[t][j];
+        Quu[i][j] = double(q);
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R q = R(0);
+#pragma unroll
+        for (int t = 0; t < N; ++t)
+          if (Sys::b_nz(t, i)) q += B[t][i] * PA[t][j];
+        Qux[i][j] = q;
+      }
+    }
+    // Cholesky of Q_uu and the gains, in FP64
+    double Lc[M][M], invd[M];
+    if (!chol_fp64<M>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    R Kk[M][N], kk[M];
+    bool fin = true;
+    {
+      double col[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
+      chol_solve_fp64<M>(Lc, invd, col);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        kk[i] = R(-col[i]);
+        fin = fin && isfinite(col[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) col[i] = double(Qux[i][j]);
+        chol_solve_fp64<M>(Lc, invd, col);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          Kk[i][j] = R(-col[i]);
+          fin = fin && isfinite(col[i]);
+        }
+      }
+    }
+    if (!fin) return ST_NONFINITE;
+    if (store) {
+      R* dK = Kp(w, k, s);
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) dK[i * N + j] = Kk[i][j];
+      st(kp(w, k, s), kk);
+    }
+    // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R v = Qx[i];
+#pragma unroll
+      for (int t = 0; t < M; ++t) v += Qux[t][i] * kk[t];
+      p[i] = v;
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        R q = Qxx[i][j];
+#pragma unroll
+        for (int t = 0; t < M; ++t) q += Qux[t][i] * Kk[t][j];
+        P[i][j] = q;
+        P[j][i] = q;
+      }
+    }
+    return 0;
+  }
+
+  __device__ static __forceinline__ void stage_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+
+  // One Riccati sweep over the iterate in buffer `buf`; writes K_k, k_k.
+  // For a model whose per-step derivatives are worth staging (ND > 0) the
+  // sweep runs in chunks of C steps: the GL lanes of the group first evaluate
+  // the derivative blocks of the chunk's steps in parallel into the group's
+  // LDS area `stage` ([C][ND]), then every lane runs the (serial, redundant)
+  // recursion over them.  Every group width goes through the same code, so
+  // results do not depend on the width.  Models with constant derivatives
+  // (ND = 0) evaluate them per step, with (x_k, u_k) prefetched two steps ahead.
+  template <int GL>
+  __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R eps,
+                                      bool store, R* stage, int r) {
+    constexpr int ND = Model::ND;
+    constexpr bool staged = ND > 0;
+    constexpr int C = staged ? GL * (ND <= 8 ? 2 : 1) : 1;
     R P[N][N], p[N];
     {
       R xT[N];
       ld(xT, xp(w, buf, T, s));
       mdl.term_derivs(xT, p, P, eps, true);
     }
-    uint32_t bad = 0;
-    // software prefetch of the next two steps' (x, u)
+    if (staged) {
+      for (int kc = T - 1; kc >= 0; kc -= C) {
+        for (int q = r; q < C; q += GL) {
+          const int k = kc - q;
+          if (k >= 0) {
+            R x[N], u[M];
+            ld(x, xp(w, buf, k, s));
+            ld(u, up(w, buf, k, s));
+            mdl.pack_derivs(x, u, stage + q * ND, eps);
+          }
+        }
+        stage_sync();
+        const int cn = kc + 1 < C ? kc + 1 : C;
+        for (int q = 0; q < cn; ++q) {
+          R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
+          mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
+          const uint32_t bad = riccati_step(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store);
+          if (bad) return bad;
+        }
+        stage_sync();
+      }
+      return 0;
+    }
+    // unstaged: software prefetch of the next two steps' (x, u)
     R xn[N], un[M], xn2[N], un2[M];
     ld(xn, xp(w, buf, T - 1, s));
     ld(un, up(w, buf, T - 1, s));
@@ -120,131 +283,10 @@ struct Lane {
       R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
       mdl.jac(x, u, A, B);
       mdl.cost_derivs(x, u, lx, lu, Qc, Rc, eps, true);
-
-      // PA = P A, PB = P B  (structural zeros of A, B skipped at compile time)
-      R PA[N][N], PB[N][M];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          R v = R(0);
-#pragma unroll
-          for (int t = 0; t < N; ++t)
-            if (Sys::a_nz(t, j)) v += P[i][t] * A[t][j];
-          PA[i][j] = v;
-        }
-#pragma unroll
-        for (int j = 0; j < M; ++j) {
-          R v = R(0);
-#pragma unroll
-          for (int t = 0; t < N; ++t)
-            if (Sys::b_nz(t, j)) v += P[i][t] * B[t][j];
-          PB[i][j] = v;
-        }
-      }
-      R Qx[N], Qu[M], Qxx[N][N], Qux[M][N];
-      double Quu[M][M];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        R v = lx[i];
-#pragma unroll
-        for (int t = 0; t < N; ++t)
-          if (Sys::a_nz(t, i)) v += A[t][i] * p[t];
-        Qx[i] = v;
-#pragma unroll
-        for (int j = i; j < N; ++j) {
-          R q = Qc[i][j];
-#pragma unroll
-          for (int t = 0; t < N; ++t)
-            if (Sys::a_nz(t, i)) q += A[t][i] * PA[t][j];
-          Qxx[i][j] = q;
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        R v = lu[i];
-#pragma unroll
-        for (int t = 0; t < N; ++t)
-          if (Sys::b_nz(t, i)) v += B[t][i] * p[t];
-        Qu[i] = v;
-#pragma unroll
-        for (int j = i; j < M; ++j) {
-          R q = Rc[i][j];
-#pragma unroll
-          for (int t = 0; t < N; ++t)
-            if (Sys::b_nz(t, i)) q += B[t][i] * PB[t][j];
-          Quu[i][j] = double(q);
-        }
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          R q = R(0);
-#pragma unroll
-          for (int t = 0; t < N; ++t)
-            if (Sys::b_nz(t, i)) q += B[t][i] * PA[t][j];
-          Qux[i][j] = q;
-        }
-      }
-      // Cholesky of Q_uu and the gains, in FP64
-      double Lc[M][M], invd[M];
-      const bool ok = chol_fp64<M>(Quu, Lc, invd);
-      if (!ok) {
-        bad = ST_CHOL_FAIL;
-        break;
-      }
-      R Kk[M][N], kk[M];
-      bool fin = true;
-      {
-        double col[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
-        chol_solve_fp64<M>(Lc, invd, col);
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          kk[i] = R(-col[i]);
-          fin = fin && isfinite(col[i]);
-        }
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-#pragma unroll
-          for (int i = 0; i < M; ++i) col[i] = double(Qux[i][j]);
-          chol_solve_fp64<M>(Lc, invd, col);
-#pragma unroll
-          for (int i = 0; i < M; ++i) {
-            Kk[i][j] = R(-col[i]);
-            fin = fin && isfinite(col[i]);
-          }
-        }
-      }
-      if (!fin) {
-        bad = ST_NONFINITE;
-        break;
-      }
-      if (store) {
-        R* dK = Kp(w, k, s);
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-          for (int j = 0; j < N; ++j) dK[i * N + j] = Kk[i][j];
-        st(kp(w, k, s), kk);
-      }
-      // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        R v = Qx[i];
-#pragma unroll
-        for (int t = 0; t < M; ++t) v += Qux[t][i] * kk[t];
-        p[i] = v;
-#pragma unroll
-        for (int j = i; j < N; ++j) {
-          R q = Qxx[i][j];
-#pragma unroll
-          for (int t = 0; t < M; ++t) q += Qux[t][i] * Kk[t][j];
-          P[i][j] = q;
-          P[j][i] = q;
-        }
-      }
+      const uint32_t bad = riccati_step(w, s, k, A, B, lx, lu, Qc, Rc, P, p, store);
+      if (bad) return bad;
     }
-    return bad;
+    return 0;
   }
 
   // ------------------------------------------------------------------ line search trial
@@ -392,6 +434,12 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
   const bool lead = (r == 0);
   const int gbase = (threadIdx.x & 63) & ~(GL - 1);  // first lane of this group in the wave
   const typename LN::Model mdl{prm};
+  // LDS staging area of the backward sweep's derivative blocks, per group
+  constexpr int ND = LN::Model::ND;
+  constexpr bool staged = ND > 0;
+  constexpr int C = staged ? GL * (ND <= 8 ? 2 : 1) : 1;
+  __shared__ R stage_mem[staged ? (64 / GL) * C * ND : 1];
+  R* stage = staged ? stage_mem + (gbase / GL) * C * ND : nullptr;
   const int T = w.T[s];
   const int b = w.inst[s];
   double J = w.J[s];
@@ -405,7 +453,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
       break;
     }
     ++nsweep;
-    const uint32_t bad = LN::backward(mdl, w, s, T, buf, eps, lead);
+    const uint32_t bad = LN::template backward<GL>(mdl, w, s, T, buf, eps, lead, stage, r);
     if (bad) {
       st = bad;
       break;
