@@ -103,24 +103,31 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
   wave_sync();
   const bool row = lane < NV;
   const int ri = row ? lane : 0;
-  // M = A^T A + diag(1 + 0.1 sin q) into L (rows on lanes), then an in-place
-  // right-looking Cholesky with the matrix in LDS (few live registers)
-  if (row) {
-    for (int j = 0; j <= ri; ++j) ws.L[ri][j] = sm.M0[ri][j];
-    ws.L[ri][ri] += R(1) + R(0.1) * ws.s[ri];
-  }
-  wave_sync();
+  // M = A^T A + diag(1 + 0.1 sin q); Cholesky with the rows on lanes, the
+  // pivot column exchanged by lane shuffles
+  R m[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) m[j] = row ? sm.M0[ri][j] : R(0);
+#pragma unroll
+  for (int j = 0; j < NV; ++j)
+    if (j == lane) m[j] += R(1) + R(0.1) * ws.s[ri];
+#pragma unroll
   for (int j = 0; j < NV; ++j) {
-    const R ljj = dsqrt(ws.L[j][j]);
-    wave_sync();
-    if (row && ri >= j) ws.L[ri][j] = (ri == j) ? ljj : ws.L[ri][j] / ljj;
-    wave_sync();
-    if (row && ri > j) {
-      const R lij = ws.L[ri][j];
-      for (int k = j + 1; k <= ri; ++k) ws.L[ri][k] -= lij * ws.L[k][j];
+    const R piv = __shfl(m[j], j, 64);
+    const R ljj = dsqrt(piv);
+    const R inv = R(1) / ljj;
+    const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
+    m[j] = lij;
+#pragma unroll
+    for (int k = j + 1; k < NV; ++k) {
+      const R lkj = __shfl(lij, k, 64);
+      m[k] -= lij * lkj;
     }
-    wave_sync();
   }
+  if (row)
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+      if (j <= lane) ws.L[ri][j] = m[j];
   // bias forces and right-hand side r = S u - b
   R y = R(0);
   if (row) {
@@ -134,15 +141,20 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
     const R b = b1 + b2 * ws.x[NQ + ri];
     y = (ri >= 6 ? ws.u[ri - 6] : R(0)) - b;
   }
-  const R lii = row ? ws.L[ri][ri] : R(1);
-  // L z = r and L^T a = z (rows on lanes, the solved entry broadcast by a shuffle)
+  wave_sync();
+  // L z = r (rows on lanes)
+#pragma unroll
   for (int j = 0; j < NV; ++j) {
-    const R yj = __shfl(y / lii, j, 64);
+    const R t = y / m[j];
+    const R yj = __shfl(t, j, 64);
     if (lane == j) y = yj;
-    else if (row && lane > j) y -= ws.L[ri][j] * yj;
+    else if (lane > j) y -= m[j] * yj;
   }
+  // L^T a = z
+#pragma unroll
   for (int j = NV - 1; j >= 0; --j) {
-    const R zj = __shfl(y / lii, j, 64);
+    const R t = y / m[j];
+    const R zj = __shfl(t, j, 64);
     if (lane == j) y = zj;
     else if (lane < j) y -= ws.L[j][ri] * zj;
   }
