@@ -37,6 +37,41 @@ FP32_PEAK_TFLOPS = 157.3
 METRIC = "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latency"
 
 
+# HBM traffic of the dominant kernels from rocprofv3 counter runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch, each in a run of its own), scaled by what
+# the same counters read for a plain 512 MiB device copy: FETCH_SIZE read
+# 262159 KiB and WRITE_SIZE 524288 KiB for 524288 KiB moved each way.  An
+# entry holds only while the sources it was taken from are unchanged (their
+# sha256 is recorded); otherwise traffic is reported as null.
+FETCH_SCALE = 524288.0 / 262159.0
+WRITE_SCALE = 524288.0 / 524288.0
+LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp")
+COUNTERS = {
+    ("pm16k", "mixed_tol1e-7", "lane_iterate<PointMass,float,8>"): {
+        "sources": LANE_SOURCES + ("k_lane_pm.hip",),
+        "sha256": "f5b183ecf0f1992ef50862b88c88362eb11656f15a3ef24bd99f15f28ba751b0",
+        "fetch_kib": 689729.0, "write_kib": 501666.0,
+        "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
+    },
+}
+
+
+def sources_sha(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2602_19699_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(name, form, kernel):
+    e = COUNTERS.get((name, form, kernel))
+    if e is None or e["sha256"] != sources_sha(e["sources"]):
+        return None
+    return round((e["fetch_kib"] * FETCH_SCALE + e["write_kib"] * WRITE_SCALE) * 1024.0)
+
+
 def riccati_flops(n, m):
     """Dense, symmetry-unaware flop count of one backward Riccati step."""
     return 4 * n ** 3 + 6 * n * n * m + 2 * m * m * n + 2 * m * m * (n + 1) + m ** 3 / 3 + 2 * n * n + 4 * n * m
@@ -139,19 +174,21 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
     return results, best, cpu
 
 
-def roofline_for(name, res, form_opts):
+def roofline_for(name, form, res, form_opts):
+    prec = "double" if form_opts.precision == 0 else "float"
     if name == "quad1k":
         peak = FP64_PEAK_TFLOPS if form_opts.precision == 0 else FP32_PEAK_TFLOPS
+        kernel = f"quad_iterate<{prec}>"
         return {"bound": "alu", "achieved": round(res["iterate_TFLOPs"], 4), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(res["iterate_TFLOPs"] / peak, 5), "traffic": None,
-                "kernel": f"quad_iterate<{'double' if form_opts.precision == 0 else 'float'}>",
-                "alg_flops_per_launch": res["iterate_alg_flops"], "iterate_ms": round(res["iterate_ms"], 4)}
+                "frac": round(res["iterate_TFLOPs"] / peak, 5), "traffic": traffic_for(name, form, kernel),
+                "kernel": kernel, "alg_flops_per_launch": res["iterate_alg_flops"],
+                "iterate_ms": round(res["iterate_ms"], 4)}
     sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
+    kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']}>"
     return {"bound": "hbm", "achieved": round(res["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": None,
-            "kernel": f"lane_iterate<{sysname},{'double' if form_opts.precision == 0 else 'float'},"
-                      f"{res['lanes_per_instance']}>",
-            "alg_bytes_per_launch": res["iterate_alg_bytes"], "iterate_ms": round(res["iterate_ms"], 4)}
+            "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": traffic_for(name, form, kernel),
+            "kernel": kernel, "alg_bytes_per_launch": res["iterate_alg_bytes"],
+            "iterate_ms": round(res["iterate_ms"], 4)}
 
 
 def serving(ctx, rates, seconds):
@@ -185,14 +222,26 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline, no serving")
     ap.add_argument("--only", default=None, help="time only this form (for profiler runs)")
     ap.add_argument("--workload", default=None, help="time only this workload (pm16k, pm64, arm4k, quad1k)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="only three plain 512 MiB device copies (to scale the HBM byte counters)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving workload: Poisson rates 1k..50k/s, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the instances are independent and a "
-              f"multi-GPU run would shard the batch with no exchange, which this build does not launch.",
+              f"multi-GPU run would shard the batch with no exchange, which this program does not launch.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calib:
+        import torch
+        a = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": a.numel() * 8, "launches": 3}))
+        return
 
     from paper_2602_19699_amd import cbic
 
@@ -225,7 +274,7 @@ def main():
         res, best, cpu = workload_bench(ctx, nme, forms[nme], steps, args.warmup, cpu_cfg[nme][0],
                                         cpu_cfg[nme][1], quick=args.quick or bool(args.only))
         entry = {"best_form": best, "forms": {k: fmt(v) for k, v in res.items()},
-                 "roofline": roofline_for(nme, res[best], forms[nme][best]), "cpu_baseline": cpu,
+                 "roofline": roofline_for(nme, best, res[best], forms[nme][best]), "cpu_baseline": cpu,
                  "steps": steps}
         if head is None:
             head = (nme, res, best, entry)
