@@ -155,7 +155,7 @@ CBIC_HD __forceinline__ void clip_sym3(R h[9], R eps) {
 // triangle of a (a[i][j], j >= i).  Returns false on a non-positive or
 // non-finite pivot.  L is returned in l[i][j], j <= i; diag holds 1/L_ii.
 template <int M>
-CBIC_HD __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], double inv_diag[M]) {
+__device__ __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], double inv_diag[M]) {
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
@@ -163,8 +163,13 @@ CBIC_HD __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], dou
 #pragma unroll
     for (int k = 0; k < j; ++k) d -= l[j][k] * l[j][k];
     ok = ok && (d > 0.0) && isfinite(d);
-    const double ljj = sqrt(d);
-    const double inv = 1.0 / ljj;
+    // 1/sqrt(d) from the hardware estimate (relative error below 2^-22) and
+    // two Newton steps y <- y (3 - d y^2) / 2, which take it to a few ulp;
+    // sqrt(d) = d / sqrt(d)
+    double inv = __builtin_amdgcn_rsq(d);
+    inv = inv * (1.5 - 0.5 * d * inv * inv);
+    inv = inv * (1.5 - 0.5 * d * inv * inv);
+    const double ljj = d * inv;
     l[j][j] = ljj;
     inv_diag[j] = inv;
 #pragma unroll
@@ -180,7 +185,7 @@ CBIC_HD __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], dou
 
 // Solve (L L^T) y = b in place.
 template <int M>
-CBIC_HD __forceinline__ void chol_solve_fp64(const double l[M][M], const double inv_diag[M], double b[M]) {
+__device__ __forceinline__ void chol_solve_fp64(const double l[M][M], const double inv_diag[M], double b[M]) {
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     double v = b[i];

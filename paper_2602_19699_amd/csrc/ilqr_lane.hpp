@@ -218,7 +218,8 @@ struct Lane {
   // sweep runs in chunks of C steps: the GL lanes of the group first evaluate
   // the derivative blocks of the chunk's steps in parallel into the group's
   // LDS area `stage` ([C][ND]), then every lane runs the (serial, redundant)
-  // recursion over them.  Every group width goes through the same code, so
+  // recursion over them; the (x_k, u_k) of the next chunk are loaded while the
+  // recursion runs.  Every group width goes through the same code, so
   // results do not depend on the width.  Models with constant derivatives
   // (ND = 0) evaluate them per step, with (x_k, u_k) prefetched two steps ahead.
   template <int GL>
@@ -234,14 +235,28 @@ struct Lane {
       mdl.term_derivs(xT, p, P, eps, true);
     }
     if (staged) {
+      // (x_k, u_k) of the lane's steps of the next chunk are loaded while the
+      // current chunk's recursion runs
+      constexpr int PB = C / GL > 0 ? C / GL : 1;
+      R px[PB][N], pu[PB][M];
+#pragma unroll
+      for (int q = 0; q < PB; ++q) {
+        const int k = T - 1 - (r + q * GL);
+        if (k >= 0) {
+          ld(px[q], xp(w, buf, k, s));
+          ld(pu[q], up(w, buf, k, s));
+        }
+      }
       for (int kc = T - 1; kc >= 0; kc -= C) {
-        for (int q = r; q < C; q += GL) {
-          const int k = kc - q;
+#pragma unroll
+        for (int q = 0; q < PB; ++q)
+          if (kc - (r + q * GL) >= 0) mdl.pack_derivs(px[q], pu[q], stage + (r + q * GL) * ND, eps);
+#pragma unroll
+        for (int q = 0; q < PB; ++q) {
+          const int k = kc - C - (r + q * GL);
           if (k >= 0) {
-            R x[N], u[M];
-            ld(x, xp(w, buf, k, s));
-            ld(u, up(w, buf, k, s));
-            mdl.pack_derivs(x, u, stage + q * ND, eps);
+            ld(px[q], xp(w, buf, k, s));
+            ld(pu[q], up(w, buf, k, s));
           }
         }
         stage_sync();
@@ -290,67 +305,115 @@ struct Lane {
   }
 
   // ------------------------------------------------------------------ line search trial
+  // Step record of the line-search stream: x_k, u_k, K_k, k_k, padded to 16 B.
+  static constexpr int SW = N + M + M * N + M;
+  static constexpr int SWP = (SW + 3) & ~3;
+  // steps each lane loads per chunk
+  static constexpr int PT = SWP * int(sizeof(R)) <= 64 ? 2 : 1;
+
+  __device__ static __forceinline__ void load_step(const LaneState<R>& w, int buf, int k, int s, R (&v)[SW]) {
+    const R* a = xp(w, buf, k, s);
+    const R* b = up(w, buf, k, s);
+    const R* c = Kp(w, k, s);
+    const R* d = kp(w, k, s);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = a[i];
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[N + i] = b[i];
+#pragma unroll
+    for (int i = 0; i < M * N; ++i) v[N + M + i] = c[i];
+#pragma unroll
+    for (int i = 0; i < M; ++i) v[N + M + M * N + i] = d[i];
+  }
+  __device__ static __forceinline__ void put_step(R* dst, const R (&v)[SW]) {
+#pragma unroll
+    for (int i = 0; i < SW; ++i) dst[i] = v[i];
+  }
+
   // Closed-loop rollout with step alpha from the iterate in `buf`; returns
   // J_hat in FP64 (NaN-propagating).  With `write` the trial trajectory goes to
   // the other buffer.  With non-negative costs a trial stops as soon as its
   // partial sum reaches J: its total could only be larger, so the
   // accept/reject decision is unchanged.
+  //
+  // The iterate's step records stream through the group's LDS ring `ring`
+  // ([2][CT][SWP]) in chunks of CT = GL * PT steps: lane r loads steps
+  // r, r + GL, ... of the next chunk from HBM while the current chunk is
+  // rolled out, so the loads' latency is covered by a chunk of work.  The
+  // group keeps streaming while any of its lanes is still rolling out.
+  template <int GL>
   __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R alpha,
-                                 double Jcur, bool write, int& steps) {
-    // step data (x_k, u_k, K_k, k_k) streams through a ring of PF register
-    // sets, PF steps ahead of the step being computed
-    constexpr int PF = Sys::N * (Sys::M + 2) <= 16 ? 2 : 2;
+                                 double Jcur, bool write, int& steps, R* ring, int r, int gbase) {
+    constexpr int CT = GL * PT;
+    const unsigned long long gmask = (GL >= 64) ? ~0ull : ((1ull << GL) - 1ull);
     const int nb = buf ^ 1;
     R xh[N];
     ld(xh, xp(w, buf, 0, s));
     double Jh = 0.0;
-    R rx[PF][N], ru[PF][M], rK[PF][M * N], rk[PF][M];
-#pragma unroll
-    for (int r = 0; r < PF; ++r)
-      if (r < T) {
-        ld(rx[r], xp(w, buf, r, s));
-        ld(ru[r], up(w, buf, r, s));
-        ld(rK[r], Kp(w, r, s));
-        ld(rk[r], kp(w, r, s));
-      }
+    bool live = true;
     steps = T;
-    for (int k0 = 0; k0 < T; k0 += PF) {
+    R nxt[PT][SW];
 #pragma unroll
-      for (int r = 0; r < PF; ++r) {
-        const int k = k0 + r;
-        if (k >= T) break;
-        R dx[N], uh[M];
-#pragma unroll
-        for (int i = 0; i < N; ++i) dx[i] = xh[i] - rx[r][i];
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          R v = ru[r][i] + alpha * rk[r][i];
-#pragma unroll
-          for (int j = 0; j < N; ++j) v += rK[r][i * N + j] * dx[j];
-          uh[i] = v;
-        }
-        if (k + PF < T) {
-          ld(rx[r], xp(w, buf, k + PF, s));
-          ld(ru[r], up(w, buf, k + PF, s));
-          ld(rK[r], Kp(w, k + PF, s));
-          ld(rk[r], kp(w, k + PF, s));
-        }
-        Jh += double(mdl.cost(xh, uh));
-        R xn[N];
-        mdl.dyn(xh, uh, xn);
-#pragma unroll
-        for (int i = 0; i < N; ++i) xh[i] = xn[i];
-        if (write) {
-          st(up(w, nb, k, s), uh);
-          st(xp(w, nb, k + 1, s), xh);
-        }
-        if (Sys::kNonNegCost && !(Jh < Jcur)) {
-          steps = k + 1;
-          return Jh;
-        }
+    for (int q = 0; q < PT; ++q) {
+      const int k = r + q * GL;
+      if (k < T) {
+        load_step(w, buf, k, s, nxt[q]);
+        put_step(ring + (r + q * GL) * SWP, nxt[q]);
       }
     }
-    Jh += double(mdl.term(xh));
+    stage_sync();
+    for (int kc = 0, c = 0; kc < T; kc += CT, ++c) {
+      const R* cur = ring + (c & 1) * CT * SWP;
+      R* nx = ring + ((c + 1) & 1) * CT * SWP;
+      const bool more = kc + CT < T;
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < PT; ++q) {
+          const int k = kc + CT + r + q * GL;
+          if (k < T) load_step(w, buf, k, s, nxt[q]);
+        }
+      }
+      if (live) {
+        const int cn = T - kc < CT ? T - kc : CT;
+        for (int q = 0; q < cn; ++q) {
+          const R* v = cur + q * SWP;
+          const int k = kc + q;
+          R dx[N], uh[M];
+#pragma unroll
+          for (int i = 0; i < N; ++i) dx[i] = xh[i] - v[i];
+#pragma unroll
+          for (int i = 0; i < M; ++i) {
+            R u = v[N + i] + alpha * v[N + M + M * N + i];
+#pragma unroll
+            for (int j = 0; j < N; ++j) u += v[N + M + i * N + j] * dx[j];
+            uh[i] = u;
+          }
+          Jh += double(mdl.cost(xh, uh));
+          R xn[N];
+          mdl.dyn(xh, uh, xn);
+#pragma unroll
+          for (int i = 0; i < N; ++i) xh[i] = xn[i];
+          if (write) {
+            st(up(w, nb, k, s), uh);
+            st(xp(w, nb, k + 1, s), xh);
+          }
+          if (Sys::kNonNegCost && !(Jh < Jcur)) {
+            steps = k + 1;
+            live = false;
+            break;
+          }
+        }
+      }
+      const unsigned long long any = (__ballot(live) >> gbase) & gmask;
+      if (!any || !more) break;
+#pragma unroll
+      for (int q = 0; q < PT; ++q) {
+        const int k = kc + CT + r + q * GL;
+        if (k < T) put_step(nx + (r + q * GL) * SWP, nxt[q]);
+      }
+      stage_sync();
+    }
+    if (live) Jh += double(mdl.term(xh));
     return Jh;
   }
 };
@@ -438,8 +501,14 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
   constexpr int ND = LN::Model::ND;
   constexpr bool staged = ND > 0;
   constexpr int C = staged ? GL * (ND <= 8 ? 2 : 1) : 1;
-  __shared__ R stage_mem[staged ? (64 / GL) * C * ND : 1];
-  R* stage = staged ? stage_mem + (gbase / GL) * C * ND : nullptr;
+  // one LDS area per group, shared by the backward sweep's derivative blocks
+  // and the line search's step-record ring; the area stride is padded so that
+  // the groups of a wave start on different banks
+  constexpr int CT = GL * LN::PT;
+  constexpr int AREA = (staged && C * ND > 2 * CT * LN::SWP) ? C * ND : 2 * CT * LN::SWP;
+  constexpr int STRIDE = (AREA + 31) / 32 * 32 + 4;
+  __shared__ __align__(16) R stage_mem[(64 / GL) * STRIDE];
+  R* stage = stage_mem + (gbase / GL) * STRIDE;
   const int T = w.T[s];
   const int b = w.inst[s];
   double J = w.J[s];
@@ -474,7 +543,8 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
         // alpha = 1 (j == 0) is written while it runs, as is every trial of a
         // one-lane group; the commit is written by the group's lead lane
         const bool wr = commit ? lead : (j == 0 || GL == 1);
-        Jh = LN::trial(mdl, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, wr, steps);
+        Jh = LN::template trial<GL>(mdl, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, wr, steps, stage, r,
+                                    gbase);
       }
       ++npass;
       if (commit) {

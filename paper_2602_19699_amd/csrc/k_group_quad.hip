@@ -4,8 +4,8 @@
 // One 256-thread workgroup owns one instance.  The backward Riccati sweep
 // keeps P, f_x, P f_x, f_u, P f_u, the gains and Q_ux in LDS and forms the
 // products with block-tiled GEMM-lets (a 16 x 16 thread grid, register tiles);
-// Q_uu is factored in FP64 (wave 0, rows held by lanes, columns exchanged by
-// lane shuffles) in both precisions.  The dynamics step needs a Cholesky of
+// Q_uu is factored in FP64 (wave 0, rows held by lanes, each pivot column
+// broadcast from its lane through a scalar register) in both precisions.  The dynamics step needs a Cholesky of
 // the 18 x 18 mass matrix M(q) = A^T A + diag(1 + 0.1 sin q); a wave does it
 // with its lanes holding the rows.  Line-search trials run one per wave: in
 // round r wave w tries alpha_j with j = 4 r + w, and the first accepted j is
@@ -29,6 +29,7 @@ constexpr int O_DT = 0, O_WU = 1, O_WT = 2, O_WQ = 3, O_WV = 4, O_M0 = 5, O_W1 =
 template <class R>
 struct WaveScratch {
   R L[NV][NV + 1];  // Cholesky factor of M(q), lower, row-major
+  R Li[NV];         // reciprocals of its diagonal
   R x[LD];          // state of this wave's rollout
   R xn[LD];         // next state
   R u[16];          // control
@@ -56,7 +57,7 @@ struct Smem {
   R Qu[16], kk[16], lu[16];
   double Quu[M][M + 1];
   double Lq[M][M + 1];
-  double Yq[M][N + 1];  // [K k] solves
+  double Lqi[M];  // reciprocals of the diagonal of Lq
   double wJ[NW];
   int wok[NW];
   int flag;
@@ -67,6 +68,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// value of v in lane j (j uniform), read through a scalar register
+__device__ __forceinline__ float bcast(float v, int j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+}
+__device__ __forceinline__ double bcast(double v, int j) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 template <class R>
@@ -104,8 +116,8 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
   const bool row = lane < NV;
   const int ri = row ? lane : 0;
   // M = A^T A + diag(1 + 0.1 sin q); Cholesky with the rows on lanes, the
-  // pivot column exchanged by lane shuffles
-  R m[NV];
+  // pivot column broadcast from its lane
+  R m[NV], invd[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) m[j] = row ? sm.M0[ri][j] : R(0);
 #pragma unroll
@@ -113,14 +125,15 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
     if (j == lane) m[j] += R(1) + R(0.1) * ws.s[ri];
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    const R piv = __shfl(m[j], j, 64);
+    const R piv = bcast(m[j], j);
     const R ljj = dsqrt(piv);
     const R inv = R(1) / ljj;
+    invd[j] = inv;
     const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
     m[j] = lij;
 #pragma unroll
     for (int k = j + 1; k < NV; ++k) {
-      const R lkj = __shfl(lij, k, 64);
+      const R lkj = bcast(lij, k);
       m[k] -= lij * lkj;
     }
   }
@@ -128,6 +141,9 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
 #pragma unroll
     for (int j = 0; j < NV; ++j)
       if (j <= lane) ws.L[ri][j] = m[j];
+  if (lane == 0)
+#pragma unroll
+    for (int j = 0; j < NV; ++j) ws.Li[j] = invd[j];
   // bias forces and right-hand side r = S u - b
   R y = R(0);
   if (row) {
@@ -145,16 +161,14 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
   // L z = r (rows on lanes)
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    const R t = y / m[j];
-    const R yj = __shfl(t, j, 64);
+    const R yj = bcast(y, j) * invd[j];
     if (lane == j) y = yj;
     else if (lane > j) y -= m[j] * yj;
   }
   // L^T a = z
 #pragma unroll
   for (int j = NV - 1; j >= 0; --j) {
-    const R t = y / m[j];
-    const R zj = __shfl(t, j, 64);
+    const R zj = bcast(y, j) * invd[j];
     if (lane == j) y = zj;
     else if (lane < j) y -= ws.L[j][ri] * zj;
   }
@@ -254,18 +268,33 @@ __device__ __forceinline__ void jacobians(Smem<R>& sm, R dt, int tid) {
     Z[i * 48 + col] = v;
   }
   __syncthreads();
-  if (tid < 48) {  // column solves with L L^T, in place in LDS
-    R* zc = Z + tid;
+  if (tid < 48) {  // column solves with L L^T; the column lives in registers
+    R y[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) y[i] = Z[i * 48 + tid];
+    // two partial sums per row halve the dependent chain
+#pragma unroll
     for (int i = 0; i < NV; ++i) {
-      R v = zc[i * 48];
-      for (int k = 0; k < i; ++k) v -= ws.L[i][k] * zc[k * 48];
-      zc[i * 48] = v / ws.L[i][i];
+      R v0 = y[i], v1 = R(0);
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        if (k & 1) v1 += ws.L[i][k] * y[k];
+        else v0 -= ws.L[i][k] * y[k];
+      }
+      y[i] = (v0 - v1) * ws.Li[i];
     }
+#pragma unroll
     for (int i = NV - 1; i >= 0; --i) {
-      R v = zc[i * 48];
-      for (int k = i + 1; k < NV; ++k) v -= ws.L[k][i] * zc[k * 48];
-      zc[i * 48] = v / ws.L[i][i];
+      R v0 = y[i], v1 = R(0);
+#pragma unroll
+      for (int k = i + 1; k < NV; ++k) {
+        if (k & 1) v1 += ws.L[k][i] * y[k];
+        else v0 -= ws.L[k][i] * y[k];
+      }
+      y[i] = (v0 - v1) * ws.Li[i];
     }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) Z[i * 48 + tid] = y[i];
   }
   __syncthreads();
   // d v+/d x and d v+/d u, then q rows: q+ = q + dt E v+
@@ -308,14 +337,15 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const double piv = __shfl(m[j], j, 64);
+      const double piv = bcast(m[j], j);
       ok = ok && (piv > 0.0) && isfinite(piv);
       const double ljj = sqrt(piv);
       const double inv = 1.0 / ljj;
+      if (lane == 0) sm.Lqi[j] = inv;
       const double lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : 0.0);
       m[j] = lij;
 #pragma unroll
-      for (int k = j + 1; k < M; ++k) m[k] -= lij * __shfl(lij, k, 64);
+      for (int k = j + 1; k < M; ++k) m[k] -= lij * bcast(lij, k);
     }
     if (row)
 #pragma unroll
@@ -324,23 +354,36 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
   }
   __syncthreads();
   if (sm.flag) return false;
-  if (tid <= N) {  // column tid of [Q_ux | Q_u], solved in place in LDS
-    double* yc = &sm.Yq[0][tid];
-    for (int i = 0; i < M; ++i) yc[i * (N + 1)] = double(tid < N ? sm.Qux[i][tid] : sm.Qu[i]);
+  if (tid <= N) {  // column tid of [Q_ux | Q_u]; the column lives in registers
+    double y[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) y[i] = double(tid < N ? sm.Qux[i][tid] : sm.Qu[i]);
+#pragma unroll
     for (int i = 0; i < M; ++i) {
-      double v = yc[i * (N + 1)];
-      for (int k = 0; k < i; ++k) v -= sm.Lq[i][k] * yc[k * (N + 1)];
-      yc[i * (N + 1)] = v / sm.Lq[i][i];
+      double v0 = y[i], v1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        if (k & 1) v1 += sm.Lq[i][k] * y[k];
+        else v0 -= sm.Lq[i][k] * y[k];
+      }
+      y[i] = (v0 - v1) * sm.Lqi[i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+      double v0 = y[i], v1 = 0.0;
+#pragma unroll
+      for (int k = i + 1; k < M; ++k) {
+        if (k & 1) v1 += sm.Lq[k][i] * y[k];
+        else v0 -= sm.Lq[k][i] * y[k];
+      }
+      y[i] = (v0 - v1) * sm.Lqi[i];
     }
     bool fin = true;
-    for (int i = M - 1; i >= 0; --i) {
-      double v = yc[i * (N + 1)];
-      for (int k = i + 1; k < M; ++k) v -= sm.Lq[k][i] * yc[k * (N + 1)];
-      v /= sm.Lq[i][i];
-      yc[i * (N + 1)] = v;
-      fin = fin && isfinite(v);
-      if (tid < N) sm.Kg[i][tid] = R(-v);
-      else sm.kk[i] = R(-v);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      fin = fin && isfinite(y[i]);
+      if (tid < N) sm.Kg[i][tid] = R(-y[i]);
+      else sm.kk[i] = R(-y[i]);
     }
     if (!fin) sm.flag = 2;
   }
