@@ -3,11 +3,13 @@
 //
 // One 256-thread workgroup owns one instance.  The backward Riccati sweep
 // keeps P, f_x, P f_x, f_u, P f_u, the gains and Q_ux in LDS and forms the
-// products with block-tiled GEMM-lets (a 16 x 16 thread grid, register tiles);
-// Q_uu is factored in FP64 (wave 0, rows held by lanes, each pivot column
-// broadcast from its lane through a scalar register) in both precisions.  The dynamics step needs a Cholesky of
-// the 18 x 18 mass matrix M(q) = A^T A + diag(1 + 0.1 sin q); a wave does it
-// with its lanes holding the rows.  Line-search trials run one per wave: in
+// products as 16 x 16 output tiles on the matrix cores (FP32 MFMA for the
+// mixed form, FP64 MFMA for the plain one), the tiles spread over the four
+// waves; Q_uu is factored in FP64 (wave 0, rows held by lanes, each pivot
+// column broadcast from its lane through a scalar register) in both
+// precisions.  The dynamics step needs a Cholesky of the 18 x 18 mass matrix
+// M(q) = A^T A + diag(1 + 0.1 sin q); a wave does it with its lanes holding
+// the rows.  Line-search trials run one per wave: in
 // round r wave w tries alpha_j with j = 4 r + w, and the first accepted j is
 // taken, as in the sequential rule.  Trajectories and gains use the same
 // step-major workspace as the lane schedule.
@@ -201,47 +203,56 @@ __device__ __forceinline__ R wave_cost(const Smem<R>& sm, const R* x, const R* u
   return wave_sum(v);
 }
 
-// ------------------------------------------------------------------ block GEMM
-// C = Cin + op(A) op(B) over an Mr x Nc output with inner size Kd, on a 16 x 16
-// thread grid with register tiles; op(A)(i,k) = TA ? A[k][i] : A[i][k].
-template <int Mr, int Nc, int Kd, bool TA, bool TB, class R>
-__device__ __forceinline__ void blk_gemm(R* C, int ldc, const R* A, int lda, const R* Bp, int ldb, const R* Cin,
-                                         int ldcin, int tid) {
-  constexpr int RT = (Mr + 15) / 16, CT = (Nc + 15) / 16;
-  const int tr = tid >> 4, tc = tid & 15;
-  R acc[RT][CT];
+// ------------------------------------------------------------------ MFMA tiles
+// One 16 x 16 output tile of C = Cin + op(A) op(B) (inner size Kd) by one wave
+// with 16x16x4 matrix-core instructions: FP32 for the mixed form, FP64 for the
+// plain one.  Lane l supplies A(i0 + l % 16, k0 + l / 16) and
+// B(k0 + l / 16, j0 + l % 16) per step of 4; its result register r holds
+// C(i0 + 4 (l / 16) + r, j0 + l % 16) in FP32 and C(i0 + l / 16 + 4 r,
+// j0 + l % 16) in FP64.  Entries outside Mr x Nc x Kd enter as zeros and are
+// not stored.
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ mf_f4 mfma16(float a, float b, mf_f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mf_d4 mfma16(double a, double b, mf_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <class R> struct MfAcc;
+template <> struct MfAcc<float> {
+  using type = mf_f4;
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+template <> struct MfAcc<double> {
+  using type = mf_d4;
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+
+template <int Kd, bool TA, bool TB, class R>
+__device__ __forceinline__ void mfma_tile(R* C, int ldc, const R* A, int lda, const R* Bp, int ldb, const R* Cin,
+                                          int ldcin, int Mr, int Nc, int i0, int j0, int lane) {
+  using V = typename MfAcc<R>::type;
+  const int li = lane & 15, lk = lane >> 4;
+  V acc;
 #pragma unroll
-  for (int a = 0; a < RT; ++a)
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + MfAcc<R>::row(lk, r), j = j0 + li;
+    acc[r] = (Cin && i < Mr && j < Nc) ? Cin[i * ldcin + j] : R(0);
+  }
+  const int ia = i0 + li, jb = j0 + li;
 #pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      acc[a][b] = (Cin && i < Mr && j < Nc) ? Cin[i * ldcin + j] : R(0);
-    }
-#pragma unroll 2
-  for (int k = 0; k < Kd; ++k) {
-    R av[RT], bv[CT];
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      const int i = tr + 16 * a;
-      av[a] = i < Mr ? (TA ? A[k * lda + i] : A[i * lda + k]) : R(0);
-    }
-#pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      const int j = tc + 16 * b;
-      bv[b] = j < Nc ? (TB ? Bp[j * ldb + k] : Bp[k * ldb + j]) : R(0);
-    }
-#pragma unroll
-    for (int a = 0; a < RT; ++a)
-#pragma unroll
-      for (int b = 0; b < CT; ++b) acc[a][b] += av[a] * bv[b];
+  for (int k0 = 0; k0 < Kd; k0 += 4) {
+    const int k = k0 + lk;
+    const R a = (ia < Mr && k < Kd) ? (TA ? A[k * lda + ia] : A[ia * lda + k]) : R(0);
+    const R b = (k < Kd && jb < Nc) ? (TB ? Bp[jb * ldb + k] : Bp[k * ldb + jb]) : R(0);
+    acc = mfma16(a, b, acc);
   }
 #pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      const int i = tr + 16 * a, j = tc + 16 * b;
-      if (i < Mr && j < Nc) C[i * ldc + j] = acc[a][b];
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + MfAcc<R>::row(lk, r), j = j0 + li;
+    if (i < Mr && j < Nc) C[i * ldc + j] = acc[r];
+  }
 }
 
 // ------------------------------------------------------------------ Jacobians
@@ -436,8 +447,15 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
     if (tid < N) sm.lx[tid] = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
     if (tid < M) sm.lu[tid] = R(2) * wu * w0.u[tid];
     // PA = P A, PB = P B
-    blk_gemm<N, N, N, false, false>(&sm.PA[0][0], LD, &sm.P[0][0], LD, &sm.A[0][0], LD, (const R*)nullptr, 0, tid);
-    blk_gemm<N, M, N, false, false>(&sm.PB[0][0], LDB, &sm.P[0][0], LD, &sm.Bm[0][0], LDB, (const R*)nullptr, 0, tid);
+    // nine 16 x 16 tiles of P A and three of P B over the four waves
+    for (int t = tid >> 6; t < 12; t += NW) {
+      if (t < 9)
+        mfma_tile<N, false, false>(&sm.PA[0][0], LD, &sm.P[0][0], LD, &sm.A[0][0], LD, (const R*)nullptr, 0, N, N,
+                                   (t / 3) * 16, (t % 3) * 16, tid & 63);
+      else
+        mfma_tile<N, false, false>(&sm.PB[0][0], LDB, &sm.P[0][0], LD, &sm.Bm[0][0], LDB, (const R*)nullptr, 0, N, M,
+                                   (t - 9) * 16, 0, tid & 63);
+    }
     __syncthreads();
     // Q_x = l_x + A^T p, Q_u = l_u + B^T p (before P is overwritten)
     if (tid < N + M) {
@@ -455,8 +473,14 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
     }
     __syncthreads();
     // Q_xx = clip(l_xx) + A^T (P A) into P; Q_uu = clip(l_uu) + B^T (P B); Q_ux = B^T (P A)
-    blk_gemm<N, N, N, true, false>(&sm.P[0][0], LD, &sm.A[0][0], LD, &sm.PA[0][0], LD, (const R*)nullptr, 0, tid);
-    blk_gemm<M, N, N, true, false>(&sm.Qux[0][0], LD, &sm.Bm[0][0], LDB, &sm.PA[0][0], LD, (const R*)nullptr, 0, tid);
+    for (int t = tid >> 6; t < 12; t += NW) {
+      if (t < 9)
+        mfma_tile<N, true, false>(&sm.P[0][0], LD, &sm.A[0][0], LD, &sm.PA[0][0], LD, (const R*)nullptr, 0, N, N,
+                                  (t / 3) * 16, (t % 3) * 16, tid & 63);
+      else
+        mfma_tile<N, true, false>(&sm.Qux[0][0], LD, &sm.Bm[0][0], LDB, &sm.PA[0][0], LD, (const R*)nullptr, 0, M, N,
+                                  0, (t - 9) * 16, tid & 63);
+    }
     if (tid < M * M) {
       const int i = tid / M, j = tid % M;
       R v = R(0);
@@ -473,7 +497,9 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       if (tid < M) Q::kp(w, k, s)[tid] = sm.kk[tid];
     }
     // C = Q_xx + Q_ux^T K into PA, p = Q_x + Q_ux^T k
-    blk_gemm<N, N, M, true, false>(&sm.PA[0][0], LD, &sm.Qux[0][0], LD, &sm.Kg[0][0], LD, &sm.P[0][0], LD, tid);
+    for (int t = tid >> 6; t < 9; t += NW)
+      mfma_tile<M, true, false>(&sm.PA[0][0], LD, &sm.Qux[0][0], LD, &sm.Kg[0][0], LD, &sm.P[0][0], LD, N, N,
+                                (t / 3) * 16, (t % 3) * 16, tid & 63);
     if (tid < N) {
       R v = sm.Qx[tid];
       for (int t = 0; t < M; ++t) v += sm.Qux[t][tid] * sm.kk[t];
