@@ -63,6 +63,8 @@ struct Launcher {
   hipError_t (*finalize)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
                          const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
                          hipStream_t st);
+  // device bytes per slot that ws_bytes holds beyond the lane layout
+  size_t slot_extra = 0;
 };
 
 const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);

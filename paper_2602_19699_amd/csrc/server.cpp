@@ -147,11 +147,13 @@ bool make_pool(cbic_server* srv, Pool* p) {
   p->lay = lane_layout(p->n, p->m, elem, p->Bcap, p->Tcap);
   SRV_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
   SRV_TRY(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
-  SRV_TRY(hipMalloc(&p->ws, p->lay.total));
+  // the launcher's workspace: the lane layout plus whatever it keeps per slot
+  const size_t wsb = p->L->ws_bytes(p->Bcap, p->Tcap);
+  SRV_TRY(hipMalloc(&p->ws, wsb));
   const size_t sb = staging_bytes(p->Bcap, p->Tcap, p->n, p->m);
   SRV_TRY(hipMalloc(&p->dbuf, sb));
   SRV_TRY(hipHostMalloc(&p->hbuf, sb, hipHostMallocDefault));
-  p->bytes = p->lay.total + sb;
+  p->bytes = wsb + sb;
   for (int pass = 0; pass < 2; ++pass) {
     char* q = pass ? p->hbuf : p->dbuf;
     int32_t** i32[] = {pass ? &p->h_list : &p->d_list, pass ? &p->h_adm : &p->d_adm, pass ? &p->h_T : &p->d_T,
@@ -442,7 +444,8 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   if (opts->struct_size != sizeof(cbic_solve_opts)) { set_error("opts.struct_size mismatch"); return CBIC_E_INVALID; }
   if (T < 1 || T > srv->opts.t_max) { set_error("T must be in 1..%d", srv->opts.t_max); return CBIC_E_INVALID; }
   if (opts->precision != CBIC_FP64 && opts->precision != CBIC_MIXED) { set_error("bad precision"); return CBIC_E_INVALID; }
-  if (!find_launcher(sys->kind, sys->n, sys->m, opts->precision, 0)) {
+  const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, 0);
+  if (!L) {
     set_error("no kernel for this system and precision");
     return CBIC_E_UNSUPPORTED;
   }
@@ -453,10 +456,9 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   r->x0.assign(h_x0, h_x0 + sys->n);
   if (h_U0) r->U0.assign(h_U0, h_U0 + size_t(T) * sys->m);
   r->opts = *opts;
-  r->bytes = footprint(sys->n, sys->m, opts->precision ? 4 : 8, T);
+  r->bytes = footprint(sys->n, sys->m, opts->precision ? 4 : 8, T) + L->slot_extra;
   // a request that can never fit: its own footprint plus its class pool over the cap
-  const int elem = opts->precision ? 4 : 8;
-  const size_t pool = lane_layout(sys->n, sys->m, elem, srv->opts.slots_per_class, srv->opts.t_max).total +
+  const size_t pool = L->ws_bytes(srv->opts.slots_per_class, srv->opts.t_max) +
                       staging_bytes(srv->opts.slots_per_class, srv->opts.t_max, sys->n, sys->m);
   if (r->bytes > srv->opts.mem_cap_bytes || pool > srv->opts.mem_cap_bytes) {
     set_error("request footprint %zu B (pool %zu B) exceeds the memory cap %zu B", r->bytes, pool,
