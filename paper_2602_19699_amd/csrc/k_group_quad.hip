@@ -9,7 +9,10 @@
 // column broadcast from its lane through a scalar register) in both
 // precisions.  The dynamics step needs a Cholesky of the 18 x 18 mass matrix
 // M(q) = A^T A + diag(1 + 0.1 sin q); a wave does it with its lanes holding
-// the rows.  Line-search trials run one per wave: in
+// the rows.  The dynamics Jacobians do not depend on P, so the sweep
+// evaluates them ahead of the recursion, CH steps at a time with every wave
+// taking its own steps, into per-slot blocks in HBM that the recursion then
+// reads back.  Line-search trials run one per wave: in
 // round r wave w tries alpha_j with j = 4 r + w, and the first accepted j is
 // taken, as in the sequential rule.  Trajectories and gains use the same
 // step-major workspace as the lane schedule.
@@ -23,6 +26,8 @@ constexpr int LD = 40;   // row stride of 37-wide LDS matrices
 constexpr int LDB = 13;  // row stride of 12-wide LDS matrices
 constexpr int NT = 256;  // threads per workgroup
 constexpr int NW = NT / 64;
+constexpr int DB = N * (N + M);  // derivative block [f_x | f_u], row-major 37 x 49
+constexpr int CH = 16;           // steps per chunk of precomputed derivative blocks
 
 // device block: [dt, w_u, w_T, w_q, w_v, M0 = A^T A (18x18), W1, W2, e(18), x_nom(37)]
 constexpr int O_DT = 0, O_WU = 1, O_WT = 2, O_WQ = 3, O_WV = 4, O_M0 = 5, O_W1 = O_M0 + 324,
@@ -119,7 +124,7 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
   const int ri = row ? lane : 0;
   // M = A^T A + diag(1 + 0.1 sin q); Cholesky with the rows on lanes, the
   // pivot column broadcast from its lane
-  R m[NV], invd[NV];
+  R m[NV];
 #pragma unroll
   for (int j = 0; j < NV; ++j) m[j] = row ? sm.M0[ri][j] : R(0);
 #pragma unroll
@@ -130,7 +135,7 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
     const R piv = bcast(m[j], j);
     const R ljj = dsqrt(piv);
     const R inv = R(1) / ljj;
-    invd[j] = inv;
+    if (lane == 0) ws.Li[j] = inv;
     const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
     m[j] = lij;
 #pragma unroll
@@ -143,9 +148,6 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
 #pragma unroll
     for (int j = 0; j < NV; ++j)
       if (j <= lane) ws.L[ri][j] = m[j];
-  if (lane == 0)
-#pragma unroll
-    for (int j = 0; j < NV; ++j) ws.Li[j] = invd[j];
   // bias forces and right-hand side r = S u - b
   R y = R(0);
   if (row) {
@@ -163,14 +165,14 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
   // L z = r (rows on lanes)
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
-    const R yj = bcast(y, j) * invd[j];
+    const R yj = bcast(y, j) * ws.Li[j];
     if (lane == j) y = yj;
     else if (lane > j) y -= m[j] * yj;
   }
   // L^T a = z
 #pragma unroll
   for (int j = NV - 1; j >= 0; --j) {
-    const R zj = bcast(y, j) * invd[j];
+    const R zj = bcast(y, j) * ws.Li[j];
     if (lane == j) y = zj;
     else if (lane < j) y -= ws.L[j][ri] * zj;
   }
@@ -252,6 +254,71 @@ __device__ __forceinline__ void mfma_tile(R* C, int ldc, const R* A, int lda, co
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + MfAcc<R>::row(lk, r), j = j0 + li;
     if (i < Mr && j < Nc) C[i * ldc + j] = acc[r];
+  }
+}
+
+// ------------------------------------------------------------------ wave Jacobians
+// [f_x | f_u] at (ws.x, ws.u) by one wave, after wave_dyn on that point (L, its
+// reciprocal diagonal, a, sin/cos and W2 cos q in ws), written row-major
+// (37 x 49) to dst.  Lane c < 48 owns column c of the right-hand sides
+// (0..17 -dD/dq with a and v held, 18..35 -dD/dv, 36..47 the actuation S),
+// solves it with M = L L^T in registers and writes the output column that
+// depends on it: c for c < 18, c + 1 otherwise.  Lane 48 writes column 18
+// (q_18 does not enter the dynamics; only the identity).
+template <class R>
+__device__ __forceinline__ void wave_jac(const Smem<R>& sm, const WaveScratch<R>& ws, R dt, int lane,
+                                         R* __restrict__ dst) {
+  if (lane < 48) {
+    const int c = lane;
+    R y[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      R v;
+      if (c < NV) {
+        v = -(sm.W1[i][c] * ws.c[c] - ws.x[NQ + i] * sm.W2[i][c] * ws.s[c]);
+        if (i == c) v -= R(0.1) * ws.c[i] * ws.a[i];
+      } else if (c < 2 * NV) {
+        v = (c - NV == i) ? -ws.w2c[i] : R(0);
+      } else {
+        v = (c - 2 * NV + 6 == i) ? R(1) : R(0);
+      }
+      y[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      R v0 = y[i], v1 = R(0);
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        if (k & 1) v1 += ws.L[i][k] * y[k];
+        else v0 -= ws.L[i][k] * y[k];
+      }
+      y[i] = (v0 - v1) * ws.Li[i];
+    }
+#pragma unroll
+    for (int i = NV - 1; i >= 0; --i) {
+      R v0 = y[i], v1 = R(0);
+#pragma unroll
+      for (int k = i + 1; k < NV; ++k) {
+        if (k & 1) v1 += ws.L[k][i] * y[k];
+        else v0 -= ws.L[k][i] * y[k];
+      }
+      y[i] = (v0 - v1) * ws.Li[i];
+    }
+    // d v+_i / d (x, u)_col = [col is the velocity column i] + dt y_i; rows:
+    // v+ (19..36), q+ = q + dt v+ (0..17), q_18+ = q_18 + dt e . v+
+    const int col = c < NV ? c : c + 1;
+    R se = R(0);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const R d = ((c >= NV && c < 2 * NV && c - NV == i) ? R(1) : R(0)) + dt * y[i];
+      se += sm.e[i] * d;
+      dst[(NQ + i) * (N + M) + col] = d;
+      dst[i * (N + M) + col] = ((col == i) ? R(1) : R(0)) + dt * d;
+    }
+    dst[NV * (N + M) + col] = dt * se;
+  } else if (lane == 48) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) dst[r * (N + M) + NV] = (r == NV) ? R(1) : R(0);
   }
 }
 
@@ -421,7 +488,7 @@ struct QW {  // workspace accessors (same layout as the lane schedule)
 // ------------------------------------------------------------------ backward sweep
 template <class R>
 __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
-                             int buf, R eps, int tid) {
+                             int buf, R eps, int tid, R* __restrict__ blk) {
   using Q = QW<R>;
   const R dt = R(prm[O_DT]);
   const R wq = R(prm[O_WQ]), wv = R(prm[O_WV]), wu = R(prm[O_WU]), wT = R(prm[O_WT]);
@@ -436,13 +503,35 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
     sm.P[tid][tid] = dmax(R(2) * wi, eps);
   }
   __syncthreads();
+  const int wid = tid >> 6, lane = tid & 63;
   for (int k = T - 1; k >= 0; --k) {
+    const int q = (T - 1 - k) % CH;
+    if (q == 0) {
+      // derivative blocks of the next CH steps, wave wid taking every fourth
+      // step (they do not depend on P)
+      WaveScratch<R>& wsw = sm.wv[wid];
+      for (int qq = wid; qq < CH && k - qq >= 0; qq += NW) {
+        if (lane < N) wsw.x[lane] = Q::xp(w, buf, k - qq, s)[lane];
+        if (lane < M) wsw.u[lane] = Q::up(w, buf, k - qq, s)[lane];
+        wave_sync();
+        wave_dyn(sm, wsw, dt, lane);
+        wave_jac(sm, wsw, dt, lane, blk + qq * DB);
+        wave_sync();
+      }
+      __syncthreads();
+    }
     if (tid < N) w0.x[tid] = Q::xp(w, buf, k, s)[tid];
     if (tid < M) w0.u[tid] = Q::up(w, buf, k, s)[tid];
+    {
+      const R* src = blk + q * DB;
+      for (int i = tid; i < DB; i += NT) {
+        const int r = i / (N + M), c = i - r * (N + M);
+        const R v = src[i];
+        if (c < N) sm.A[r][c] = v;
+        else sm.Bm[r][c - N] = v;
+      }
+    }
     __syncthreads();
-    if (tid < 64) wave_dyn(sm, w0, dt, tid);
-    __syncthreads();
-    jacobians(sm, dt, tid);
     // cost derivatives (diagonal Hessians)
     if (tid < N) sm.lx[tid] = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
     if (tid < M) sm.lu[tid] = R(2) * wu * w0.u[tid];
@@ -630,7 +719,8 @@ __global__ void __launch_bounds__(NT) quad_init(const double* __restrict__ prm, 
 template <class R>
 __global__ void __launch_bounds__(NT, 1) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                     const int32_t* __restrict__ slots, SolveParams sp,
-                                                    int iters_this_launch, double* __restrict__ trace) {
+                                                    int iters_this_launch, double* __restrict__ trace,
+                                                    R* __restrict__ dblk) {
   __shared__ Smem<R> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
   if (g >= nslots) return;
@@ -653,7 +743,7 @@ __global__ void __launch_bounds__(NT, 1) quad_iterate(const double* __restrict__
       break;
     }
     ++nsweep;
-    const uint32_t bad = backward(sm, prm, w, s, T, buf, eps, tid);
+    const uint32_t bad = backward(sm, prm, w, s, T, buf, eps, tid, dblk + size_t(s) * CH * DB);
     if (bad) {
       st = bad;
       break;
@@ -853,7 +943,13 @@ __global__ void __launch_bounds__(NT, 1) quad_final(const double* __restrict__ p
 
 template <class R>
 struct QuadLaunch {
-  static size_t ws_bytes(int Bcap, int Tcap) { return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total; }
+  // the lane layout, then per slot CH derivative blocks
+  static size_t ws_bytes(int Bcap, int Tcap) {
+    return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total + size_t(Bcap) * CH * DB * sizeof(R);
+  }
+  static R* blocks(void* base, int Bcap, int Tcap) {
+    return reinterpret_cast<R*>(static_cast<char*>(base) + lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total);
+  }
 
   static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
@@ -871,7 +967,7 @@ struct QuadLaunch {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap);
     hipLaunchKernelGGL(quad_iterate<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, to_dev(sp), G,
-                       trace);
+                       trace, blocks(base, Bcap, Tcap));
     return hipGetLastError();
   }
 
@@ -887,7 +983,8 @@ struct QuadLaunch {
   }
 
   static const Launcher* get() {
-    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_GROUP, &ws_bytes, &init, &iterate, &finalize};
+    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_GROUP, &ws_bytes, &init, &iterate, &finalize,
+                            size_t(CH) * DB * sizeof(R)};
     return &L;
   }
 };
