@@ -21,14 +21,23 @@ enum : uint32_t {
 };
 
 // ---------------------------------------------------------------- math by precision
+// FP64 (the plain form) uses the correctly rounded library functions.  FP32
+// (the mixed form's rollouts and derivatives, device only) uses the hardware
+// exponential and sine/cosine: their error, a few ulp for exp and about 2^-20
+// absolute for sin/cos at the angles met here, stays far below the mixed
+// form's cost tolerance.
 CBIC_HD __forceinline__ double dexp(double v) { return exp(v); }
-CBIC_HD __forceinline__ float dexp(float v) { return expf(v); }
+__device__ __forceinline__ float dexp(float v) { return __expf(v); }
 CBIC_HD __forceinline__ double dsin(double v) { return sin(v); }
-CBIC_HD __forceinline__ float dsin(float v) { return sinf(v); }
+__device__ __forceinline__ float dsin(float v) { return __sinf(v); }
 CBIC_HD __forceinline__ double dcos(double v) { return cos(v); }
-CBIC_HD __forceinline__ float dcos(float v) { return cosf(v); }
+__device__ __forceinline__ float dcos(float v) { return __cosf(v); }
 CBIC_HD __forceinline__ void dsincos(double v, double* s, double* c) { sincos(v, s, c); }
-CBIC_HD __forceinline__ void dsincos(float v, float* s, float* c) { sincosf(v, s, c); }
+__device__ __forceinline__ void dsincos(float v, float* s, float* c) { __sincosf(v, s, c); }
+// the library sine/cosine in both precisions (measured faster than the
+// hardware pair inside the quadruped's large kernel)
+CBIC_HD __forceinline__ void dsincos_lib(double v, double* s, double* c) { sincos(v, s, c); }
+__device__ __forceinline__ void dsincos_lib(float v, float* s, float* c) { sincosf(v, s, c); }
 CBIC_HD __forceinline__ double dsqrt(double v) { return sqrt(v); }
 CBIC_HD __forceinline__ float dsqrt(float v) { return sqrtf(v); }
 CBIC_HD __forceinline__ bool dfinite(double v) { return isfinite(v); }

@@ -115,7 +115,7 @@ template <class R>
 __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) {
   if (lane < NV) {
     R sn, cs;
-    dsincos(ws.x[lane], &sn, &cs);
+    dsincos_lib(ws.x[lane], &sn, &cs);
     ws.s[lane] = sn;
     ws.c[lane] = cs;
   }
