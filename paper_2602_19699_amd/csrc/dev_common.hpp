@@ -163,7 +163,10 @@ CBIC_HD __forceinline__ void clip_sym3(R h[9], R eps) {
 // In-place lower Cholesky of the M x M symmetric matrix held in the upper
 // triangle of a (a[i][j], j >= i).  Returns false on a non-positive or
 // non-finite pivot.  L is returned in l[i][j], j <= i; diag holds 1/L_ii.
-template <int M>
+// NR Newton steps refine the reciprocal square roots: two give full FP64
+// accuracy, one (relative error near 2^-44) suffices when the results are
+// rounded to FP32.
+template <int M, int NR = 2>
 __device__ __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], double inv_diag[M]) {
   bool ok = true;
 #pragma unroll
@@ -173,11 +176,11 @@ __device__ __forceinline__ bool chol_fp64(const double a[M][M], double l[M][M], 
     for (int k = 0; k < j; ++k) d -= l[j][k] * l[j][k];
     ok = ok && (d > 0.0) && isfinite(d);
     // 1/sqrt(d) from the hardware estimate (relative error below 2^-22) and
-    // two Newton steps y <- y (3 - d y^2) / 2, which take it to a few ulp;
+    // Newton steps y <- y (3 - d y^2) / 2, each squaring the relative error;
     // sqrt(d) = d / sqrt(d)
     double inv = __builtin_amdgcn_rsq(d);
-    inv = inv * (1.5 - 0.5 * d * inv * inv);
-    inv = inv * (1.5 - 0.5 * d * inv * inv);
+#pragma unroll
+    for (int it = 0; it < NR; ++it) inv = inv * (1.5 - 0.5 * d * inv * inv);
     const double ljj = d * inv;
     l[j][j] = ljj;
     inv_diag[j] = inv;
@@ -208,6 +211,27 @@ __device__ __forceinline__ void chol_solve_fp64(const double l[M][M], const doub
 #pragma unroll
     for (int k = i + 1; k < M; ++k) v -= l[k][i] * b[k];
     b[i] = v * inv_diag[i];
+  }
+}
+
+// Solve (L L^T) y = b and return -y in b: the sign folds into the reciprocal
+// diagonal of the back substitution (z = -y: z_i = (w_i + sum_k L_ki z_k) (-1/L_ii)),
+// which rounds exactly as negating the solution would.
+template <int M>
+__device__ __forceinline__ void chol_solve_neg_fp64(const double l[M][M], const double inv_diag[M], double b[M]) {
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= l[i][k] * b[k];
+    b[i] = v * inv_diag[i];
+  }
+#pragma unroll
+  for (int i = M - 1; i >= 0; --i) {
+    double v = b[i];
+#pragma unroll
+    for (int k = i + 1; k < M; ++k) v += l[k][i] * b[k];
+    b[i] = v * -inv_diag[i];
   }
 }
 

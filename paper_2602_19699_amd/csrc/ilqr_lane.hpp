@@ -152,30 +152,32 @@ struct Lane {
         Qux[i][j] = q;
       }
     }
-    // Cholesky of Q_uu and the gains, in FP64
+    // Cholesky of Q_uu and the gains, in FP64 (one Newton step on the
+    // reciprocal pivots when the gains are rounded to FP32); the checks are on
+    // the gains as stored, so an FP32 overflow is caught as well
     double Lc[M][M], invd[M];
-    if (!chol_fp64<M>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    if (!chol_fp64<M, sizeof(R) == 4 ? 1 : 2>(Quu, Lc, invd)) return ST_CHOL_FAIL;
     R Kk[M][N], kk[M];
     bool fin = true;
     {
       double col[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
-      chol_solve_fp64<M>(Lc, invd, col);
+      chol_solve_neg_fp64<M>(Lc, invd, col);
 #pragma unroll
       for (int i = 0; i < M; ++i) {
-        kk[i] = R(-col[i]);
-        fin = fin && isfinite(col[i]);
+        kk[i] = R(col[i]);
+        fin = fin && dfinite(kk[i]);
       }
 #pragma unroll
       for (int j = 0; j < N; ++j) {
 #pragma unroll
         for (int i = 0; i < M; ++i) col[i] = double(Qux[i][j]);
-        chol_solve_fp64<M>(Lc, invd, col);
+        chol_solve_neg_fp64<M>(Lc, invd, col);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-          Kk[i][j] = R(-col[i]);
-          fin = fin && isfinite(col[i]);
+          Kk[i][j] = R(col[i]);
+          fin = fin && dfinite(Kk[i][j]);
         }
       }
     }
@@ -234,7 +236,7 @@ struct Lane {
       ld(xT, xp(w, buf, T, s));
       mdl.term_derivs(xT, p, P, eps, true);
     }
-    if (staged) {
+    if constexpr (staged) {
       // (x_k, u_k) of the lane's steps of the next chunk are loaded while the
       // current chunk's recursion runs
       constexpr int PB = C / GL > 0 ? C / GL : 1;
