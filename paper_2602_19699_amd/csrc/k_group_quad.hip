@@ -825,7 +825,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
 }
 
 template <class R>
-__global__ void __launch_bounds__(NT, 1) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
+__global__ void __launch_bounds__(NT, 2) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                   const int32_t* __restrict__ slots, int Tmax, int max_iter,
                                                   int lookahead, FinalOut o) {
   using Q = QW<R>;
