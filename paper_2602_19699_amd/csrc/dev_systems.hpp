@@ -22,6 +22,9 @@ struct PointMass {
   static constexpr int N = 4, M = 2;
   static constexpr int NPRM = 16;
   static constexpr bool kNonNegCost = true;
+  // a rollout step costs little next to the stores of GL trial trajectories:
+  // the line search writes only alpha = 1 and re-rolls another accepted step
+  static constexpr bool kOwnTrialBuffers = false;
   // structural nonzeros of f_x and f_u (A = [[I, dt I], [0, I]], B = [[dt^2 I], [dt I]])
   __host__ __device__ static constexpr bool a_nz(int i, int j) { return i == j || j == i + 2; }
   __host__ __device__ static constexpr bool b_nz(int i, int j) { return (i & 1) == j; }
@@ -164,6 +167,9 @@ struct Arm3 {
   static constexpr int N = 6, M = 3;
   static constexpr int NPRM = 19;
   static constexpr bool kNonNegCost = true;
+  // a rollout step is expensive: every trial lane writes its own trajectory
+  // so that an accepted step needs no second rollout
+  static constexpr bool kOwnTrialBuffers = true;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 
@@ -487,6 +493,7 @@ struct LinQuad {
                        OXR = OQT + N * N, OQC = OXR + N, ORC = OQC + N * N, OQTC = ORC + M * M,
                        NPRM = OQTC + N * N;
   static constexpr bool kNonNegCost = false;
+  static constexpr bool kOwnTrialBuffers = false;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 

@@ -35,11 +35,11 @@ struct LaneState {
   int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
   int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
   // trajectories and gains, step-major
-  R* X;   // [2][Tcap+1][Bcap][N]
-  R* U;   // [2][Tcap][Bcap][M]
+  R* X;   // [nbuf][Tcap+1][Bcap][N]: the iterate (buffer cur) and trial trajectories
+  R* U;   // [nbuf][Tcap][Bcap][M]
   R* K;   // [Tcap][Bcap][M][N]
   R* kf;  // [Tcap][Bcap][M]
-  int Bcap, Tcap;
+  int Bcap, Tcap, nbuf;
 };
 
 struct SolveParams {
@@ -334,7 +334,7 @@ struct Lane {
 
   // Closed-loop rollout with step alpha from the iterate in `buf`; returns
   // J_hat in FP64 (NaN-propagating).  With `write` the trial trajectory goes to
-  // the other buffer.  With non-negative costs a trial stops as soon as its
+  // buffer `nb`.  With non-negative costs a trial stops as soon as its
   // partial sum reaches J: its total could only be larger, so the
   // accept/reject decision is unchanged.
   //
@@ -344,11 +344,10 @@ struct Lane {
   // rolled out, so the loads' latency is covered by a chunk of work.  The
   // group keeps streaming while any of its lanes is still rolling out.
   template <int GL>
-  __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R alpha,
-                                 double Jcur, bool write, int& steps, R* ring, int r, int gbase) {
+  __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, int nb,
+                                 R alpha, double Jcur, bool write, int& steps, R* ring, int r, int gbase) {
     constexpr int CT = GL * PT;
     const unsigned long long gmask = (GL >= 64) ? ~0ull : ((1ull << GL) - 1ull);
-    const int nb = buf ^ 1;
     R xh[N];
     ld(xh, xp(w, buf, 0, s));
     double Jh = 0.0;
@@ -441,8 +440,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   R x[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = R(x0[size_t(b) * N + i]);
-  LN::st(LN::xp(w, 0, 0, s), x);
-  LN::st(LN::xp(w, 1, 0, s), x);
+  for (int b = 0; b < w.nbuf; ++b) LN::st(LN::xp(w, b, 0, s), x);
   double J = 0.0;
   for (int k = 0; k < T; ++k) {
     R u[M];
@@ -479,8 +477,8 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 // arithmetic on identical data; one lane stores the gains) and split the line
 // search: in round q lane r tries alpha_j, j = q*GL + r.  The first j whose
 // J_hat < J is taken (a wave ballot over the group), which is exactly the
-// sequential rule; the accepted step is then rolled out once more to write
-// it, unless it was alpha = 1, whose lane wrote while it ran.  `slots`
+// sequential rule.  Every lane writes its trial into a trajectory buffer of
+// its own, and the accepted lane's buffer becomes the iterate.  `slots`
 // (optional) maps the group index to a slot, for sparse slot sets.
 template <class Sys, class R, int GL>
 __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
@@ -529,57 +527,96 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
       st = bad;
       break;
     }
-    // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
-    // whose lane wrote while trying it) one commit rollout that writes it; one
-    // call site of the rollout keeps the register footprint down
-    int acc = -1;
+    int acc = -1, nbuf_acc = buf;
     double Jn = J;
-    bool commit = false;
-    for (int j0 = 0;;) {
-      const int j = commit ? acc : j0 + r;
-      double Jh = __builtin_nan("");
-      int steps = 0;
-      if (commit || j < sp.ls_trials) {
-        double alpha = 1.0;
-        for (int q = 0; q < j; ++q) alpha *= sp.beta;
-        // alpha = 1 (j == 0) is written while it runs, as is every trial of a
-        // one-lane group; the commit is written by the group's lead lane
-        const bool wr = commit ? lead : (j == 0 || GL == 1);
-        Jh = LN::template trial<GL>(mdl, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, wr, steps, stage, r,
-                                    gbase);
-      }
-      ++npass;
-      if (commit) {
-        Jn = Jh;
-        nread += steps;
-        nwrite += steps;
-        break;
-      }
-      // the lanes of a group read the same data: a round moves as many steps
-      // as its longest trial; only the alpha = 1 trial (or every trial of a
-      // one-lane group) writes
-      if (j0 == 0 || GL == 1) nwrite += (GL == 1) ? steps : __shfl(steps, gbase, 64);
-      int longest = steps;
+    if constexpr (Sys::kOwnTrialBuffers) {
+      // rounds of GL parallel trials; lane r of the group rolls out into its own
+      // trajectory buffer, so the accepted trial is already written and becomes
+      // the iterate (no second rollout); one call site of the rollout keeps the
+      // register footprint down
+      const int wb = (buf + 1 + r) % w.nbuf;  // never the iterate's buffer (GL < nbuf)
+      for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += GL) {
+        const int j = j0 + r;
+        double Jh = __builtin_nan("");
+        int steps = 0;
+        if (j < sp.ls_trials) {
+          double alpha = 1.0;
+          for (int q = 0; q < j; ++q) alpha *= sp.beta;
+          Jh = LN::template trial<GL>(mdl, w, s, T, buf, wb, R(alpha), J, true, steps, stage, r, gbase);
+        }
+        ++npass;
+        // every lane writes what it rolled out; the lanes of a group read the
+        // same data, so a round reads as many steps as its longest trial
+        int total = steps, longest = steps;
 #pragma unroll
-      for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
-      nread += longest;
-      const bool ok = isfinite(Jh) && Jh < J;
-      unsigned long long bits = __ballot(ok);
-      bits = (bits >> gbase) & ((1ull << GL) - 1);
-      if (bits) {
-        const int rs = __ffsll(bits) - 1;
-        acc = j0 + rs;
-        Jn = __shfl(Jh, gbase + rs, 64);
+        for (int o = 1; o < GL; o <<= 1) {
+          total += __shfl_xor(total, o, 64);
+          longest = max(longest, __shfl_xor(longest, o, 64));
+        }
+        nwrite += total;
+        nread += longest;
+        const bool ok = isfinite(Jh) && Jh < J;
+        unsigned long long bits = __ballot(ok);
+        bits = (bits >> gbase) & ((GL >= 64) ? ~0ull : ((1ull << GL) - 1ull));
+        if (bits) {
+          const int rs = __ffsll(bits) - 1;
+          acc = j0 + rs;
+          Jn = __shfl(Jh, gbase + rs, 64);
+          nbuf_acc = (buf + 1 + rs) % w.nbuf;
+        }
       }
-      j0 += GL;
-      if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
-      if (acc > 0) commit = true;
+    } else {
+      // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
+      // whose lane wrote while trying it) one commit rollout that writes it; one
+      // call site of the rollout keeps the register footprint down
+      bool commit = false;
+      for (int j0 = 0;;) {
+        const int j = commit ? acc : j0 + r;
+        double Jh = __builtin_nan("");
+        int steps = 0;
+        if (commit || j < sp.ls_trials) {
+          double alpha = 1.0;
+          for (int q = 0; q < j; ++q) alpha *= sp.beta;
+          // alpha = 1 (j == 0) is written while it runs, as is every trial of a
+          // one-lane group; the commit is written by the group's lead lane
+          const bool wr = commit ? lead : (j == 0 || GL == 1);
+          Jh = LN::template trial<GL>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr, steps,
+                                      stage, r, gbase);
+        }
+        ++npass;
+        if (commit) {
+          Jn = Jh;
+          nread += steps;
+          nwrite += steps;
+          break;
+        }
+        // the lanes of a group read the same data: a round moves as many steps
+        // as its longest trial; only the alpha = 1 trial (or every trial of a
+        // one-lane group) writes
+        if (j0 == 0 || GL == 1) nwrite += (GL == 1) ? steps : __shfl(steps, gbase, 64);
+        int longest = steps;
+#pragma unroll
+        for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+        nread += longest;
+        const bool ok = isfinite(Jh) && Jh < J;
+        unsigned long long bits = __ballot(ok);
+        bits = (bits >> gbase) & ((1ull << GL) - 1);
+        if (bits) {
+          const int rs = __ffsll(bits) - 1;
+          acc = j0 + rs;
+          Jn = __shfl(Jh, gbase + rs, 64);
+        }
+        j0 += GL;
+        if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
+        if (acc > 0) commit = true;
+      }
+      nbuf_acc = buf ^ 1;
     }
     if (acc < 0) {
       st = ST_LS_FAILED;
       break;
     }
-    buf ^= 1;
+    buf = nbuf_acc;
     const double Jold = J;
     J = Jn;
     ++iters;

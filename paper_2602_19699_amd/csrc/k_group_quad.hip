@@ -958,7 +958,7 @@ struct QuadLaunch {
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
                          int max_iter, double* trace, hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,
                        x0, U0, max_iter, trace);
     return hipGetLastError();
@@ -968,7 +968,7 @@ struct QuadLaunch {
                             const int32_t* slots, const SolveParamsH& sp, int G, int, double* trace,
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     hipLaunchKernelGGL(quad_iterate<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, to_dev(sp), G,
                        trace, blocks(base, Bcap, Tcap));
     return hipGetLastError();
@@ -978,7 +978,7 @@ struct QuadLaunch {
                              const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
                              hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
     hipLaunchKernelGGL(quad_final<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, max_iter,
                        lookahead, fo);

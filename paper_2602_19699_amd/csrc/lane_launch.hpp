@@ -5,9 +5,16 @@
 
 namespace cbic {
 
+// Trajectory buffers of the lane kernels: for a system whose trial lanes
+// write their own trajectories, the iterate plus one per lane of the widest
+// group (the accepted trial is then already written wherever it was found);
+// otherwise the iterate and one trial trajectory.
+template <class Sys>
+constexpr int lane_bufs() { return Sys::kOwnTrialBuffers ? 17 : 2; }
+
 template <class R>
-inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap) {
-  const LaneLayout L = lane_layout(N, M, int(sizeof(R)), Bcap, Tcap);
+inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap, int nbuf) {
+  const LaneLayout L = lane_layout(N, M, int(sizeof(R)), Bcap, Tcap, nbuf);
   char* b = static_cast<char*>(base);
   LaneState<R> w;
   w.T = reinterpret_cast<int32_t*>(b + L.T);
@@ -23,6 +30,7 @@ inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap) {
   w.kf = reinterpret_cast<R*>(b + L.kf);
   w.Bcap = Bcap;
   w.Tcap = Tcap;
+  w.nbuf = nbuf;
   return w;
 }
 
@@ -43,13 +51,15 @@ struct LaneLaunch {
   static constexpr int N = Sys::N, M = Sys::M;
   static constexpr int WG = 64;
 
-  static size_t ws_bytes(int Bcap, int Tcap) { return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap).total; }
+  static size_t ws_bytes(int Bcap, int Tcap) {
+    return lane_layout(N, M, int(sizeof(R)), Bcap, Tcap, lane_bufs<Sys>()).total;
+  }
 
   static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
                          int max_iter, double* trace, hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     hipLaunchKernelGGL((lane_init<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
                        slots, Tmax, Tin, perm, x0, U0, max_iter, trace);
     return hipGetLastError();
@@ -68,7 +78,7 @@ struct LaneLaunch {
                             const int32_t* slots, const SolveParamsH& sp, int G, int group, double* trace,
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     const SolveParams d = to_dev(sp);
     switch (group) {
       case 1: return iterate_g<1>(prm, w, nthreads, slots, d, G, trace, st);
@@ -84,7 +94,7 @@ struct LaneLaunch {
                              const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
                              hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap);
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
     hipLaunchKernelGGL((lane_final<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
                        slots, Tmax, max_iter, lookahead, fo);
@@ -92,7 +102,8 @@ struct LaneLaunch {
   }
 
   static const Launcher* get() {
-    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_LANE, &ws_bytes, &init, &iterate, &finalize};
+    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_LANE, &ws_bytes, &init, &iterate, &finalize, 0,
+                            lane_bufs<Sys>()};
     return &L;
   }
 };

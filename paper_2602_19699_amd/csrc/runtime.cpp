@@ -28,7 +28,7 @@ const char* last_error() { return g_err; }
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap) {
+LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf) {
   LaneLayout L{};
   size_t o = 0;
   const size_t B = size_t(Bcap);
@@ -39,8 +39,8 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap) {
   L.status = o; o = align256(o + 4 * B);
   L.cur = o; o = align256(o + 4 * B);
   L.work = o; o = align256(o + 16 * B);
-  L.X = o; o = align256(o + size_t(elem) * 2 * (Tcap + 1) * B * N);
-  L.U = o; o = align256(o + size_t(elem) * 2 * Tcap * B * M);
+  L.X = o; o = align256(o + size_t(elem) * nbuf * (Tcap + 1) * B * N);
+  L.U = o; o = align256(o + size_t(elem) * nbuf * Tcap * B * M);
   L.K = o; o = align256(o + size_t(elem) * Tcap * B * M * N);
   L.kf = o; o = align256(o + size_t(elem) * Tcap * B * M);
   L.total = o;

@@ -25,7 +25,8 @@ struct LaneLayout {
   size_t X, U, K, kf;
   size_t total;
 };
-LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap);
+// nbuf trajectory buffers (X, U): the iterate and the trial trajectories
+LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf = 2);
 
 // Group schedule (one workgroup per instance) for large systems.
 struct GroupLayout {
@@ -65,6 +66,8 @@ struct Launcher {
                          hipStream_t st);
   // device bytes per slot that ws_bytes holds beyond the lane layout
   size_t slot_extra = 0;
+  // trajectory buffers of the lane layout
+  int nbuf = 2;
 };
 
 const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);

@@ -49,8 +49,8 @@ struct Result {
 
 // per-request device footprint: the slot's state and the trajectory, gain and
 // trial-trajectory storage for its own horizon
-size_t footprint(int n, int m, int elem, int T) {
-  const size_t words = 2 * size_t(T + 1) * n + 2 * size_t(T) * m + size_t(T) * m * n + size_t(T) * m;
+size_t footprint(int n, int m, int elem, int T, int nbuf) {
+  const size_t words = size_t(nbuf) * (T + 1) * n + size_t(nbuf) * T * m + size_t(T) * m * n + size_t(T) * m;
   return words * elem + 40;
 }
 
@@ -144,7 +144,7 @@ size_t staging_bytes(int B, int T, int n, int m) {
 
 bool make_pool(cbic_server* srv, Pool* p) {
   const int elem = p->precision ? 4 : 8;
-  p->lay = lane_layout(p->n, p->m, elem, p->Bcap, p->Tcap);
+  p->lay = lane_layout(p->n, p->m, elem, p->Bcap, p->Tcap, p->L->nbuf);
   SRV_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
   SRV_TRY(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
   // the launcher's workspace: the lane layout plus whatever it keeps per slot
@@ -456,7 +456,7 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   r->x0.assign(h_x0, h_x0 + sys->n);
   if (h_U0) r->U0.assign(h_U0, h_U0 + size_t(T) * sys->m);
   r->opts = *opts;
-  r->bytes = footprint(sys->n, sys->m, opts->precision ? 4 : 8, T) + L->slot_extra;
+  r->bytes = footprint(sys->n, sys->m, opts->precision ? 4 : 8, T, L->nbuf) + L->slot_extra;
   // a request that can never fit: its own footprint plus its class pool over the cap
   const size_t pool = L->ws_bytes(srv->opts.slots_per_class, srv->opts.t_max) +
                       staging_bytes(srv->opts.slots_per_class, srv->opts.t_max, sys->n, sys->m);
