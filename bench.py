@@ -144,9 +144,11 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
     Jref = ref.J.cpu().numpy()
     n, m = sysm.n, sysm.m
     results = {}
+    Jforms = {}
     for fname, opts in forms.items():
         out, ms, lat, ph, width = time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup)
         J = out.J.cpu().numpy()
+        Jforms[fname] = J
         work = out.work.cpu().numpy()
         rel = np.abs(J - Jref) / np.abs(Jref)
         conv = int(np.sum(rel <= 1e-4))
@@ -170,8 +172,16 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
         fo = forms[cpu_opts_form]
         oo = orc.Options(max_iter=fo.max_iter, stop_mode=fo.stop_mode, rtol=max(fo.rtol, 1e-10))
         t0 = time.perf_counter()
-        orc.solve_batch(kind, params, x0[:ns], T, T=None if Tb is None else Tb[:ns], opts=oo, nthreads=threads)
+        ores = orc.solve_batch(kind, params, x0[:ns], T, T=None if Tb is None else Tb[:ns], opts=oo, nthreads=threads)
         dt = time.perf_counter() - t0
+        # every form's cost against the FP64 oracle on the sampled instances
+        Jo = np.asarray(ores.J)
+        for fname, J in Jforms.items():
+            r = np.abs(J[:ns] - Jo) / np.abs(Jo)
+            results[fname]["vs_oracle"] = {
+                "oracle_form": cpu_opts_form, "instances": int(ns), "max_rel_cost": float(np.nanmax(r)),
+                "median_rel_cost": float(np.nanmedian(r)), "frac_within_1e-9": float(np.mean(r <= 1e-9)),
+                "frac_within_1e-4": float(np.mean(r <= 1e-4))}
         cpu = {"value": round(ns / dt, 2), "unit": "solves/s", "cores": threads, "kind": "oracle",
                "sample": f"{'all' if ns == B else 'first %d of the' % ns} {B} instances, FP64, "
                          f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed %d iterations' % oo.max_iter}"
@@ -218,7 +228,8 @@ def serving(ctx, rates, seconds):
 
 
 def fmt(d):
-    return {k: (float(f"{v:.6g}") if isinstance(v, float) else v) for k, v in d.items()}
+    return {k: (float(f"{v:.6g}") if isinstance(v, float) else fmt(v) if isinstance(v, dict) else v)
+            for k, v in d.items()}
 
 
 def main():
@@ -293,7 +304,8 @@ def main():
           "pm64": "point-mass OCP (n=4, m=2), B=64, T=100",
           "arm4k": "planar 3-link arm (n=6, m=3), B=4096, T uniform 50..200",
           "quad1k": "quadruped-sized system (n=37, m=12), B=1024, T=100"}[nme]
-    serve = None if (args.quick or args.only or args.workload) else serving(ctx, rates=(2000, 10000), seconds=1.5)
+    serve = None if (args.quick or args.only or args.workload) else serving(
+        ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=1.5)
     line = {
         "metric": METRIC,
         "value": round(h["converged_solves_per_s"], 1),
