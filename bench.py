@@ -49,14 +49,14 @@ LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_laun
 COUNTERS = {
     ("pm16k", "mixed_tol1e-7", "lane_iterate<PointMass,float,8>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "122a5a677c1e48b2e187a1a54e3bb8e9f0c50025ee9e1944336c7ebbc698dba8",
-        "fetch_kib": 693801.0, "write_kib": 501458.0,
+        "sha256": "f5cf0e34aa78d199a2035e70242d5437dd4546a4881caa0ce97dc21d38fdb747",
+        "fetch_kib": 695052.1, "write_kib": 501434.0,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "7640557902355b06fad8b6351ac5b302b94e2887828aeaa626c73c739dd499be",
-        "fetch_kib": 4648640.0, "write_kib": 3108890.0,
+        "sha256": "ee22bd46394229339ecd7cd78fa7b5539a45a281dad26cbf97fa14c43b5f97a2",
+        "fetch_kib": 6172815.3, "write_kib": 16491061.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
