@@ -143,6 +143,17 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
     torch.cuda.synchronize(dev)
     Jref = ref.J.cpu().numpy()
     n, m = sysm.n, sysm.m
+    # iteration budget (paper Sec. IV-A): the 99th percentile of a
+    # tolerance-stop solve's iteration counts under a cap of 1000, then the
+    # fixed-budget FP64 solve at that budget timed as a form of its own
+    calib = None
+    if "fp64_fixed50" in forms:
+        t0 = time.perf_counter()
+        p99, p50, hist = cbic.calibrate_max_iter(ctx, sysm, x0d, T, T=Td, opts=cbic.Options(rtol=1e-10), cap=1000)
+        calib = {"cap": 1000, "rtol": 1e-10, "p99": p99, "p50": p50, "max": int(np.nonzero(hist)[0].max()),
+                 "frac_at_cap": float(hist[1000] / hist.sum()), "seconds": round(time.perf_counter() - t0, 3)}
+        if p99 < 1000:  # a budget at the cap would only time the cap
+            forms = {**forms, "fp64_fixed_p99": cbic.Options(max_iter=p99)}
     results = {}
     Jforms = {}
     for fname, opts in forms.items():
@@ -187,7 +198,7 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
                          f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed %d iterations' % oo.max_iter}"
                          f", {threads} OpenMP threads, {dt:.2f} s"}
     sysm.close()
-    return results, best, cpu
+    return results, best, cpu, calib
 
 
 def roofline_for(name, form, res, form_opts):
@@ -289,11 +300,11 @@ def main():
     head = None
     for nme in names:
         steps = args.steps if nme in ("pm16k", "pm64") else max(3, args.steps // 4)
-        res, best, cpu = workload_bench(ctx, nme, forms[nme], steps, args.warmup, cpu_cfg[nme][0],
-                                        cpu_cfg[nme][1], quick=args.quick or bool(args.only))
+        res, best, cpu, calib = workload_bench(ctx, nme, forms[nme], steps, args.warmup, cpu_cfg[nme][0],
+                                               cpu_cfg[nme][1], quick=args.quick or bool(args.only))
         entry = {"best_form": best, "forms": {k: fmt(v) for k, v in res.items()},
                  "roofline": roofline_for(nme, best, res[best], forms[nme][best]), "cpu_baseline": cpu,
-                 "steps": steps}
+                 "max_iter_calibration": calib, "steps": steps}
         if head is None:
             head = (nme, res, best, entry)
         else:
@@ -324,6 +335,7 @@ def main():
         "forms": entry["forms"],
         "roofline": entry["roofline"],
         "cpu_baseline": entry["cpu_baseline"],
+        "max_iter_calibration": entry["max_iter_calibration"],
         "workloads": other,
         "serving": serve,
     }

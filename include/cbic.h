@@ -203,6 +203,22 @@ cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, int32_t B, 
                           const double* d_x0, const double* d_U0, const cbic_solve_opts* opts, void* stream,
                           int32_t* best_group, double* best_ms);
 
+/* Iteration-budget calibration (paper Sec. IV-A).  Solves the batch (same
+ * arguments as cbic_solve_batch, zero warm start) with the relative-decrease
+ * stop (opts->rtol) and at most `cap` iterations (1..100000; the paper uses
+ * 1000), then returns the nearest-rank 99th (*p99) and 50th (*p50) percentiles
+ * of the per-instance accepted-iteration counts: the budget for batches
+ * warm-started naively and from a trained actor, respectively.  An instance
+ * stopped by the cap counts as `cap`; instances with an invalid horizon are
+ * left out.  opts supplies precision, eps and the line search; its stop_mode
+ * and max_iter are replaced.  hist (optional, host, cap + 1 entries) receives
+ * the histogram of the counts.  Blocks until done; allocates scratch outputs.
+ * Errors: CBIC_E_INVALID (NULL required pointer, B or T_max < 1, cap out of
+ * range, no valid instance), CBIC_E_OOM, CBIC_E_HIP. */
+cbic_status cbic_calibrate_max_iter(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max,
+                                    const int32_t* d_T, const double* d_x0, const cbic_solve_opts* opts,
+                                    int32_t cap, void* stream, int32_t* p99, int32_t* p50, int64_t* hist);
+
 /* Milliseconds spent by the last solve on this context that was launched with
  * CBIC_FLAG_TIMING in its three phases: ms[0] warm start and initial rollout,
  * ms[1] the iteration kernels (backward sweeps and line searches), ms[2]

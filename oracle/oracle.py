@@ -229,6 +229,27 @@ def max_threads() -> int:
     return lib().orc_max_threads()
 
 
+def percentile_nearest_rank(values, q):
+    """Nearest-rank percentile: the smallest value v with at least q percent of
+    the values <= v (the rank is ceil(q n / 100))."""
+    v = sorted(int(x) for x in values)
+    rank = -(-q * len(v) // 100)
+    return v[max(rank, 1) - 1]
+
+
+def calibrate_max_iter(kind, params, x0, T_max, T=None, opts: Options | None = None, cap=1000, nthreads=0):
+    """Iteration budget (paper Sec. IV-A): solve with the relative-decrease stop
+    under `cap` iterations and return (p99, p50, counts), the 99th and 50th
+    nearest-rank percentiles of the per-instance iteration counts (the oracle
+    rejects invalid horizons outright)."""
+    base = opts or Options()
+    o = Options(max_iter=cap, ls_trials=base.ls_trials, stop_mode=1, lookahead=base.lookahead, eps=base.eps,
+                beta=base.beta, rtol=base.rtol)
+    r = solve_batch(kind, params, x0, T_max, T=T, opts=o, nthreads=nthreads)
+    counts = r.iters.astype(np.int64)
+    return percentile_nearest_rank(counts, 99), percentile_nearest_rank(counts, 50), counts
+
+
 def extract(kind, params, X, U, lookahead=0):
     """(V-bar, V-bar_x, x_K) of the given trajectory X (T+1, n), U (T, m)."""
     params = _f64(params)

@@ -79,6 +79,8 @@ _SIGS = {
     "cbic_phase_times": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "cbic_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_calibrate_max_iter": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_opts_default": (C.c_int32, [C.c_void_p]),
     "cbic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -276,6 +278,28 @@ def autotune(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts: O
     _check(lib().cbic_autotune(ctx.h, sys.h, x0.shape[0], T_max, _dptr(T), x0.data_ptr(), _dptr(U0), C.byref(o),
                                st, C.byref(g), C.byref(ms)))
     return g.value, ms.value
+
+
+def calibrate_max_iter(ctx: Context, sys: System, x0, T_max: int, T=None, opts: Options | None = None,
+                       cap: int = 1000, stream=None):
+    """Iteration budget from a tolerance-stop solve of this batch (paper Sec.
+    IV-A): returns (p99, p50, hist), the nearest-rank 99th and 50th
+    percentiles of the per-instance iteration counts and their histogram
+    (cap + 1 entries)."""
+    import numpy as np
+    import torch
+    opts = opts or Options()
+    dev = torch.device("cuda", ctx.device)
+    x0 = x0.to(device=dev, dtype=torch.float64).contiguous()
+    T = None if T is None else T.to(device=dev, dtype=torch.int32).contiguous()
+    o = opts.c()
+    p99, p50 = C.c_int32(), C.c_int32()
+    hist = np.zeros(cap + 1, dtype=np.int64)
+    st = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().cbic_calibrate_max_iter(ctx.h, sys.h, x0.shape[0], T_max, _dptr(T), x0.data_ptr(), C.byref(o),
+                                         cap, st, C.byref(p99), C.byref(p50),
+                                         hist.ctypes.data_as(C.c_void_p)))
+    return p99.value, p50.value, hist
 
 
 # ---------------------------------------------------------------- serving
