@@ -174,7 +174,20 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
             iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
             iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
             mean_sweeps=float(work[:, 0].mean()), lanes_per_instance=width)
-    best = max(results, key=lambda k: results[k]["converged_solves_per_s"])
+    # forms ending in "_lm" are the Levenberg-Marquardt ablation (Sec. IV-B):
+    # reported beside their clipped counterpart, never the headline form
+    best = max((k for k in results if not k.endswith("_lm")), key=lambda k: results[k]["converged_solves_per_s"])
+    for fname in [k for k in results if k.endswith("_lm")]:
+        base = fname[:-3]
+        if base in results:
+            a, b = results[base], results[fname]
+            d = (Jforms[fname] - Jforms[base]) / np.abs(Jforms[base])
+            b["vs_clip"] = {
+                "clip_form": base, "time_ratio": b["ms_per_step"] / a["ms_per_step"],
+                "iterate_time_ratio": b["iterate_ms"] / a["iterate_ms"],
+                "mean_iters": [a["mean_iters"], b["mean_iters"]], "mean_sweeps": [a["mean_sweeps"], b["mean_sweeps"]],
+                "median_rel_cost_diff": float(np.nanmedian(d)), "frac_lower_cost": float(np.mean(d < -1e-9)),
+                "frac_higher_cost": float(np.mean(d > 1e-9))}
     cpu = None
     if cpu_sample and not quick:
         from oracle import oracle as orc
@@ -282,9 +295,12 @@ def main():
     F = cbic.Options
     forms = {
         "pm16k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
-                  "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+                  "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM)},
         "pm64": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
-        "arm4k": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+        "arm4k": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+                  "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
+                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM)},
         "quad1k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                    "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
     }

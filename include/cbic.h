@@ -118,7 +118,25 @@ typedef struct {
   int32_t group_lanes;   /* lane schedule: lanes per instance (1,2,4,8,16; they split the
                             line-search trials); 0 = automatic                               */
   uint32_t flags;        /* CBIC_FLAG_* bits                                                 */
+  int32_t regularization; /* CBIC_REG_CLIP (default) or CBIC_REG_LM, see below               */
+  double lm_mu0;         /* CBIC_REG_LM: initial and smallest mu (> 0); default 1e-6          */
+  double lm_factor;      /* CBIC_REG_LM: mu is multiplied or divided by it (> 1); default 10   */
+  double lm_mu_max;      /* CBIC_REG_LM: largest mu tried (>= lm_mu0); default 1e10            */
 } cbic_solve_opts;
+
+/* regularization of the backward sweep (paper Sec. IV-B)
+ * CBIC_REG_CLIP  the running and terminal state-cost Hessians and the
+ *                control-cost Hessian are eigenvalue-clipped at psd_eps (eq. 7)
+ * CBIC_REG_LM    Levenberg-Marquardt, the ablation the paper argues against
+ *                for batches: the Hessians are only symmetrised and
+ *                Q_uu + mu I is factored, mu per instance; when the Cholesky
+ *                or the line search fails the instance multiplies mu by
+ *                lm_factor and retries its backward sweep (frozen with the
+ *                failure's status once mu would exceed lm_mu_max), after an
+ *                accepted step it divides mu by lm_factor (not below lm_mu0).
+ *                Lane schedule only (not the quadruped kernel, not the server). */
+#define CBIC_REG_CLIP 0
+#define CBIC_REG_LM 1
 
 /* schedule ids */
 #define CBIC_SCHED_LANE 1  /* one lane per instance, registers + step-major HBM          */

@@ -705,7 +705,19 @@ struct Opts {
   double eps;
   double beta;
   double rtol;
+  // regularization (Sec. IV-B): 0 eigenvalue clip (eq. 7); 1 Levenberg-Marquardt:
+  // Hessians only symmetrised, Q_uu + mu I, mu raised by mu_factor and the
+  // backward pass retried after a failed Cholesky or line search (up to
+  // mu_max), lowered by mu_factor (not below mu0) after an accepted step
+  int32_t reg;
+  double mu0, mu_factor, mu_max;
 };
+
+// the symmetric part of H (no clipping)
+void sym_part(int n, const double* H, double* out) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) out[i * n + j] = 0.5 * (H[i * n + j] + H[j * n + i]);
+}
 
 bool all_finite(const double* v, int k) {
   for (int i = 0; i < k; ++i)
@@ -814,18 +826,28 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
   std::vector<double> Qc(n * n), Rc(m * m), P(n * n), p(n), PA(n * n), PB(n * m);
   std::vector<double> Qx(n), Qu(m), Qxx(n * n), Quu(m * m), Qux(m * n), L(m * m), rhs(m * (n + 1));
 
-  for (int it = 0; it < o.max_iter && !frozen; ++it) {
-    // ---- backward Riccati sweep
+  const bool lm = o.reg == 1;
+  double mu = o.mu0;
+
+  // backward Riccati sweep about (X, U) with Levenberg-Marquardt parameter mu
+  // (used only when lm); fills the gains Kg, kf; returns 0 or the failure's
+  // status bit
+  auto sweep = [&](double mu_) -> uint32_t {
     term_derivs(s, X.data() + T * n, p.data(), lxx.data());
-    psd_clip(n, lxx.data(), o.eps, P.data());
-    bool ok = true;
-    for (int k = T - 1; k >= 0 && ok; --k) {
+    if (lm) sym_part(n, lxx.data(), P.data());
+    else psd_clip(n, lxx.data(), o.eps, P.data());
+    for (int k = T - 1; k >= 0; --k) {
       const double* xk = X.data() + k * n;
       const double* uk = U.data() + k * m;
       dyn_jac(s, xk, uk, A.data(), B.data());
       cost_derivs(s, xk, uk, lx.data(), lu.data(), lxx.data(), luu.data(), lux.data());
-      psd_clip(n, lxx.data(), o.eps, Qc.data());
-      psd_clip(m, luu.data(), o.eps, Rc.data());
+      if (lm) {
+        sym_part(n, lxx.data(), Qc.data());
+        sym_part(m, luu.data(), Rc.data());
+      } else {
+        psd_clip(n, lxx.data(), o.eps, Qc.data());
+        psd_clip(m, luu.data(), o.eps, Rc.data());
+      }
       // PA = P A, PB = P B
       for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j) {
@@ -864,11 +886,9 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
           Qux[i * n + j] = w;
         }
       }
-      if (!cholesky(m, Quu.data(), L.data())) {
-        status |= ST_CHOL_FAIL;
-        ok = false;
-        break;
-      }
+      if (lm)
+        for (int i = 0; i < m; ++i) Quu[i * m + i] += mu_;
+      if (!cholesky(m, Quu.data(), L.data())) return ST_CHOL_FAIL;
       // [K k] = -Q_uu^-1 [Q_ux Q_u]
       for (int i = 0; i < m; ++i) {
         for (int j = 0; j < n; ++j) rhs[i * (n + 1) + j] = Qux[i * n + j];
@@ -881,11 +901,7 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
         for (int j = 0; j < n; ++j) Kk[i * n + j] = -rhs[i * (n + 1) + j];
         kk[i] = -rhs[i * (n + 1) + n];
       }
-      if (!all_finite(Kk, m * n) || !all_finite(kk, m)) {
-        status |= ST_NONFINITE;
-        ok = false;
-        break;
-      }
+      if (!all_finite(Kk, m * n) || !all_finite(kk, m)) return ST_NONFINITE;
       // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
       for (int i = 0; i < n; ++i) {
         double v = Qx[i];
@@ -900,14 +916,13 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) P[i * n + j] = 0.5 * (PA[i * n + j] + PA[j * n + i]);
     }
-    if (!ok) {
-      frozen = true;
-      if (r.jtrace) r.jtrace[it] = -1;
-      break;
-    }
-    // ---- backtracking line search on the closed-loop rollout
+    return 0u;
+  };
+
+  // backtracking line search of iteration it: returns the accepted j (or -1)
+  // and the trial's cost in Jnew, the trial trajectory in (Xn, Un)
+  auto line_search = [&](int it, double& Jnew) -> int {
     int accepted = -1;
-    double Jnew = J;
     double alpha = 1.0;
     double margin = INFINITY;
     const int jmax = o.ls_trials;
@@ -942,11 +957,40 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
     }
     if (r.margin) r.margin[it] = margin;
     if (r.jtrace) r.jtrace[it] = accepted;
-    if (accepted < 0) {
-      status |= ST_LS_FAILED;
+    return accepted;
+  };
+
+  for (int it = 0; it < o.max_iter && !frozen; ++it) {
+    // one sweep and line search; the Levenberg-Marquardt variant raises mu and
+    // retries after a failed Cholesky or line search while mu stays <= mu_max
+    double Jnew = J;
+    uint32_t fail = 0;
+    for (;;) {
+      const uint32_t bad = sweep(mu);
+      if (bad) {
+        if (lm && bad == ST_CHOL_FAIL && mu * o.mu_factor <= o.mu_max) {
+          mu *= o.mu_factor;
+          continue;
+        }
+        fail = bad;
+        if (r.jtrace) r.jtrace[it] = -1;
+        break;
+      }
+      if (line_search(it, Jnew) < 0) {
+        if (lm && mu * o.mu_factor <= o.mu_max) {
+          mu *= o.mu_factor;
+          continue;
+        }
+        fail = ST_LS_FAILED;
+      }
+      break;
+    }
+    if (fail) {
+      status |= fail;
       frozen = true;
       break;
     }
+    if (lm) mu = std::max(mu / o.mu_factor, o.mu0);
     X.swap(Xn);
     U.swap(Un);
     const double Jold = J;
@@ -986,6 +1030,8 @@ struct orc_opts {
   double eps;
   double beta;
   double rtol;
+  int32_t reg;
+  double mu0, mu_factor, mu_max;
 };
 
 const char* orc_last_error() { return g_err; }
@@ -1111,7 +1157,8 @@ int orc_solve_batch(int kind, const double* p, int np, int B, int Tmax, const in
     return -1;
   }
   const int n = s.n, m = s.m;
-  Opts o{opt->max_iter, opt->ls_trials, opt->stop_mode, opt->lookahead, opt->eps, opt->beta, opt->rtol};
+  Opts o{opt->max_iter, opt->ls_trials, opt->stop_mode, opt->lookahead, opt->eps, opt->beta, opt->rtol,
+         opt->reg, opt->mu0, opt->mu_factor, opt->mu_max};
   const size_t sx = (size_t)(Tmax + 1) * n, su = (size_t)Tmax * m;
   std::memset(X, 0, sizeof(double) * sx * B);
   std::memset(U, 0, sizeof(double) * su * B);

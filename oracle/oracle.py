@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+import dataclasses
 from dataclasses import dataclass
 
 import numpy as np
@@ -32,7 +33,9 @@ def build(force: bool = True) -> str:
 class _Opts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("ls_trials", C.c_int32),
                 ("stop_mode", C.c_int32), ("lookahead", C.c_int32),
-                ("eps", C.c_double), ("beta", C.c_double), ("rtol", C.c_double)]
+                ("eps", C.c_double), ("beta", C.c_double), ("rtol", C.c_double),
+                ("reg", C.c_int32), ("mu0", C.c_double), ("mu_factor", C.c_double),
+                ("mu_max", C.c_double)]
 
 
 _lib = None
@@ -64,10 +67,17 @@ class Options:
     eps: float = 1e-6
     beta: float = 0.5
     rtol: float = 1e-10
+    # regularisation of the backward pass: 0 = eigenvalue clipping (eq. 7),
+    # 1 = Levenberg-Marquardt (Sec. IV-B ablation: no clipping, Q_uu + mu I)
+    reg: int = 0
+    mu0: float = 1e-6
+    mu_factor: float = 10.0
+    mu_max: float = 1e10
 
     def c(self):
         return _Opts(self.max_iter, self.ls_trials, self.stop_mode, self.lookahead,
-                     self.eps, self.beta, self.rtol)
+                     self.eps, self.beta, self.rtol, self.reg, self.mu0, self.mu_factor,
+                     self.mu_max)
 
 
 def dims(kind, params):
@@ -243,8 +253,7 @@ def calibrate_max_iter(kind, params, x0, T_max, T=None, opts: Options | None = N
     nearest-rank percentiles of the per-instance iteration counts (the oracle
     rejects invalid horizons outright)."""
     base = opts or Options()
-    o = Options(max_iter=cap, ls_trials=base.ls_trials, stop_mode=1, lookahead=base.lookahead, eps=base.eps,
-                beta=base.beta, rtol=base.rtol)
+    o = dataclasses.replace(base, max_iter=cap, stop_mode=1)
     r = solve_batch(kind, params, x0, T_max, T=T, opts=o, nthreads=nthreads)
     counts = r.iters.astype(np.int64)
     return percentile_nearest_rank(counts, 99), percentile_nearest_rank(counts, 50), counts

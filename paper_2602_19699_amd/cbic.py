@@ -21,6 +21,7 @@ ST_CONVERGED, ST_MAX_ITER, ST_LS_FAILED, ST_NONFINITE, ST_CHOL_FAIL, ST_BAD_INPU
 SYS_LQ, SYS_POINT_MASS, SYS_PLANAR3, SYS_QUAD_SYNTH = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 SCHED_AUTO, SCHED_LANE, SCHED_GROUP = 0, 1, 2
+REG_CLIP, REG_LM = 0, 1
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
 
@@ -36,7 +37,8 @@ class _Opts(C.Structure):
                 ("ls_max_trials", C.c_int32), ("ls_beta", C.c_double), ("stop_mode", C.c_int32),
                 ("rtol", C.c_double), ("lookahead_K", C.c_int32), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("group_lanes", C.c_int32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("regularization", C.c_int32), ("lm_mu0", C.c_double),
+                ("lm_factor", C.c_double), ("lm_mu_max", C.c_double)]
 
 
 class _Outputs(C.Structure):
@@ -134,12 +136,17 @@ class Options:
     iters_per_launch: int = 0
     group_lanes: int = 0
     flags: int = 0
+    regularization: int = REG_CLIP
+    lm_mu0: float = 1e-6
+    lm_factor: float = 10.0
+    lm_mu_max: float = 1e10
 
     def c(self) -> _Opts:
         o = _Opts()
         _check(lib().cbic_opts_default(C.byref(o)))
         for f in ("max_iter", "psd_eps", "ls_max_trials", "ls_beta", "stop_mode", "rtol", "lookahead_K",
-                  "precision", "schedule", "iters_per_launch", "group_lanes", "flags"):
+                  "precision", "schedule", "iters_per_launch", "group_lanes", "flags", "regularization",
+                  "lm_mu0", "lm_factor", "lm_mu_max"):
             setattr(o, f, getattr(self, f))
         return o
 

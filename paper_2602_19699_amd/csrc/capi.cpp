@@ -48,7 +48,31 @@ cbic_status check_opts(const cbic_solve_opts* o) {
     set_error("group_lanes must be 0, 1, 2, 4, 8 or 16");
     return CBIC_E_INVALID;
   }
+  if (o->regularization != CBIC_REG_CLIP && o->regularization != CBIC_REG_LM) {
+    set_error("regularization must be CBIC_REG_CLIP or CBIC_REG_LM");
+    return CBIC_E_INVALID;
+  }
+  if (o->regularization == CBIC_REG_LM &&
+      (!(o->lm_mu0 > 0.0) || !std::isfinite(o->lm_mu0) || !(o->lm_factor > 1.0) || !std::isfinite(o->lm_factor) ||
+       !(o->lm_mu_max >= o->lm_mu0) || !std::isfinite(o->lm_mu_max))) {
+    set_error("Levenberg-Marquardt needs finite lm_mu0 > 0, lm_factor > 1 and lm_mu_max >= lm_mu0");
+    return CBIC_E_INVALID;
+  }
   return CBIC_OK;
+}
+
+// the solve's parameters; the Levenberg-Marquardt variant clips nothing, which
+// the kernels read from a negative eps
+SolveParamsH solve_params(const cbic_solve_opts* o) {
+  SolveParamsH sp{o->max_iter, o->ls_max_trials, o->stop_mode, o->lookahead_K, o->psd_eps, o->ls_beta, o->rtol};
+  if (o->regularization == CBIC_REG_LM) {
+    sp.eps = -INFINITY;
+    sp.reg = 1;
+    sp.mu0 = o->lm_mu0;
+    sp.mu_fac = o->lm_factor;
+    sp.mu_max = o->lm_mu_max;
+  }
+  return sp;
 }
 
 size_t sort_bytes(int B, int Tmax) {
@@ -108,6 +132,10 @@ cbic_status cbic_opts_default(cbic_solve_opts* o) {
   o->iters_per_launch = 0;
   o->group_lanes = 0;
   o->flags = 0;
+  o->regularization = CBIC_REG_CLIP;
+  o->lm_mu0 = 1e-6;
+  o->lm_factor = 10.0;
+  o->lm_mu_max = 1e10;
   return CBIC_OK;
 }
 
@@ -252,16 +280,22 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
               sys->m, opts->precision, opts->schedule);
     return CBIC_E_UNSUPPORTED;
   }
+  if (opts->regularization == CBIC_REG_LM && L->schedule != CBIC_SCHED_LANE) {
+    set_error("the Levenberg-Marquardt variant runs on the lane schedule only");
+    return CBIC_E_UNSUPPORTED;
+  }
+  const SolveParamsH sp = solve_params(opts);
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   HIP_TRY(hipSetDevice(ctx->device));
   cbic_system* ms = const_cast<cbic_system*>(sys);
-  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != opts->psd_eps) {
+  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != sp.eps) {
     // the LQ Hessians are constant; their clip is refreshed for a new eps
+    // (none for the Levenberg-Marquardt variant)
     HIP_TRY(hipDeviceSynchronize());
-    make_device_block(ms, opts->psd_eps);
+    make_device_block(ms, sp.eps);
     HIP_TRY(hipMemcpy(ms->d_prm, ms->dev.data(), ms->dev.size() * sizeof(double), hipMemcpyHostToDevice));
-    ms->dev_eps = opts->psd_eps;
+    ms->dev_eps = sp.eps;
   }
   const size_t ws_main = L->ws_bytes(B, Tmax);
   st = ensure_ws(ctx, ws_main + sort_bytes(B, Tmax));
@@ -279,8 +313,6 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
   HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, stream));
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
-  SolveParamsH sp{opts->max_iter, opts->ls_max_trials, opts->stop_mode, opts->lookahead_K,
-                  opts->psd_eps, opts->ls_beta, opts->rtol};
   int group = opts->group_lanes;
   if (group <= 0) {
     auto it = ctx->tuned.find(tune_key(sys, B, Tmax, opts));
@@ -294,10 +326,11 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
       for (int c = 0; c < chunks; ++c)
         HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream));
     } else {
-      char key[256];
-      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p", (const void*)L,
-                    (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group, sp.max_iter,
-                    sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace);
+      char key[512];
+      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%d|%.17g|%.17g|%.17g",
+                    (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
+                    sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
+                    sp.reg, sp.mu0, sp.mu_fac, sp.mu_max);
       auto it = ctx->graphs.find(key);
       if (it == ctx->graphs.end()) {
         cbic_context::GraphEntry ge;

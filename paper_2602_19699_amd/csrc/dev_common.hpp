@@ -57,6 +57,7 @@ template <> struct JacobiTol<float> { static constexpr float v = 4e-15f; };
 // which leaves H bit-for-bit unchanged when no eigenvalue is clipped.
 template <class R>
 CBIC_HD __forceinline__ void clip_sym2(R& a, R& b, R& c, R eps) {
+  if (eps < R(0)) return;  // a negative floor means no clipping (Levenberg-Marquardt variant)
   if (b == R(0)) {
     a = dmax(a, eps);
     c = dmax(c, eps);
@@ -93,6 +94,7 @@ CBIC_HD __forceinline__ void clip_sym2(R& a, R& b, R& c, R eps) {
 // the clipped spectrum is recombined.
 template <class R>
 CBIC_HD __forceinline__ void clip_sym3(R h[9], R eps) {
+  if (eps < R(0)) return;  // a negative floor means no clipping (Levenberg-Marquardt variant)
   {
     const R a00 = h[0] - eps, a11 = h[4] - eps, a22 = h[8] - eps;
     bool pd = a00 > R(0);

@@ -34,6 +34,7 @@ struct LaneState {
   uint32_t* status;  // status bits; nonzero = frozen
   int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
   int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
+  double* mu;        // Levenberg-Marquardt parameter (that variant only)
   // trajectories and gains, step-major
   R* X;   // [nbuf][Tcap+1][Bcap][N]: the iterate (buffer cur) and trial trajectories
   R* U;   // [nbuf][Tcap][Bcap][M]
@@ -47,9 +48,11 @@ struct SolveParams {
   int32_t ls_trials;
   int32_t stop_mode;
   int32_t lookahead;
-  double eps;
+  double eps;  // negative: no clipping
   double beta;
   double rtol;
+  int32_t reg;  // 1: Levenberg-Marquardt (Q_uu + mu I, mu adapted per instance)
+  double mu0, mu_fac, mu_max;
 };
 
 template <class Sys, class R>
@@ -88,7 +91,7 @@ struct Lane {
   __device__ static __forceinline__ uint32_t riccati_step(const LaneState<R>& w, int s, int k, const R (&A)[N][N],
                                                           const R (&B)[N][M], const R (&lx)[N], const R (&lu)[M],
                                                           const R (&Qc)[N][N], const R (&Rc)[M][M], R (&P)[N][N],
-                                                          R (&p)[N], bool store) {
+                                                          R (&p)[N], bool store, double mu) {
     // PA = P A, PB = P B  (structural zeros of A, B skipped at compile time)
     R PA[N][N], PB[N][M];
 #pragma unroll
@@ -152,9 +155,13 @@ struct Lane {
         Qux[i][j] = q;
       }
     }
-    // Cholesky of Q_uu and the gains, in FP64 (one Newton step on the
-    // reciprocal pivots when the gains are rounded to FP32); the checks are on
-    // the gains as stored, so an FP32 overflow is caught as well
+    // Cholesky of Q_uu (+ mu I in the Levenberg-Marquardt variant) and the
+    // gains, in FP64 (one Newton step on the reciprocal pivots when the gains
+    // are rounded to FP32); the checks are on the gains as stored, so an FP32
+    // overflow is caught as well
+    if (mu != 0.0)
+#pragma unroll
+      for (int i = 0; i < M; ++i) Quu[i][i] += mu;
     double Lc[M][M], invd[M];
     if (!chol_fp64<M, sizeof(R) == 4 ? 1 : 2>(Quu, Lc, invd)) return ST_CHOL_FAIL;
     R Kk[M][N], kk[M];
@@ -226,7 +233,7 @@ struct Lane {
   // (ND = 0) evaluate them per step, with (x_k, u_k) prefetched two steps ahead.
   template <int GL>
   __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R eps,
-                                      bool store, R* stage, int r) {
+                                      bool store, R* stage, int r, double mu) {
     constexpr int ND = Model::ND;
     constexpr bool staged = ND > 0;
     constexpr int C = staged ? GL * (ND <= 8 ? 2 : 1) : 1;
@@ -266,7 +273,7 @@ struct Lane {
         for (int q = 0; q < cn; ++q) {
           R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
           mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
-          const uint32_t bad = riccati_step(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store);
+          const uint32_t bad = riccati_step(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store, mu);
           if (bad) return bad;
         }
         stage_sync();
@@ -300,7 +307,7 @@ struct Lane {
       R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
       mdl.jac(x, u, A, B);
       mdl.cost_derivs(x, u, lx, lu, Qc, Rc, eps, true);
-      const uint32_t bad = riccati_step(w, s, k, A, B, lx, lu, Qc, Rc, P, p, store);
+      const uint32_t bad = riccati_step(w, s, k, A, B, lx, lu, Qc, Rc, P, p, store, mu);
       if (bad) return bad;
     }
     return 0;
@@ -516,106 +523,132 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
   int buf = w.cur[s];
   int nsweep = w.work[4 * s], npass = w.work[4 * s + 1], nread = w.work[4 * s + 2], nwrite = w.work[4 * s + 3];
   const R eps = R(sp.eps);
+  const bool lm = sp.reg == 1;
+  // the Levenberg-Marquardt parameter carries over between launches; a slot
+  // that has not swept yet starts from mu0
+  double mu = lm ? (nsweep == 0 ? sp.mu0 : w.mu[s]) : 0.0;
   for (int g = 0; g < iters_this_launch && st == 0; ++g) {
     if (iters >= sp.max_iter) {
       st = ST_MAX_ITER;
       break;
     }
-    ++nsweep;
-    const uint32_t bad = LN::template backward<GL>(mdl, w, s, T, buf, eps, lead, stage, r);
-    if (bad) {
-      st = bad;
-      break;
-    }
     int acc = -1, nbuf_acc = buf;
     double Jn = J;
-    if constexpr (Sys::kOwnTrialBuffers) {
-      // rounds of GL parallel trials; lane r of the group rolls out into its own
-      // trajectory buffer, so the accepted trial is already written and becomes
-      // the iterate (no second rollout); one call site of the rollout keeps the
-      // register footprint down
-      const int wb = (buf + 1 + r) % w.nbuf;  // never the iterate's buffer (GL < nbuf)
-      for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += GL) {
-        const int j = j0 + r;
-        double Jh = __builtin_nan("");
-        int steps = 0;
-        if (j < sp.ls_trials) {
-          double alpha = 1.0;
-          for (int q = 0; q < j; ++q) alpha *= sp.beta;
-          Jh = LN::template trial<GL>(mdl, w, s, T, buf, wb, R(alpha), J, true, steps, stage, r, gbase);
+    uint32_t fail = 0;
+    // one sweep and line search; in the Levenberg-Marquardt variant a failed
+    // Cholesky or line search multiplies mu by mu_fac and retries while mu
+    // stays within mu_max (the group's lanes decide alike)
+    for (;;) {
+      ++nsweep;
+      const uint32_t bad = LN::template backward<GL>(mdl, w, s, T, buf, eps, lead, stage, r, mu);
+      if (bad) {
+        if (lm && bad == ST_CHOL_FAIL && mu * sp.mu_fac <= sp.mu_max) {
+          mu *= sp.mu_fac;
+          continue;
         }
-        ++npass;
-        // every lane writes what it rolled out; the lanes of a group read the
-        // same data, so a round reads as many steps as its longest trial
-        int total = steps, longest = steps;
-#pragma unroll
-        for (int o = 1; o < GL; o <<= 1) {
-          total += __shfl_xor(total, o, 64);
-          longest = max(longest, __shfl_xor(longest, o, 64));
-        }
-        nwrite += total;
-        nread += longest;
-        const bool ok = isfinite(Jh) && Jh < J;
-        unsigned long long bits = __ballot(ok);
-        bits = (bits >> gbase) & ((GL >= 64) ? ~0ull : ((1ull << GL) - 1ull));
-        if (bits) {
-          const int rs = __ffsll(bits) - 1;
-          acc = j0 + rs;
-          Jn = __shfl(Jh, gbase + rs, 64);
-          nbuf_acc = (buf + 1 + rs) % w.nbuf;
-        }
+        fail = bad;
+        break;
       }
-    } else {
-      // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
-      // whose lane wrote while trying it) one commit rollout that writes it; one
-      // call site of the rollout keeps the register footprint down
-      bool commit = false;
-      for (int j0 = 0;;) {
-        const int j = commit ? acc : j0 + r;
-        double Jh = __builtin_nan("");
-        int steps = 0;
-        if (commit || j < sp.ls_trials) {
-          double alpha = 1.0;
-          for (int q = 0; q < j; ++q) alpha *= sp.beta;
-          // alpha = 1 (j == 0) is written while it runs, as is every trial of a
-          // one-lane group; the commit is written by the group's lead lane
-          const bool wr = commit ? lead : (j == 0 || GL == 1);
-          Jh = LN::template trial<GL>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr, steps,
-                                      stage, r, gbase);
-        }
-        ++npass;
-        if (commit) {
-          Jn = Jh;
-          nread += steps;
-          nwrite += steps;
-          break;
-        }
-        // the lanes of a group read the same data: a round moves as many steps
-        // as its longest trial; only the alpha = 1 trial (or every trial of a
-        // one-lane group) writes
-        if (j0 == 0 || GL == 1) nwrite += (GL == 1) ? steps : __shfl(steps, gbase, 64);
-        int longest = steps;
+      acc = -1;
+      nbuf_acc = buf;
+      Jn = J;
+      if constexpr (Sys::kOwnTrialBuffers) {
+        // rounds of GL parallel trials; lane r of the group rolls out into its own
+        // trajectory buffer, so the accepted trial is already written and becomes
+        // the iterate (no second rollout); one call site of the rollout keeps the
+        // register footprint down
+        const int wb = (buf + 1 + r) % w.nbuf;  // never the iterate's buffer (GL < nbuf)
+        for (int j0 = 0; j0 < sp.ls_trials && acc < 0; j0 += GL) {
+          const int j = j0 + r;
+          double Jh = __builtin_nan("");
+          int steps = 0;
+          if (j < sp.ls_trials) {
+            double alpha = 1.0;
+            for (int q = 0; q < j; ++q) alpha *= sp.beta;
+            Jh = LN::template trial<GL>(mdl, w, s, T, buf, wb, R(alpha), J, true, steps, stage, r, gbase);
+          }
+          ++npass;
+          // every lane writes what it rolled out; the lanes of a group read the
+          // same data, so a round reads as many steps as its longest trial
+          int total = steps, longest = steps;
 #pragma unroll
-        for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
-        nread += longest;
-        const bool ok = isfinite(Jh) && Jh < J;
-        unsigned long long bits = __ballot(ok);
-        bits = (bits >> gbase) & ((1ull << GL) - 1);
-        if (bits) {
-          const int rs = __ffsll(bits) - 1;
-          acc = j0 + rs;
-          Jn = __shfl(Jh, gbase + rs, 64);
+          for (int o = 1; o < GL; o <<= 1) {
+            total += __shfl_xor(total, o, 64);
+            longest = max(longest, __shfl_xor(longest, o, 64));
+          }
+          nwrite += total;
+          nread += longest;
+          const bool ok = isfinite(Jh) && Jh < J;
+          unsigned long long bits = __ballot(ok);
+          bits = (bits >> gbase) & ((GL >= 64) ? ~0ull : ((1ull << GL) - 1ull));
+          if (bits) {
+            const int rs = __ffsll(bits) - 1;
+            acc = j0 + rs;
+            Jn = __shfl(Jh, gbase + rs, 64);
+            nbuf_acc = (buf + 1 + rs) % w.nbuf;
+          }
         }
-        j0 += GL;
-        if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
-        if (acc > 0) commit = true;
+      } else {
+        // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
+        // whose lane wrote while trying it) one commit rollout that writes it; one
+        // call site of the rollout keeps the register footprint down
+        bool commit = false;
+        for (int j0 = 0;;) {
+          const int j = commit ? acc : j0 + r;
+          double Jh = __builtin_nan("");
+          int steps = 0;
+          if (commit || j < sp.ls_trials) {
+            double alpha = 1.0;
+            for (int q = 0; q < j; ++q) alpha *= sp.beta;
+            // alpha = 1 (j == 0) is written while it runs, as is every trial of a
+            // one-lane group; the commit is written by the group's lead lane
+            const bool wr = commit ? lead : (j == 0 || GL == 1);
+            Jh = LN::template trial<GL>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr, steps,
+                                        stage, r, gbase);
+          }
+          ++npass;
+          if (commit) {
+            Jn = Jh;
+            nread += steps;
+            nwrite += steps;
+            break;
+          }
+          // the lanes of a group read the same data: a round moves as many steps
+          // as its longest trial; only the alpha = 1 trial (or every trial of a
+          // one-lane group) writes
+          if (j0 == 0 || GL == 1) nwrite += (GL == 1) ? steps : __shfl(steps, gbase, 64);
+          int longest = steps;
+#pragma unroll
+          for (int o = 1; o < GL; o <<= 1) longest = max(longest, __shfl_xor(longest, o, 64));
+          nread += longest;
+          const bool ok = isfinite(Jh) && Jh < J;
+          unsigned long long bits = __ballot(ok);
+          bits = (bits >> gbase) & ((1ull << GL) - 1);
+          if (bits) {
+            const int rs = __ffsll(bits) - 1;
+            acc = j0 + rs;
+            Jn = __shfl(Jh, gbase + rs, 64);
+          }
+          j0 += GL;
+          if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
+          if (acc > 0) commit = true;
+        }
+        nbuf_acc = buf ^ 1;
       }
-      nbuf_acc = buf ^ 1;
-    }
-    if (acc < 0) {
-      st = ST_LS_FAILED;
+      if (acc < 0) {
+        if (lm && mu * sp.mu_fac <= sp.mu_max) {
+          mu *= sp.mu_fac;
+          continue;
+        }
+        fail = ST_LS_FAILED;
+      }
       break;
     }
+    if (fail) {
+      st = fail;
+      break;
+    }
+    if (lm) mu = fmax(mu / sp.mu_fac, sp.mu0);
     buf = nbuf_acc;
     const double Jold = J;
     J = Jn;
@@ -636,6 +669,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
     w.work[4 * s + 1] = npass;
     w.work[4 * s + 2] = nread;
     w.work[4 * s + 3] = nwrite;
+    w.mu[s] = mu;
   }
 }
 

@@ -24,6 +24,7 @@ inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap, int
   w.status = reinterpret_cast<uint32_t*>(b + L.status);
   w.cur = reinterpret_cast<int32_t*>(b + L.cur);
   w.work = reinterpret_cast<int32_t*>(b + L.work);
+  w.mu = reinterpret_cast<double*>(b + L.mu);
   w.X = reinterpret_cast<R*>(b + L.X);
   w.U = reinterpret_cast<R*>(b + L.U);
   w.K = reinterpret_cast<R*>(b + L.K);
@@ -43,6 +44,10 @@ inline SolveParams to_dev(const SolveParamsH& h) {
   s.eps = h.eps;
   s.beta = h.beta;
   s.rtol = h.rtol;
+  s.reg = h.reg;
+  s.mu0 = h.mu0;
+  s.mu_fac = h.mu_fac;
+  s.mu_max = h.mu_max;
   return s;
 }
 

@@ -39,6 +39,7 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf) {
   L.status = o; o = align256(o + 4 * B);
   L.cur = o; o = align256(o + 4 * B);
   L.work = o; o = align256(o + 16 * B);
+  L.mu = o; o = align256(o + 8 * B);
   L.X = o; o = align256(o + size_t(elem) * nbuf * (Tcap + 1) * B * N);
   L.U = o; o = align256(o + size_t(elem) * nbuf * Tcap * B * M);
   L.K = o; o = align256(o + size_t(elem) * Tcap * B * M * N);
@@ -75,6 +76,10 @@ static void host_clip(int n, const double* H, double eps, double* out) {
   std::vector<double> a(n * n), v(n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) a[i * n + j] = 0.5 * (H[i * n + j] + H[j * n + i]);
+  if (eps < 0.0) {  // no clipping (the Levenberg-Marquardt variant): symmetric part only
+    for (int i = 0; i < n * n; ++i) out[i] = a[i];
+    return;
+  }
   for (int i = 0; i < n; ++i) v[i * n + i] = 1.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;

@@ -21,7 +21,7 @@ struct SolveParams;  // ilqr_lane.hpp
 // Byte offsets of the per-slot state, trajectories and gains inside one
 // workspace allocation (lane schedule).  All sub-arrays are 256-byte aligned.
 struct LaneLayout {
-  size_t T, inst, J, iters, status, cur, work;
+  size_t T, inst, J, iters, status, cur, work, mu;
   size_t X, U, K, kf;
   size_t total;
 };
@@ -30,7 +30,7 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf = 2)
 
 // Group schedule (one workgroup per instance) for large systems.
 struct GroupLayout {
-  size_t T, inst, J, iters, status, cur, work;
+  size_t T, inst, J, iters, status, cur, work, mu;
   size_t X, U, K, kf;
   size_t total;
 };
@@ -39,6 +39,9 @@ GroupLayout group_layout(int N, int M, int elem, int Bcap, int Tcap);
 struct SolveParamsH {
   int32_t max_iter, ls_trials, stop_mode, lookahead;
   double eps, beta, rtol;
+  // Levenberg-Marquardt (reg = 1; eps is then negative: no clipping)
+  int32_t reg = 0;
+  double mu0 = 0.0, mu_fac = 1.0, mu_max = 0.0;
 };
 
 struct FinalOutH {

@@ -444,6 +444,10 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   if (opts->struct_size != sizeof(cbic_solve_opts)) { set_error("opts.struct_size mismatch"); return CBIC_E_INVALID; }
   if (T < 1 || T > srv->opts.t_max) { set_error("T must be in 1..%d", srv->opts.t_max); return CBIC_E_INVALID; }
   if (opts->precision != CBIC_FP64 && opts->precision != CBIC_MIXED) { set_error("bad precision"); return CBIC_E_INVALID; }
+  if (opts->regularization != CBIC_REG_CLIP) {
+    set_error("the server runs the clipped regularization only");
+    return CBIC_E_UNSUPPORTED;
+  }
   const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, 0);
   if (!L) {
     set_error("no kernel for this system and precision");

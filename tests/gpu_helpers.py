@@ -29,9 +29,13 @@ def gpu_solve(ctx, kind, params, x0, T_max, T=None, U0=None, trace=False, **opt)
 
 
 def oracle_opts(**opt):
+    """The oracle's options for the same keyword arguments gpu_solve takes."""
+    lm = opt.get("regularization", 0) == 1
     return orc.Options(max_iter=opt.get("max_iter", 50), ls_trials=opt.get("ls_max_trials", 16),
                        stop_mode=opt.get("stop_mode", 0), lookahead=opt.get("lookahead_K", 0),
-                       eps=opt.get("psd_eps", 1e-6), beta=opt.get("ls_beta", 0.5), rtol=opt.get("rtol", 1e-10))
+                       eps=-np.inf if lm else opt.get("psd_eps", 1e-6), beta=opt.get("ls_beta", 0.5),
+                       rtol=opt.get("rtol", 1e-10), reg=1 if lm else 0, mu0=opt.get("lm_mu0", 1e-6),
+                       mu_factor=opt.get("lm_factor", 10.0), mu_max=opt.get("lm_mu_max", 1e10))
 
 
 def rel(a, b):

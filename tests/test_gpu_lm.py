@@ -1,0 +1,148 @@
+"""GPU parity of the Levenberg-Marquardt regularisation (Sec. IV-B ablation:
+no eigenvalue clipping, Q_uu + mu I with mu raised and the sweep retried after
+a failure) against the FP64 CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2602_19699_amd import inputs as I
+
+from gpu_helpers import compare, compare_sensitivity_aware, gpu_solve, oracle_opts, oracle_with_sensitivity, rel
+
+pytestmark = pytest.mark.gpu
+
+PM, P3, LQ, QUAD = I.SYS_POINT_MASS, I.SYS_PLANAR3, I.SYS_LQ, I.SYS_QUAD_SYNTH
+LM = dict(regularization=1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2602_19699_amd import cbic
+    assert torch.cuda.is_available()
+    c = cbic.Context(0)
+    yield c
+    c.close()
+
+
+def test_lm_point_mass_fp64(ctx):
+    kind, p, x0, T, _ = I.workload("pm64")
+    for o in (dict(max_iter=50), dict(max_iter=200, stop_mode=1, rtol=1e-10)):
+        g = gpu_solve(ctx, kind, p, x0, T, trace=True, **LM, **o)
+        r = orc.solve_batch(kind, p, x0, T, opts=oracle_opts(**LM, **o))
+        worst = compare(g, r, label=f"pm64 lm {o}")
+        print(f"pm64 LM {o}: worst rel cost {worst:.2e}; iters gpu {g['iters'][:8]} oracle {r.iters[:8]}")
+        for b in range(64):
+            tr = g["cost_trace"][b, : g["iters"][b] + 1]
+            assert np.all(np.diff(tr) < 0)
+
+
+def test_lm_point_mass_ragged_mixed(ctx):
+    B = 200
+    p = I.point_mass_params(1)
+    x0 = I.point_mass_x0(B, 77)
+    T = I.horizons(B, 1, 100, seed=5)
+    g = gpu_solve(ctx, PM, p, x0, 100, T=T, **LM)
+    r = orc.solve_batch(PM, p, x0, 100, T=T, opts=oracle_opts(**LM))
+    compare(g, r, label="pm-ragged lm")
+    for b in range(B):
+        assert np.all(g["X"][b, T[b] + 1:] == 0) and np.all(g["U"][b, T[b]:] == 0)
+    gm = gpu_solve(ctx, PM, p, x0, 100, T=T, precision=1, **LM)
+    e = rel(gm["J"], r.J)
+    print(f"pm-ragged LM mixed: max rel {e.max():.2e}, within 1e-4: {(e <= 1e-4).mean():.3f}")
+    assert (e <= 1e-4).mean() >= 0.95 and np.all(np.isfinite(gm["J"]))
+
+
+@pytest.mark.parametrize("mu0", [1e-3, 0.5])
+def test_lm_lq_proximal_steps(ctx, mu0):
+    p = I.lq_random(4, 2, seed=9, ref=True)
+    x0 = I.lq_x0(70, 4)
+    T = 40
+    U0 = np.random.default_rng(1).normal(size=(70, T, 2))
+    for it in (1, 2):
+        g = gpu_solve(ctx, LQ, p, x0, T, U0=U0, max_iter=it, lm_mu0=mu0, **LM)
+        r = orc.solve_batch(LQ, p, x0, T, U0=U0, opts=oracle_opts(max_iter=it, lm_mu0=mu0, **LM))
+        compare(g, r, tol_J=1e-11, label=f"lq lm mu0={mu0} it={it}")
+        np.testing.assert_allclose(g["U"], r.U, atol=1e-9)
+
+
+def _indefinite_lq():
+    th = 0.3
+    W = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    R = W @ np.diag([-1.5, 2.5]) @ W.T  # control Hessian 2R: eigenvalues -3 and 5
+    # n = 4, m = 2 (a size the library instantiates); no control authority
+    return I.lq_params(np.eye(4), np.zeros((4, 2)), np.eye(4), R, np.eye(4))
+
+
+def test_lm_retries_and_limits(ctx):
+    p = _indefinite_lq()
+    x0 = np.tile([[1.0, -1.0, 0.5, 2.0]], (3, 1))
+    U0 = np.tile([[[0.7, -0.2]]], (3, 1, 1))
+    # mu climbs from 1e-6 to 10 before the Cholesky succeeds, in every iteration
+    g = gpu_solve(ctx, LQ, p, x0, 1, U0=U0, max_iter=2, **LM)
+    r = orc.solve_batch(LQ, p, x0, 1, U0=U0, opts=oracle_opts(max_iter=2, **LM))
+    np.testing.assert_allclose(g["U"], r.U, atol=1e-13, rtol=0)
+    assert np.all(g["iters"] == 2) and np.all(g["status"] == orc.ST_MAX_ITER)
+    # mu_max below what the problem needs: Cholesky failure, iterate unchanged
+    g = gpu_solve(ctx, LQ, p, x0, 1, U0=U0, max_iter=5, lm_mu_max=1.0, **LM)
+    assert np.all(g["status"] == orc.ST_CHOL_FAIL) and np.all(g["iters"] == 0)
+    np.testing.assert_array_equal(g["U"], U0)
+    # no line-search trials: mu climbs to mu_max, then a line-search failure
+    q = I.lq_random(2, 1, seed=1)
+    g = gpu_solve(ctx, LQ, q, I.lq_x0(3, 2), 5, ls_max_trials=0, **LM)
+    assert np.all(g["status"] == orc.ST_LS_FAILED) and np.all(g["iters"] == 0) and np.all(g["U"] == 0)
+
+
+def test_lm_arm_ragged_fp64(ctx):
+    B = 130
+    p = I.planar3_params(0)
+    x0 = I.planar3_x0(B, 11)
+    T = I.horizons(B, 50, 200, seed=12)
+    g = gpu_solve(ctx, P3, p, x0, 200, T=T, max_iter=20, **LM)
+    r, rho = oracle_with_sensitivity(P3, p, x0, 200, T=T, opts=oracle_opts(max_iter=20, **LM))
+    compare_sensitivity_aware(g, r, rho, label="arm lm")
+    for b in range(B):
+        d, J = orc.check_trajectory(P3, p, g["X"][b, :T[b] + 1], g["U"][b, :T[b]])
+        assert d <= 1e-12 and abs(J - g["J"][b]) <= 1e-12 * abs(J)
+
+
+@pytest.mark.parametrize("kind", [PM, P3], ids=["pm", "arm"])
+def test_lm_group_widths_and_launch_splits_identical(ctx, kind):
+    # mu lives in the workspace between launches: chunked and graph-replayed
+    # launches and every group width give the same bits as one launch
+    if kind == PM:
+        p, x0, T, Tb = I.point_mass_params(0), I.point_mass_x0(150, 5), 100, None
+    else:
+        p, x0, T, Tb = I.planar3_params(0), I.planar3_x0(90, 6), 120, I.horizons(90, 30, 120, seed=3)
+    ref = gpu_solve(ctx, kind, p, x0, T, T=Tb, max_iter=15, group_lanes=1, **LM)
+    runs = [dict(group_lanes=gl) for gl in (2, 4, 8, 16)]
+    runs += [dict(group_lanes=1, iters_per_launch=4), dict(group_lanes=1, iters_per_launch=5, flags=1)]
+    for o in runs:
+        g = gpu_solve(ctx, kind, p, x0, T, T=Tb, max_iter=15, **o, **LM)
+        for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"):
+            np.testing.assert_array_equal(ref[k], g[k], err_msg=f"{o} field {k}")
+
+
+def test_lm_rejected_where_unsupported(ctx):
+    import torch
+    from paper_2602_19699_amd import cbic
+    # the workgroup-per-instance schedule has no LM variant
+    p = I.quad_params(0)
+    with pytest.raises(cbic.CbicError) as e:
+        gpu_solve(ctx, QUAD, p, I.quad_x0(2, p, seed=7), 10, **LM)
+    assert e.value.code == cbic.E_UNSUPPORTED
+    # invalid LM parameters
+    kind, p, x0, T, _ = I.workload("pm64")
+    for bad in (dict(lm_mu0=0.0), dict(lm_factor=1.0), dict(lm_mu_max=1e-9), dict(regularization=2)):
+        with pytest.raises(cbic.CbicError) as e:
+            gpu_solve(ctx, kind, p, x0[:2], T, **{**LM, **bad})
+        assert e.value.code == cbic.E_INVALID
+    # the serving runtime takes clip-regularised requests only
+    srv = cbic.Server(ctx, slots_per_class=4, t_max=200)
+    sys_ = cbic.System(ctx, PM, p)
+    with pytest.raises(cbic.CbicError) as e:
+        srv.submit(sys_, x0[0], 50, opts=cbic.Options(regularization=1))
+    assert e.value.code == cbic.E_UNSUPPORTED
+    srv.close()
+    sys_.close()
+    torch.cuda.synchronize()
