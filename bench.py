@@ -156,12 +156,22 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
             forms = {**forms, "fp64_fixed_p99": cbic.Options(max_iter=p99)}
     results = {}
     Jforms = {}
+    bounded_ref = {}  # u_max -> J of the FP64 50-iteration solve under that bound
     for fname, opts in forms.items():
         out, ms, lat, ph, width = time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup)
         J = out.J.cpu().numpy()
         Jforms[fname] = J
         work = out.work.cpu().numpy()
-        rel = np.abs(J - Jref) / np.abs(Jref)
+        Jr = Jref
+        if np.isfinite(opts.u_max):
+            # a bounded form solves another problem: its reference is the FP64
+            # solve under the same bound
+            if opts.u_max not in bounded_ref:
+                rb = cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=cbic.Options(max_iter=50, u_max=opts.u_max),
+                                      targets=False)
+                bounded_ref[opts.u_max] = rb.J.cpu().numpy()
+            Jr = bounded_ref[opts.u_max]
+        rel = np.abs(J - Jr) / np.abs(Jr)
         conv = int(np.sum(rel <= 1e-4))
         elem = 8 if opts.precision == cbic.FP64 else 4
         nb = alg_bytes(work, Tvec, n, m, elem)
@@ -174,9 +184,16 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
             iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
             iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
             mean_sweeps=float(work[:, 0].mean()), lanes_per_instance=width)
-    # forms ending in "_lm" are the Levenberg-Marquardt ablation (Sec. IV-B):
-    # reported beside their clipped counterpart, never the headline form
-    best = max((k for k in results if not k.endswith("_lm")), key=lambda k: results[k]["converged_solves_per_s"])
+        if np.isfinite(opts.u_max):
+            Uo = out.U.cpu().numpy()
+            results[fname]["u_max"] = opts.u_max
+            results[fname]["frac_instances_at_bound"] = float(np.mean(np.any(np.abs(Uo) >= opts.u_max, axis=(1, 2))))
+            results[fname]["max_abs_u"] = float(np.abs(Uo).max())
+    # forms ending in "_lm" are the Levenberg-Marquardt ablation (Sec. IV-B),
+    # reported beside their clipped counterpart; forms with "_umax" solve the
+    # problem with the control bound of eq. 1; neither is the headline form
+    best = max((k for k in results if not k.endswith("_lm") and "_umax" not in k),
+               key=lambda k: results[k]["converged_solves_per_s"])
     for fname in [k for k in results if k.endswith("_lm")]:
         base = fname[:-3]
         if base in results:
@@ -201,6 +218,8 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
         # every form's cost against the FP64 oracle on the sampled instances
         Jo = np.asarray(ores.J)
         for fname, J in Jforms.items():
+            if np.isfinite(forms[fname].u_max):
+                continue  # the oracle leg solves the unbounded problem
             r = np.abs(J[:ns] - Jo) / np.abs(Jo)
             results[fname]["vs_oracle"] = {
                 "oracle_form": cpu_opts_form, "instances": int(ns), "max_rel_cost": float(np.nanmax(r)),
@@ -296,11 +315,13 @@ def main():
     forms = {
         "pm16k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                   "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
-                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM)},
+                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM),
+                  "mixed_tol1e-7_umax10": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=10.0)},
         "pm64": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
         "arm4k": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
                   "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
-                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM)},
+                  "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM),
+                  "mixed_tol1e-7_umax8": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=8.0)},
         "quad1k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                    "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
     }

@@ -122,6 +122,8 @@ typedef struct {
   double lm_mu0;         /* CBIC_REG_LM: initial and smallest mu (> 0); default 1e-6          */
   double lm_factor;      /* CBIC_REG_LM: mu is multiplied or divided by it (> 1); default 10   */
   double lm_mu_max;      /* CBIC_REG_LM: largest mu tried (>= lm_mu0); default 1e10            */
+  double u_max;          /* control bound |u_k,i| <= u_max of eq. 1 (> 0); default +infinity
+                            (unbounded); see below                                            */
 } cbic_solve_opts;
 
 /* regularization of the backward sweep (paper Sec. IV-B)
@@ -137,6 +139,14 @@ typedef struct {
  *                Lane schedule only (not the quadruped kernel, not the server). */
 #define CBIC_REG_CLIP 0
 #define CBIC_REG_LM 1
+
+/* control bound (paper eq. 1): with a finite u_max every control component is
+ * kept in [-u_max, u_max].  The warm start is clamped into the box; each step
+ * of the backward sweep minimises the local model over the box (a bounded
+ * quadratic program in the control step, solved exactly by an active-set
+ * method in FP64), the feedback rows of the components held at a bound are
+ * zero, and the line-search rollouts clamp their controls.  Lane schedule only
+ * (not the quadruped kernel, not the server): CBIC_E_UNSUPPORTED there. */
 
 /* schedule ids */
 #define CBIC_SCHED_LANE 1  /* one lane per instance, registers + step-major HBM          */

@@ -696,6 +696,127 @@ void chol_solve(int m, const double* L, double* Bm, int nrhs) {
   }
 }
 
+// ------------------------------------------------------------ control bound
+// Bounded control step (eq. 1 keeps every control in [-u_max, u_max]): the
+// minimiser d of 0.5 d'Hd + g'd subject to lo <= d <= hi, H symmetric
+// positive definite (m x m, row-major), by the primal active-set method.
+// On entry d holds the unconstrained minimiser -H^-1 g.  If it lies in the
+// box it is the answer.  Otherwise its out-of-box components are clamped and
+// held at their bounds (the working set), and the method alternates:
+//  - if d is not yet the minimiser over the free components with the held
+//    ones fixed (the face), compute that minimiser y and move from d towards
+//    it until a free component meets a bound (the first such, lowest index on
+//    ties, joins the working set) or, if none does, up to y;
+//  - if d is the face's minimiser, compute the multiplier of every held
+//    component (its gradient g + H d, with the sign flipped at an upper
+//    bound); release the most negative one (lowest index on ties), or stop
+//    when none is negative: d then satisfies the optimality conditions.
+// At most 4m + 4 such steps are taken (a strictly convex problem needs fewer;
+// d stays feasible either way).  held[i] = 1 for the components held at the
+// end.  Returns false when a face's block of H cannot be factorised.
+bool face_factor(int m, const double* H, const std::vector<char>& held, std::vector<int>& F,
+                 std::vector<double>& LF) {
+  F.clear();
+  for (int i = 0; i < m; ++i)
+    if (!held[i]) F.push_back(i);
+  const int f = (int)F.size();
+  std::vector<double> HF(f * f);
+  for (int a = 0; a < f; ++a)
+    for (int b = 0; b < f; ++b) HF[a * f + b] = H[F[a] * m + F[b]];
+  LF.assign(f * f, 0.0);
+  return f == 0 || cholesky(f, HF.data(), LF.data());
+}
+
+bool box_qp(int m, const double* H, const double* g, const double* lo, const double* hi, double* d,
+            std::vector<char>& held) {
+  held.assign(m, 0);
+  bool inside = true;
+  for (int i = 0; i < m; ++i) {
+    if (std::isnan(d[i])) return true;  // reported by the caller's finiteness check
+    inside = inside && d[i] >= lo[i] && d[i] <= hi[i];
+  }
+  if (inside) return true;
+  std::vector<char> upper(m, 0);
+  for (int i = 0; i < m; ++i) {
+    if (d[i] < lo[i]) {
+      d[i] = lo[i];
+      held[i] = 1;
+    } else if (d[i] > hi[i]) {
+      d[i] = hi[i];
+      held[i] = 1;
+      upper[i] = 1;
+    }
+  }
+  std::vector<int> F;
+  std::vector<double> LF, y;
+  bool at_min = false;
+  for (int step = 0; step < 4 * m + 4; ++step) {
+    if (!at_min) {
+      if (!face_factor(m, H, held, F, LF)) return false;
+      const int f = (int)F.size();
+      if (f == 0) {
+        at_min = true;
+        continue;
+      }
+      // face minimiser: H_FF y_F = -(g_F + H_FW d_W)
+      y.assign(f, 0.0);
+      for (int a = 0; a < f; ++a) {
+        double v = g[F[a]];
+        for (int j = 0; j < m; ++j)
+          if (held[j]) v += H[F[a] * m + j] * d[j];
+        y[a] = -v;
+      }
+      chol_solve(f, LF.data(), y.data(), 1);
+      double t_best = 1.0;
+      int blocking = -1;
+      bool blocking_upper = false;
+      for (int a = 0; a < f; ++a) {
+        const int i = F[a];
+        const double dir = y[a] - d[i];
+        double t = INFINITY;
+        if (dir < 0.0) t = (lo[i] - d[i]) / dir;
+        else if (dir > 0.0) t = (hi[i] - d[i]) / dir;
+        if (t < t_best) {
+          t_best = t;
+          blocking = i;
+          blocking_upper = dir > 0.0;
+        }
+      }
+      if (blocking < 0) {
+        for (int a = 0; a < f; ++a) d[F[a]] = y[a];
+        at_min = true;
+      } else {
+        for (int a = 0; a < f; ++a) {
+          const int i = F[a];
+          if (i == blocking) continue;
+          const double v = d[i] + t_best * (y[a] - d[i]);
+          d[i] = v < lo[i] ? lo[i] : (v > hi[i] ? hi[i] : v);
+        }
+        d[blocking] = blocking_upper ? hi[blocking] : lo[blocking];
+        held[blocking] = 1;
+        upper[blocking] = blocking_upper;
+      }
+    } else {
+      int release = -1;
+      double most_negative = 0.0;
+      for (int i = 0; i < m; ++i) {
+        if (!held[i]) continue;
+        double gr = g[i];
+        for (int j = 0; j < m; ++j) gr += H[i * m + j] * d[j];
+        const double mult = upper[i] ? -gr : gr;
+        if (mult < most_negative) {
+          most_negative = mult;
+          release = i;
+        }
+      }
+      if (release < 0) break;
+      held[release] = 0;
+      at_min = false;
+    }
+  }
+  return true;
+}
+
 // ------------------------------------------------------------ one instance
 struct Opts {
   int32_t max_iter;
@@ -711,6 +832,8 @@ struct Opts {
   // mu_max), lowered by mu_factor (not below mu0) after an accepted step
   int32_t reg;
   double mu0, mu_factor, mu_max;
+  // control bound |u_k,i| <= umax (eq. 1); infinite: none
+  double umax;
 };
 
 // the symmetric part of H (no clipping)
@@ -810,6 +933,11 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
   std::vector<double> X((T + 1) * n), U(T * m, 0.0), Xn((T + 1) * n), Un(T * m);
   std::vector<double> Kg(T * m * n), kf(T * m);
   if (U0) std::memcpy(U.data(), U0, sizeof(double) * T * m);
+  const bool bounded = std::isfinite(o.umax);
+  // controls are kept in [-umax, umax], the warm start included (NaN stays)
+  auto clamp_u = [&](double v) { return v < -o.umax ? -o.umax : (v > o.umax ? o.umax : v); };
+  if (bounded)
+    for (auto& v : U) v = clamp_u(v);
   double J = rollout(s, T, x0, U.data(), X.data());
   uint32_t status = 0;
   int iters = 0;
@@ -825,6 +953,9 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
   std::vector<double> A(n * n), B(n * m), lx(n), lu(m), lxx(n * n), luu(m * m), lux(m * n);
   std::vector<double> Qc(n * n), Rc(m * m), P(n * n), p(n), PA(n * n), PB(n * m);
   std::vector<double> Qx(n), Qu(m), Qxx(n * n), Quu(m * m), Qux(m * n), L(m * m), rhs(m * (n + 1));
+  std::vector<double> lo(m), hi(m), LF;
+  std::vector<char> held;
+  std::vector<int> F;
 
   const bool lm = o.reg == 1;
   double mu = o.mu0;
@@ -901,6 +1032,29 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
         for (int j = 0; j < n; ++j) Kk[i * n + j] = -rhs[i * (n + 1) + j];
         kk[i] = -rhs[i * (n + 1) + n];
       }
+      if (bounded) {
+        // the step minimises the local model over the box u_k + d in
+        // [-umax, umax]; held components get no feedback, the free ones the
+        // feedback of their block of Q_uu
+        for (int i = 0; i < m; ++i) {
+          lo[i] = -o.umax - uk[i];
+          hi[i] = o.umax - uk[i];
+        }
+        if (!box_qp(m, Quu.data(), Qu.data(), lo.data(), hi.data(), kk, held)) return ST_CHOL_FAIL;
+        bool any = false;
+        for (int i = 0; i < m; ++i) any = any || held[i];
+        if (any) {
+          if (!face_factor(m, Quu.data(), held, F, LF)) return ST_CHOL_FAIL;
+          const int f = (int)F.size();
+          std::vector<double> col(f);
+          for (int j = 0; j < n; ++j) {
+            for (int a = 0; a < f; ++a) col[a] = Qux[F[a] * n + j];
+            if (f) chol_solve(f, LF.data(), col.data(), 1);
+            for (int i = 0; i < m; ++i) Kk[i * n + j] = 0.0;
+            for (int a = 0; a < f; ++a) Kk[F[a] * n + j] = -col[a];
+          }
+        }
+      }
       if (!all_finite(Kk, m * n) || !all_finite(kk, m)) return ST_NONFINITE;
       // P = sym(Q_xx + Q_ux^T K), p = Q_x + Q_ux^T k
       for (int i = 0; i < n; ++i) {
@@ -940,7 +1094,7 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
         for (int i = 0; i < m; ++i) {
           double v = U[k * m + i] + alpha * kk[i];
           for (int t = 0; t < n; ++t) v += Kk[i * n + t] * (Xn[k * n + t] - X[k * n + t]);
-          Un[k * m + i] = v;
+          Un[k * m + i] = bounded ? clamp_u(v) : v;
         }
         Jh += cost<double>(s, Xn.data() + k * n, Un.data() + k * m);
         dyn<double>(s, Xn.data() + k * n, Un.data() + k * m, Xn.data() + (k + 1) * n);
@@ -1032,6 +1186,7 @@ struct orc_opts {
   double rtol;
   int32_t reg;
   double mu0, mu_factor, mu_max;
+  double umax;
 };
 
 const char* orc_last_error() { return g_err; }
@@ -1085,6 +1240,16 @@ int orc_term_derivs(int kind, const double* p, int np, const double* x, double* 
   Sys s;
   if (!make_sys(kind, p, np, &s)) return -1;
   term_derivs(s, x, lx, lxx);
+  return 0;
+}
+
+// Bounded control step (see box_qp): d in/out, held[m] out.
+int orc_box_qp(int m, const double* H, const double* g, const double* lo, const double* hi, double* d,
+               int32_t* held_out) {
+  if (m < 1) return -1;
+  std::vector<char> held;
+  if (!box_qp(m, H, g, lo, hi, d, held)) return 1;
+  for (int i = 0; i < m; ++i) held_out[i] = held[i];
   return 0;
 }
 
@@ -1158,7 +1323,7 @@ int orc_solve_batch(int kind, const double* p, int np, int B, int Tmax, const in
   }
   const int n = s.n, m = s.m;
   Opts o{opt->max_iter, opt->ls_trials, opt->stop_mode, opt->lookahead, opt->eps, opt->beta, opt->rtol,
-         opt->reg, opt->mu0, opt->mu_factor, opt->mu_max};
+         opt->reg, opt->mu0, opt->mu_factor, opt->mu_max, opt->umax};
   const size_t sx = (size_t)(Tmax + 1) * n, su = (size_t)Tmax * m;
   std::memset(X, 0, sizeof(double) * sx * B);
   std::memset(U, 0, sizeof(double) * su * B);

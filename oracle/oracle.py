@@ -35,7 +35,7 @@ class _Opts(C.Structure):
                 ("stop_mode", C.c_int32), ("lookahead", C.c_int32),
                 ("eps", C.c_double), ("beta", C.c_double), ("rtol", C.c_double),
                 ("reg", C.c_int32), ("mu0", C.c_double), ("mu_factor", C.c_double),
-                ("mu_max", C.c_double)]
+                ("mu_max", C.c_double), ("umax", C.c_double)]
 
 
 _lib = None
@@ -73,11 +73,13 @@ class Options:
     mu0: float = 1e-6
     mu_factor: float = 10.0
     mu_max: float = 1e10
+    # control bound |u_k,i| <= umax of eq. 1 (infinite: unbounded)
+    umax: float = float("inf")
 
     def c(self):
         return _Opts(self.max_iter, self.ls_trials, self.stop_mode, self.lookahead,
                      self.eps, self.beta, self.rtol, self.reg, self.mu0, self.mu_factor,
-                     self.mu_max)
+                     self.mu_max, self.umax)
 
 
 def dims(kind, params):
@@ -134,6 +136,18 @@ def term_derivs(kind, params, x):
     lx, lxx = np.zeros(n), np.zeros((n, n))
     lib().orc_term_derivs(kind, _p(params), len(params), _p(_f64(x)), _p(lx), _p(lxx))
     return lx, lxx
+
+
+def box_qp(H, g, lo, hi):
+    """Bounded control step: (d, held) minimising 0.5 d'Hd + g'd over lo <= d <= hi
+    (the oracle's active-set solver, started from the unconstrained minimiser)."""
+    H, g, lo, hi = _f64(H), _f64(g), _f64(lo), _f64(hi)
+    m = len(g)
+    d = -np.linalg.solve(H, g)
+    held = np.zeros(m, np.int32)
+    if lib().orc_box_qp(m, _p(H), _p(g), _p(lo), _p(hi), _p(d), held.ctypes.data_as(C.c_void_p)) != 0:
+        raise ValueError("a face of H does not factorise")
+    return d, held.astype(bool)
 
 
 def psd_clip(H, eps):

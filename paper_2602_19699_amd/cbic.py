@@ -38,7 +38,7 @@ class _Opts(C.Structure):
                 ("rtol", C.c_double), ("lookahead_K", C.c_int32), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("group_lanes", C.c_int32),
                 ("flags", C.c_uint32), ("regularization", C.c_int32), ("lm_mu0", C.c_double),
-                ("lm_factor", C.c_double), ("lm_mu_max", C.c_double)]
+                ("lm_factor", C.c_double), ("lm_mu_max", C.c_double), ("u_max", C.c_double)]
 
 
 class _Outputs(C.Structure):
@@ -140,13 +140,14 @@ class Options:
     lm_mu0: float = 1e-6
     lm_factor: float = 10.0
     lm_mu_max: float = 1e10
+    u_max: float = float("inf")  # control bound |u_k,i| <= u_max of eq. 1; inf: none
 
     def c(self) -> _Opts:
         o = _Opts()
         _check(lib().cbic_opts_default(C.byref(o)))
         for f in ("max_iter", "psd_eps", "ls_max_trials", "ls_beta", "stop_mode", "rtol", "lookahead_K",
                   "precision", "schedule", "iters_per_launch", "group_lanes", "flags", "regularization",
-                  "lm_mu0", "lm_factor", "lm_mu_max"):
+                  "lm_mu0", "lm_factor", "lm_mu_max", "u_max"):
             setattr(o, f, getattr(self, f))
         return o
 

@@ -1,6 +1,7 @@
 // Autotuner for the lane schedule: times every lanes-per-instance width on
 // the caller's own problem and keeps the fastest per problem class in the
 // context, where solves with group_lanes = 0 find it.
+#include <cmath>
 #include <cstdio>
 #include <vector>
 
@@ -11,9 +12,10 @@ namespace cbic {
 std::string tune_key(const cbic_system* sys, int B, int Tmax, const cbic_solve_opts* o) {
   int b2 = 1;
   while (b2 < B) b2 <<= 1;
-  char k[160];
-  std::snprintf(k, sizeof k, "%d|%d|%d|%d|%d|%d|%d|%d|%d", sys->kind, sys->n, sys->m, o->precision, o->stop_mode,
-                o->max_iter, o->ls_max_trials, b2, Tmax);
+  char k[192];
+  std::snprintf(k, sizeof k, "%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", sys->kind, sys->n, sys->m, o->precision,
+                o->stop_mode, o->max_iter, o->ls_max_trials, b2, Tmax, o->regularization,
+                std::isfinite(o->u_max) ? 1 : 0);
   return k;
 }
 

@@ -58,6 +58,7 @@ cbic_status check_opts(const cbic_solve_opts* o) {
     set_error("Levenberg-Marquardt needs finite lm_mu0 > 0, lm_factor > 1 and lm_mu_max >= lm_mu0");
     return CBIC_E_INVALID;
   }
+  if (!(o->u_max > 0.0)) { set_error("u_max must be > 0 (+infinity: unbounded)"); return CBIC_E_INVALID; }
   return CBIC_OK;
 }
 
@@ -72,6 +73,7 @@ SolveParamsH solve_params(const cbic_solve_opts* o) {
     sp.mu_fac = o->lm_factor;
     sp.mu_max = o->lm_mu_max;
   }
+  sp.umax = o->u_max;
   return sp;
 }
 
@@ -136,6 +138,7 @@ cbic_status cbic_opts_default(cbic_solve_opts* o) {
   o->lm_mu0 = 1e-6;
   o->lm_factor = 10.0;
   o->lm_mu_max = 1e10;
+  o->u_max = INFINITY;
   return CBIC_OK;
 }
 
@@ -284,6 +287,10 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
     set_error("the Levenberg-Marquardt variant runs on the lane schedule only");
     return CBIC_E_UNSUPPORTED;
   }
+  if (std::isfinite(opts->u_max) && L->schedule != CBIC_SCHED_LANE) {
+    set_error("the control bound runs on the lane schedule only");
+    return CBIC_E_UNSUPPORTED;
+  }
   const SolveParamsH sp = solve_params(opts);
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
@@ -311,7 +318,7 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
   const bool timing = (opts->flags & CBIC_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[0], stream));
   HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
-                  out->cost_trace, stream));
+                  out->cost_trace, sp.umax, stream));
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
   int group = opts->group_lanes;
   if (group <= 0) {
@@ -327,10 +334,11 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
         HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream));
     } else {
       char key[512];
-      std::snprintf(key, sizeof key, "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%d|%.17g|%.17g|%.17g",
+      std::snprintf(key, sizeof key,
+                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%d|%.17g|%.17g|%.17g|%.17g",
                     (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
                     sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
-                    sp.reg, sp.mu0, sp.mu_fac, sp.mu_max);
+                    sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
       auto it = ctx->graphs.find(key);
       if (it == ctx->graphs.end()) {
         cbic_context::GraphEntry ge;

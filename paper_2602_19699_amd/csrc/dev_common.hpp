@@ -237,4 +237,162 @@ __device__ __forceinline__ void chol_solve_neg_fp64(const double l[M][M], const 
   }
 }
 
+// Clamp into [-b, b], keeping NaN (a comparison with NaN is false).
+template <class R>
+__device__ __forceinline__ R clamp_nan(R v, R b) {
+  return v < -b ? -b : (v > b ? b : v);
+}
+__device__ __forceinline__ double clamp_nan2(double v, double lo, double hi) {
+  return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Control step under the bound of eq. 1: minimise 0.5 d'Hd + g'd over
+// lo <= d <= hi, H symmetric positive definite (upper triangle used, with its
+// Cholesky factor lf/invf given), by a primal active-set method:
+//   start from the unconstrained minimiser -H^-1 g; if it is in the box it is
+//   the answer (W = 0, the factor is kept).  Otherwise clamp it into the box
+//   and hold the clamped components at their bounds (the working set W, bit
+//   i; bit i of `up` when at the upper bound), then repeat:
+//   * not yet at the minimiser of the current face: solve for the free
+//     components with W held, y_F = -H_FF^-1 (g_F + H_FW d_W), and move from
+//     d towards y as far as the box allows; a component that reaches a bound
+//     first (smallest step, lowest index on ties) joins W, otherwise d = y;
+//   * at the face's minimiser: the multiplier of a held component is its
+//     gradient g_i + (H d)_i, negated at an upper bound; if one is negative
+//     (the most negative, lowest index on ties) it is released, otherwise d
+//     is optimal.
+// A strictly convex problem ends after finitely many steps; `cap` bounds them
+// (the point reached is feasible either way).  The free block's factor goes
+// to lf/invf (which hold H's factor on entry) with identity rows for the held
+// components, so that
+// -lf^-1 [Q_ux] gives the feedback rows of the free components and zero rows
+// for the held ones.  Returns false when a free block does not factorise.
+template <int M, int NR>
+__device__ __forceinline__ bool box_qp(const double (&H)[M][M], const double (&g)[M], const double (&lo)[M],
+                                       const double (&hi)[M], double (&d)[M], unsigned& W, double (&lf)[M][M],
+                                       double (&invf)[M]) {
+  constexpr unsigned ALL = (1u << M) - 1u;
+  // on entry d = -H^-1 g (the unconstrained step) and lf/invf hold the factor
+  // of H; both stay as they are when d is in the box or not a number (the
+  // caller's finiteness check reports the latter)
+  bool inside = true, nan = false;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    inside = inside && d[i] >= lo[i] && d[i] <= hi[i];
+    nan = nan || !(d[i] == d[i]);
+  }
+  W = 0;
+  if (inside || nan) return true;
+  unsigned up = 0;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    if (d[i] < lo[i]) {
+      d[i] = lo[i];
+      W |= 1u << i;
+    } else if (d[i] > hi[i]) {
+      d[i] = hi[i];
+      W |= 1u << i;
+      up |= 1u << i;
+    }
+  }
+  auto h = [&](int i, int j) { return i <= j ? H[i][j] : H[j][i]; };
+  auto factor_face = [&]() -> bool {
+    double hm[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+      for (int j = i; j < M; ++j)
+        hm[i][j] = ((W >> i) & 1u) || ((W >> j) & 1u) ? (i == j ? 1.0 : 0.0) : H[i][j];
+    return chol_fp64<M, NR>(hm, lf, invf);
+  };
+  constexpr int cap = 4 * M + 4;
+  bool at_min = false;
+  for (int it = 0; it < cap; ++it) {
+    if (!at_min) {
+      if (W == ALL) {
+        at_min = true;
+        continue;
+      }
+      if (!factor_face()) return false;
+      double y[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        double v = g[i];
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if ((W >> j) & 1u) v += h(i, j) * d[j];
+        y[i] = ((W >> i) & 1u) ? 0.0 : -v;
+      }
+      chol_solve_fp64<M>(lf, invf, y);
+      double alpha = 1.0;
+      int blk = -1;
+      bool bup = false;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if ((W >> i) & 1u) continue;
+        const double p = y[i] - d[i];
+        if (p < 0.0) {
+          const double t = (lo[i] - d[i]) / p;
+          if (t < alpha) {
+            alpha = t;
+            blk = i;
+            bup = false;
+          }
+        } else if (p > 0.0) {
+          const double t = (hi[i] - d[i]) / p;
+          if (t < alpha) {
+            alpha = t;
+            blk = i;
+            bup = true;
+          }
+        }
+      }
+      if (blk < 0) {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+          if (!((W >> i) & 1u)) d[i] = y[i];
+        at_min = true;
+      } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          if ((W >> i) & 1u) continue;
+          d[i] = i == blk ? (bup ? hi[i] : lo[i]) : clamp_nan2(d[i] + alpha * (y[i] - d[i]), lo[i], hi[i]);
+        }
+        W |= 1u << blk;
+        up = bup ? (up | (1u << blk)) : (up & ~(1u << blk));
+      }
+    } else {
+      int rel = -1;
+      double lmin = 0.0;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        if (!((W >> i) & 1u)) continue;
+        double gr = g[i];
+#pragma unroll
+        for (int j = 0; j < M; ++j) gr += h(i, j) * d[j];
+        const double lam = ((up >> i) & 1u) ? -gr : gr;
+        if (lam < lmin) {
+          lmin = lam;
+          rel = i;
+        }
+      }
+      if (rel < 0) break;
+      W &= ~(1u << rel);
+      at_min = false;
+    }
+  }
+  // the factor of the final face
+  if (W == 0) return chol_fp64<M, NR>(H, lf, invf);
+  if (W == ALL) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) lf[i][j] = i == j ? 1.0 : 0.0;
+      invf[i] = 1.0;
+    }
+    return true;
+  }
+  return factor_face();
+}
+
 }  // namespace cbic

@@ -53,6 +53,7 @@ struct SolveParams {
   double rtol;
   int32_t reg;  // 1: Levenberg-Marquardt (Q_uu + mu I, mu adapted per instance)
   double mu0, mu_fac, mu_max;
+  double umax;  // control bound of eq. 1 (the BOX kernels; infinite otherwise)
 };
 
 template <class Sys, class R>
@@ -86,12 +87,17 @@ struct Lane {
 
   // ------------------------------------------------------------------ backward
   // One Riccati step at time k from the step's derivatives; updates (P, p)
-  // in place and writes K_k, k_k when `store`.  Returns 0 or the status bit
-  // that freezes the instance.
+  // in place and writes K_k, k_k when `store`.  With BOX the control step
+  // minimises the local model over the box |u_k + d| <= umax (eq. 1) and the
+  // feedback rows of the components held at a bound are zero; u is the
+  // iterate's control at step k.  Returns 0 or the status bit that freezes
+  // the instance.
+  template <bool BOX>
   __device__ static __forceinline__ uint32_t riccati_step(const LaneState<R>& w, int s, int k, const R (&A)[N][N],
                                                           const R (&B)[N][M], const R (&lx)[N], const R (&lu)[M],
                                                           const R (&Qc)[N][N], const R (&Rc)[M][M], R (&P)[N][N],
-                                                          R (&p)[N], bool store, double mu) {
+                                                          R (&p)[N], bool store, double mu, const R (&u)[M],
+                                                          double umax) {
     // PA = P A, PB = P B  (structural zeros of A, B skipped at compile time)
     R PA[N][N], PB[N][M];
 #pragma unroll
@@ -162,8 +168,9 @@ struct Lane {
     if (mu != 0.0)
 #pragma unroll
       for (int i = 0; i < M; ++i) Quu[i][i] += mu;
+    constexpr int NR = sizeof(R) == 4 ? 1 : 2;
     double Lc[M][M], invd[M];
-    if (!chol_fp64<M, sizeof(R) == 4 ? 1 : 2>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    if (!chol_fp64<M, NR>(Quu, Lc, invd)) return ST_CHOL_FAIL;
     R Kk[M][N], kk[M];
     bool fin = true;
     {
@@ -171,6 +178,17 @@ struct Lane {
 #pragma unroll
       for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
       chol_solve_neg_fp64<M>(Lc, invd, col);
+      unsigned held = 0;  // components held at a bound (BOX)
+      if constexpr (BOX) {
+        double g[M], lo[M], hi[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          g[i] = double(Qu[i]);
+          lo[i] = -umax - double(u[i]);
+          hi[i] = umax - double(u[i]);
+        }
+        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd)) return ST_CHOL_FAIL;
+      }
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         kk[i] = R(col[i]);
@@ -179,7 +197,7 @@ struct Lane {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) col[i] = double(Qux[i][j]);
+        for (int i = 0; i < M; ++i) col[i] = ((held >> i) & 1u) ? 0.0 : double(Qux[i][j]);
         chol_solve_neg_fp64<M>(Lc, invd, col);
 #pragma unroll
         for (int i = 0; i < M; ++i) {
@@ -231,9 +249,12 @@ struct Lane {
   // recursion runs.  Every group width goes through the same code, so
   // results do not depend on the width.  Models with constant derivatives
   // (ND = 0) evaluate them per step, with (x_k, u_k) prefetched two steps ahead.
-  template <int GL>
+  //
+  // With BOX the staged chunk also carries the controls u_k ([C][M] after the
+  // derivative blocks) for the bounded control step.
+  template <int GL, bool BOX>
   __device__ static uint32_t backward(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, R eps,
-                                      bool store, R* stage, int r, double mu) {
+                                      bool store, R* stage, int r, double mu, double umax) {
     constexpr int ND = Model::ND;
     constexpr bool staged = ND > 0;
     constexpr int C = staged ? GL * (ND <= 8 ? 2 : 1) : 1;
@@ -259,7 +280,10 @@ struct Lane {
       for (int kc = T - 1; kc >= 0; kc -= C) {
 #pragma unroll
         for (int q = 0; q < PB; ++q)
-          if (kc - (r + q * GL) >= 0) mdl.pack_derivs(px[q], pu[q], stage + (r + q * GL) * ND, eps);
+          if (kc - (r + q * GL) >= 0) {
+            mdl.pack_derivs(px[q], pu[q], stage + (r + q * GL) * ND, eps);
+            if constexpr (BOX) st(stage + C * ND + (r + q * GL) * M, pu[q]);
+          }
 #pragma unroll
         for (int q = 0; q < PB; ++q) {
           const int k = kc - C - (r + q * GL);
@@ -271,9 +295,10 @@ struct Lane {
         stage_sync();
         const int cn = kc + 1 < C ? kc + 1 : C;
         for (int q = 0; q < cn; ++q) {
-          R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
+          R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M], uq[M];
           mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
-          const uint32_t bad = riccati_step(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store, mu);
+          if constexpr (BOX) ld(uq, stage + C * ND + q * M);
+          const uint32_t bad = riccati_step<BOX>(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store, mu, uq, umax);
           if (bad) return bad;
         }
         stage_sync();
@@ -307,7 +332,7 @@ struct Lane {
       R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
       mdl.jac(x, u, A, B);
       mdl.cost_derivs(x, u, lx, lu, Qc, Rc, eps, true);
-      const uint32_t bad = riccati_step(w, s, k, A, B, lx, lu, Qc, Rc, P, p, store, mu);
+      const uint32_t bad = riccati_step<BOX>(w, s, k, A, B, lx, lu, Qc, Rc, P, p, store, mu, u, umax);
       if (bad) return bad;
     }
     return 0;
@@ -350,9 +375,12 @@ struct Lane {
   // r, r + GL, ... of the next chunk from HBM while the current chunk is
   // rolled out, so the loads' latency is covered by a chunk of work.  The
   // group keeps streaming while any of its lanes is still rolling out.
-  template <int GL>
+  //
+  // With BOX the trial's controls are clamped into [-umax, umax] (eq. 1).
+  template <int GL, bool BOX>
   __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, int nb,
-                                 R alpha, double Jcur, bool write, int& steps, R* ring, int r, int gbase) {
+                                 R alpha, double Jcur, bool write, int& steps, R* ring, int r, int gbase,
+                                 R umax) {
     constexpr int CT = GL * PT;
     const unsigned long long gmask = (GL >= 64) ? ~0ull : ((1ull << GL) - 1ull);
     R xh[N];
@@ -394,6 +422,7 @@ struct Lane {
             R u = v[N + i] + alpha * v[N + M + M * N + i];
 #pragma unroll
             for (int j = 0; j < N; ++j) u += v[N + M + i * N + j] * dx[j];
+            if constexpr (BOX) u = clamp_nan(u, umax);
             uh[i] = u;
           }
           Jh += double(mdl.cost(xh, uh));
@@ -432,8 +461,10 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
                                                 const int32_t* __restrict__ slots, int Tmax,
                                                 const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
                                                 const double* __restrict__ x0, const double* __restrict__ U0,
-                                                int max_iter, double* __restrict__ trace) {
-  // thread t initialises slot slots[t] (or t) from caller instance perm[t] (or t).
+                                                int max_iter, double* __restrict__ trace, double umax) {
+  // thread t initialises slot slots[t] (or t) from caller instance perm[t] (or t);
+  // the warm start's controls are clamped into [-umax, umax] (eq. 1; umax may
+  // be infinite)
   using LN = Lane<Sys, R>;
   constexpr int N = Sys::N, M = Sys::M;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -452,7 +483,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   for (int k = 0; k < T; ++k) {
     R u[M];
 #pragma unroll
-    for (int i = 0; i < M; ++i) u[i] = U0 ? R(U0[(size_t(b) * Tmax + k) * M + i]) : R(0);
+    for (int i = 0; i < M; ++i) u[i] = clamp_nan(U0 ? R(U0[(size_t(b) * Tmax + k) * M + i]) : R(0), R(umax));
     LN::st(LN::up(w, 0, k, s), u);
     J += double(mdl.cost(x, u));
     R xn[N];
@@ -487,7 +518,9 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 // sequential rule.  Every lane writes its trial into a trajectory buffer of
 // its own, and the accepted lane's buffer becomes the iterate.  `slots`
 // (optional) maps the group index to a slot, for sparse slot sets.
-template <class Sys, class R, int GL>
+//
+// BOX selects the variant with the control bound of eq. 1 (sp.umax finite).
+template <class Sys, class R, int GL, bool BOX>
 __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
                                                    int nslots, const int32_t* __restrict__ slots,
                                                    SolveParams sp, int iters_this_launch,
@@ -512,7 +545,8 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
   // and the line search's step-record ring; the area stride is padded so that
   // the groups of a wave start on different banks
   constexpr int CT = GL * LN::PT;
-  constexpr int AREA = (staged && C * ND > 2 * CT * LN::SWP) ? C * ND : 2 * CT * LN::SWP;
+  constexpr int DS = staged ? C * (ND + (BOX ? LN::M : 0)) : 0;
+  constexpr int AREA = DS > 2 * CT * LN::SWP ? DS : 2 * CT * LN::SWP;
   constexpr int STRIDE = (AREA + 31) / 32 * 32 + 4;
   __shared__ __align__(16) R stage_mem[(64 / GL) * STRIDE];
   R* stage = stage_mem + (gbase / GL) * STRIDE;
@@ -540,7 +574,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
     // stays within mu_max (the group's lanes decide alike)
     for (;;) {
       ++nsweep;
-      const uint32_t bad = LN::template backward<GL>(mdl, w, s, T, buf, eps, lead, stage, r, mu);
+      const uint32_t bad = LN::template backward<GL, BOX>(mdl, w, s, T, buf, eps, lead, stage, r, mu, sp.umax);
       if (bad) {
         if (lm && bad == ST_CHOL_FAIL && mu * sp.mu_fac <= sp.mu_max) {
           mu *= sp.mu_fac;
@@ -565,7 +599,8 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
           if (j < sp.ls_trials) {
             double alpha = 1.0;
             for (int q = 0; q < j; ++q) alpha *= sp.beta;
-            Jh = LN::template trial<GL>(mdl, w, s, T, buf, wb, R(alpha), J, true, steps, stage, r, gbase);
+            Jh = LN::template trial<GL, BOX>(mdl, w, s, T, buf, wb, R(alpha), J, true, steps, stage, r, gbase,
+                                             R(sp.umax));
           }
           ++npass;
           // every lane writes what it rolled out; the lanes of a group read the
@@ -603,8 +638,8 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
             // alpha = 1 (j == 0) is written while it runs, as is every trial of a
             // one-lane group; the commit is written by the group's lead lane
             const bool wr = commit ? lead : (j == 0 || GL == 1);
-            Jh = LN::template trial<GL>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr, steps,
-                                        stage, r, gbase);
+            Jh = LN::template trial<GL, BOX>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr,
+                                             steps, stage, r, gbase, R(sp.umax));
           }
           ++npass;
           if (commit) {

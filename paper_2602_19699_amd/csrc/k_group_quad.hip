@@ -956,7 +956,8 @@ struct QuadLaunch {
 
   static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
-                         int max_iter, double* trace, hipStream_t st) {
+                         int max_iter, double* trace, double /*umax: the bound is not offered here*/,
+                         hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,

@@ -48,6 +48,7 @@ inline SolveParams to_dev(const SolveParamsH& h) {
   s.mu0 = h.mu0;
   s.mu_fac = h.mu_fac;
   s.mu_max = h.mu_max;
+  s.umax = h.umax;
   return s;
 }
 
@@ -62,20 +63,26 @@ struct LaneLaunch {
 
   static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
-                         int max_iter, double* trace, hipStream_t st) {
+                         int max_iter, double* trace, double umax, hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     hipLaunchKernelGGL((lane_init<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
-                       slots, Tmax, Tin, perm, x0, U0, max_iter, trace);
+                       slots, Tmax, Tin, perm, x0, U0, max_iter, trace, umax);
     return hipGetLastError();
   }
 
+  // the bounded variant (eq. 1) is a kernel of its own, so that the
+  // unbounded one keeps its register allocation
   template <int GL>
   static hipError_t iterate_g(const double* prm, const LaneState<R>& w, int nthreads, const int32_t* slots,
                               const SolveParams& sp, int G, double* trace, hipStream_t st) {
     const long total = long(nthreads) * GL;
-    hipLaunchKernelGGL((lane_iterate<Sys, R, GL>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                       nthreads, slots, sp, G, trace);
+    if (__builtin_isfinite(sp.umax))
+      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, true>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
+                         nthreads, slots, sp, G, trace);
+    else
+      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, false>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
+                         nthreads, slots, sp, G, trace);
     return hipGetLastError();
   }
 

@@ -42,6 +42,8 @@ struct SolveParamsH {
   // Levenberg-Marquardt (reg = 1; eps is then negative: no clipping)
   int32_t reg = 0;
   double mu0 = 0.0, mu_fac = 1.0, mu_max = 0.0;
+  // control bound of eq. 1 (infinite: none)
+  double umax = __builtin_inf();
 };
 
 struct FinalOutH {
@@ -61,7 +63,7 @@ struct Launcher {
   size_t (*ws_bytes)(int Bcap, int Tcap);
   hipError_t (*init)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                      int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
-                     int max_iter, double* trace, hipStream_t st);
+                     int max_iter, double* trace, double umax, hipStream_t st);
   hipError_t (*iterate)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                         const SolveParamsH& sp, int G, int group, double* trace, hipStream_t st);
   hipError_t (*finalize)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,

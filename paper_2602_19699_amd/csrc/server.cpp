@@ -5,6 +5,7 @@
 // stream per class, so classes overlap on the GPU), keep their iterates in
 // device memory between launches, and are extracted, copied to host and
 // freed when they finish.
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -245,7 +246,7 @@ bool admit(cbic_server* srv, Pool* p) {
   SRV_TRY(hipMemcpyAsync(p->d_T, p->h_T, 4 * nadm, hipMemcpyHostToDevice, p->stream));
   SRV_TRY(hipMemcpyAsync(p->d_adm, p->h_adm, 4 * nadm, hipMemcpyHostToDevice, p->stream));
   SRV_TRY(p->L->init(p->sys->d_prm, p->ws, p->Bcap, p->Tcap, nadm, p->d_adm, p->Tcap, p->d_T, nullptr, p->d_x0,
-                     p->d_U0, p->opts.max_iter, nullptr, p->stream));
+                     p->d_U0, p->opts.max_iter, nullptr, __builtin_inf(), p->stream));
   return true;
 }
 
@@ -446,6 +447,11 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   if (opts->precision != CBIC_FP64 && opts->precision != CBIC_MIXED) { set_error("bad precision"); return CBIC_E_INVALID; }
   if (opts->regularization != CBIC_REG_CLIP) {
     set_error("the server runs the clipped regularization only");
+    return CBIC_E_UNSUPPORTED;
+  }
+  if (!(opts->u_max > 0.0)) { set_error("u_max must be > 0"); return CBIC_E_INVALID; }
+  if (std::isfinite(opts->u_max)) {
+    set_error("the server runs unbounded controls only");
     return CBIC_E_UNSUPPORTED;
   }
   const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, 0);

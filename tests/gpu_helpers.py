@@ -35,7 +35,8 @@ def oracle_opts(**opt):
                        stop_mode=opt.get("stop_mode", 0), lookahead=opt.get("lookahead_K", 0),
                        eps=-np.inf if lm else opt.get("psd_eps", 1e-6), beta=opt.get("ls_beta", 0.5),
                        rtol=opt.get("rtol", 1e-10), reg=1 if lm else 0, mu0=opt.get("lm_mu0", 1e-6),
-                       mu_factor=opt.get("lm_factor", 10.0), mu_max=opt.get("lm_mu_max", 1e10))
+                       mu_factor=opt.get("lm_factor", 10.0), mu_max=opt.get("lm_mu_max", 1e10),
+                       umax=opt.get("u_max", np.inf))
 
 
 def rel(a, b):
