@@ -47,16 +47,16 @@ FETCH_SCALE = 524288.0 / 262159.0
 WRITE_SCALE = 524288.0 / 524288.0
 LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp")
 COUNTERS = {
-    ("pm16k", "mixed_tol1e-7", "lane_iterate<PointMass,float,8>"): {
+    ("pm16k", "mixed_tol1e-7", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "f5cf0e34aa78d199a2035e70242d5437dd4546a4881caa0ce97dc21d38fdb747",
-        "fetch_kib": 695052.1, "write_kib": 501434.0,
+        "sha256": "ab28d1c75ed8950c8a58a3c8a2599023719c1dd3775e3013c60acfeef4d74da3",
+        "fetch_kib": 694613.6, "write_kib": 501618.3,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
-    ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16>"): {
+    ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "ee22bd46394229339ecd7cd78fa7b5539a45a281dad26cbf97fa14c43b5f97a2",
-        "fetch_kib": 6172815.3, "write_kib": 16491061.2,
+        "sha256": "568ab529b4a2f5a541579e6d693d546efc4a648964a09bc4cd6b193a6eecd10d",
+        "fetch_kib": 6180497.5, "write_kib": 16474956.7,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
@@ -244,7 +244,8 @@ def roofline_for(name, form, res, form_opts):
                 "kernel": kernel, "alg_flops_per_launch": res["iterate_alg_flops"],
                 "iterate_ms": round(res["iterate_ms"], 4)}
     sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
-    kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']}>"
+    bounded = "true" if np.isfinite(form_opts.u_max) else "false"
+    kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']},{bounded}>"
     return {"bound": "hbm", "achieved": round(res["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": traffic_for(name, form, kernel),
             "kernel": kernel, "alg_bytes_per_launch": res["iterate_alg_bytes"],
