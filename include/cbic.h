@@ -313,6 +313,76 @@ double cbic_server_clock(const cbic_server* srv);
 cbic_status cbic_server_drain(cbic_server* srv);
 cbic_status cbic_server_destroy(cbic_server* srv);
 
+/* ---- Biased initial states and the actor warm start (paper Sec. II, III) ----
+ * CACTO-BIC ranks 10N candidate initial states by the std-critic's predicted
+ * standard deviation V^std (eq. 6 trains it; Sec. III-C/D) and solves the N
+ * most uncertain ones; from its second iteration the actor's rollouts
+ * warm-start the TO batch (Sec. II).  These calls run those two steps on the
+ * GPU with networks given as plain FP32 multilayer perceptrons.
+ *
+ * cbic_mlp describes a perceptron with `depth` hidden layers of `width` units
+ * and activation `act`, then a linear output layer of out_dim units followed
+ * by `out_act`.  Its parameters are one contiguous FP32 array in device memory
+ * (row-major, y = x W + b):
+ *   W_0 [in_dim][width], b_0 [width],
+ *   then depth - 1 times W_l [width][width], b_l [width],
+ *   then W_out [width][out_dim], b_out [out_dim]
+ * (cbic_mlp_param_count gives the length).  Arithmetic is FP32, as the
+ * paper's networks are.  Time enters the networks as an input feature
+ * tau in [0, 1): the fraction of the episode already elapsed (paper Sec. II
+ * appends time to the state). */
+#define CBIC_ACT_TANH 0
+#define CBIC_ACT_ELU 1
+#define CBIC_ACT_RELU 2
+#define CBIC_OUT_LINEAR 0
+#define CBIC_OUT_TANH 1     /* out_scale * tanh(z): a bounded actor      */
+#define CBIC_OUT_SOFTPLUS 2 /* log(1 + e^z): a positive std-critic output */
+typedef struct {
+  int32_t in_dim;      /* 1..64                                   */
+  int32_t width;       /* 32 or 64                                */
+  int32_t depth;       /* hidden layers, 1..4                     */
+  int32_t out_dim;     /* 1..16                                   */
+  int32_t act;         /* CBIC_ACT_*                              */
+  int32_t out_act;     /* CBIC_OUT_*                              */
+  double out_scale;    /* CBIC_OUT_TANH only; finite              */
+  const float* params; /* device, cbic_mlp_param_count() floats  */
+} cbic_mlp;
+
+/* Number of FP32 parameters of the network (*count); CBIC_E_INVALID for a
+ * description outside the ranges above. */
+cbic_status cbic_mlp_param_count(const cbic_mlp* net, int64_t* count);
+
+/* out[b][o] = net(in[b]) for B rows; d_in [B][in_dim] and d_out [B][out_dim]
+ * are FP32 device arrays.  Asynchronous on `stream`. */
+cbic_status cbic_mlp_forward(cbic_context* ctx, const cbic_mlp* net, int32_t B, const float* d_in, float* d_out,
+                             void* stream);
+
+/* Biased initial-state selection (Sec. III-D): score the Bc candidates
+ * x~_i = (x_i, tau_i) with the std-critic, d_score[i] = V^std(x~_i), and write
+ * to d_sel the indices of the N highest scores in ascending index order
+ * (equal scores: lower index first; NaN scores rank lowest; -0 equals +0).
+ * d_x [Bc][n] (FP64), d_tau [Bc] (FP64, or NULL: the network then takes
+ * the state alone), d_score [Bc] (FP32, written), d_sel [N] (int32), all device
+ * memory.  net->in_dim must be n + 1 with d_tau, n without; out_dim 1.
+ * 0 <= N <= Bc.  The selection runs in one workgroup (it reads the scores a
+ * few times over).  Asynchronous on `stream`.
+ * Errors: CBIC_E_INVALID (bad sizes or network, NULL pointer), CBIC_E_HIP. */
+cbic_status cbic_bic_select(cbic_context* ctx, const cbic_mlp* std_critic, int32_t Bc, int32_t n, const double* d_x,
+                            const double* d_tau, int32_t N, float* d_score, int32_t* d_sel, void* stream);
+
+/* Actor warm start (Sec. II): roll the system out from each initial state under
+ * the actor, u_k = actor(x_k, tau_k) with tau_k = (T_max - T_b + k) / T_max
+ * (an instance of horizon T_b starts T_max - T_b steps into the episode),
+ * x_{k+1} = f(x_k, u_k) in FP64, for k < T_b.  Writes d_U [B][T_max][m] (the
+ * warm start for cbic_solve_batch) and, if not NULL, d_X [B][T_max+1][n];
+ * entries past T_b are zero.  d_T [B] (int32, or NULL: all T_max), d_x0
+ * [B][n].  actor->in_dim must be n + 1, out_dim m.  Lane-schedule systems
+ * only (CBIC_E_UNSUPPORTED for the quadruped).  Asynchronous on `stream`.
+ * Errors: CBIC_E_INVALID, CBIC_E_UNSUPPORTED, CBIC_E_HIP. */
+cbic_status cbic_actor_rollout(cbic_context* ctx, const cbic_system* sys, const cbic_mlp* actor, int32_t B,
+                               int32_t T_max, const int32_t* d_T, const double* d_x0, double* d_U, double* d_X,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1279,6 +1279,96 @@ int orc_p3_ee(const double* p, const double* q, double* ee) {
   return 0;
 }
 
+// ------------------------------------------------------------ networks
+// The perceptron of the biased initial-state selection and the actor warm
+// start (paper Sec. II, III): depth hidden layers of `width` units with
+// activation act (0 tanh, 1 ELU, 2 ReLU), then a linear layer of out_dim
+// units and the output map out_act (0 identity, 1 out_scale * tanh,
+// 2 softplus).  Parameters (FP32, row-major, y = x W + b): W_0 [in][width],
+// b_0, then depth - 1 times W_l [width][width], b_l, then W_out
+// [width][out], b_out.  Evaluated here in FP64.
+struct Net {
+  int in_dim, width, depth, out_dim, act, out_act;
+  double out_scale;
+  const float* p;
+};
+
+double net_act(double z, int act) {
+  if (act == 0) return std::tanh(z);
+  if (act == 1) return z > 0.0 ? z : std::expm1(z);
+  return z > 0.0 ? z : 0.0;
+}
+
+void net_eval(const Net& net, const double* x, double* y) {
+  const int W = net.width;
+  std::vector<double> h(W), g(W);
+  const float* p = net.p;
+  // input layer
+  for (int j = 0; j < W; ++j) {
+    double z = p[net.in_dim * W + j];
+    for (int i = 0; i < net.in_dim; ++i) z += x[i] * (double)p[i * W + j];
+    h[j] = net_act(z, net.act);
+  }
+  p += net.in_dim * W + W;
+  for (int l = 1; l < net.depth; ++l) {
+    for (int j = 0; j < W; ++j) {
+      double z = p[W * W + j];
+      for (int i = 0; i < W; ++i) z += h[i] * (double)p[i * W + j];
+      g[j] = net_act(z, net.act);
+    }
+    h.swap(g);
+    p += W * W + W;
+  }
+  for (int o = 0; o < net.out_dim; ++o) {
+    double z = p[W * net.out_dim + o];
+    for (int j = 0; j < W; ++j) z += h[j] * (double)p[j * net.out_dim + o];
+    if (net.out_act == 1) z = net.out_scale * std::tanh(z);
+    else if (net.out_act == 2) z = std::max(z, 0.0) + std::log1p(std::exp(-std::fabs(z)));
+    y[o] = z;
+  }
+}
+
+// y[b] = net(x[b]) for B rows.
+int orc_mlp_forward(int in_dim, int width, int depth, int out_dim, int act, int out_act, double out_scale,
+                    const float* params, int B, const double* x, double* y) {
+  if (in_dim < 1 || width < 1 || depth < 1 || out_dim < 1) return -1;
+  const Net net{in_dim, width, depth, out_dim, act, out_act, out_scale, params};
+#pragma omp parallel for schedule(static)
+  for (int b = 0; b < B; ++b) net_eval(net, x + (size_t)b * in_dim, y + (size_t)b * out_dim);
+  return 0;
+}
+
+// Actor warm start: u_k = actor(x_k, tau_k), tau_k = (Tmax - T_b + k) / Tmax,
+// x_{k+1} = f(x_k, u_k) for k < T_b; U [B][Tmax][m], X [B][Tmax+1][n], zero
+// past the horizon (all zero for a horizon outside 1..Tmax).
+int orc_actor_rollout(int kind, const double* p, int np, int in_dim, int width, int depth, int out_dim, int act,
+                      int out_act, double out_scale, const float* params, int B, int Tmax, const int32_t* Tb,
+                      const double* x0, double* U, double* X) {
+  Sys s;
+  if (!make_sys(kind, p, np, &s)) return -1;
+  const int n = s.n, m = s.m;
+  if (in_dim != n + 1 || out_dim != m) return -1;
+  const Net net{in_dim, width, depth, out_dim, act, out_act, out_scale, params};
+  std::memset(U, 0, sizeof(double) * (size_t)B * Tmax * m);
+  std::memset(X, 0, sizeof(double) * (size_t)B * (Tmax + 1) * n);
+#pragma omp parallel for schedule(static)
+  for (int b = 0; b < B; ++b) {
+    const int T = Tb ? Tb[b] : Tmax;
+    if (T < 1 || T > Tmax) continue;
+    double* Xb = X + (size_t)b * (Tmax + 1) * n;
+    double* Ub = U + (size_t)b * Tmax * m;
+    std::vector<double> in(n + 1);
+    for (int i = 0; i < n; ++i) Xb[i] = x0[(size_t)b * n + i];
+    for (int k = 0; k < T; ++k) {
+      for (int i = 0; i < n; ++i) in[i] = Xb[k * n + i];
+      in[n] = (double)(Tmax - T + k) / Tmax;
+      net_eval(net, in.data(), Ub + k * m);
+      dyn<double>(s, Xb + k * n, Ub + k * m, Xb + (k + 1) * n);
+    }
+  }
+  return 0;
+}
+
 // Total cost of nb control sequences (each T x m) from one x0, in parallel.
 int orc_rollout_costs(int kind, const double* p, int np, int T, const double* x0, int nb,
                       const double* U, double* J, int nthreads) {

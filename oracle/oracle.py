@@ -273,6 +273,73 @@ def calibrate_max_iter(kind, params, x0, T_max, T=None, opts: Options | None = N
     return percentile_nearest_rank(counts, 99), percentile_nearest_rank(counts, 50), counts
 
 
+@dataclass
+class Net:
+    """A perceptron as the library describes it (cbic_mlp): FP32 parameters,
+    depth hidden layers of `width` units, activation act (0 tanh, 1 ELU,
+    2 ReLU), output map out_act (0 identity, 1 out_scale * tanh, 2 softplus)."""
+    in_dim: int
+    width: int
+    depth: int
+    out_dim: int
+    act: int
+    out_act: int
+    out_scale: float
+    params: np.ndarray  # float32
+
+    def _args(self):
+        self.params = np.ascontiguousarray(self.params, dtype=np.float32)
+        return (self.in_dim, self.width, self.depth, self.out_dim, self.act, self.out_act,
+                C.c_double(self.out_scale), self.params.ctypes.data_as(C.c_void_p))
+
+
+def mlp_forward(net: Net, x):
+    """net(x) for rows x [B][in_dim], in FP64."""
+    x = _f64(x)
+    B = x.shape[0]
+    y = np.zeros((B, net.out_dim))
+    if lib().orc_mlp_forward(*net._args(), B, _p(x), _p(y)) != 0:
+        raise ValueError("bad network")
+    return y
+
+
+def top_n(scores, N):
+    """The N highest scores' indices in ascending index order (Sec. III-D: the N
+    most uncertain candidates): ranking by score, higher first, equal scores by
+    lower index, NaN below everything, -0 equal to +0."""
+    s = np.asarray(scores, dtype=np.float64)
+    key = np.where(np.isnan(s), -np.inf, s)
+    nan_last = np.isnan(s).astype(np.int64)  # NaN after -inf
+    order = np.lexsort((np.arange(len(s)), -key, nan_last))
+    return np.sort(order[:N]).astype(np.int64)
+
+
+def bic_select(net: Net, x, tau, N):
+    """(scores, selected) of the biased initial-state selection: the std-critic's
+    score of every candidate (x_i, tau_i) in FP64 and the top-N indices."""
+    x = _f64(x)
+    inp = x if tau is None else np.concatenate([x, _f64(tau)[:, None]], axis=1)
+    sc = mlp_forward(net, inp)[:, 0]
+    return sc, top_n(sc, N)
+
+
+def actor_rollout(kind, params, net: Net, x0, T_max, T=None):
+    """(U, X) of the actor warm start: u_k = actor(x_k, tau_k), tau_k =
+    (T_max - T_b + k) / T_max, x_{k+1} = f(x_k, u_k); zero past each horizon."""
+    params = _f64(params)
+    x0 = _f64(x0)
+    n, m = dims(kind, params)
+    B = x0.shape[0]
+    U = np.zeros((B, T_max, m))
+    X = np.zeros((B, T_max + 1, n))
+    Tb = None if T is None else np.ascontiguousarray(T, dtype=np.int32)
+    r = lib().orc_actor_rollout(kind, _p(params), len(params), *net._args(), B, T_max,
+                                None if Tb is None else Tb.ctypes.data_as(C.c_void_p), _p(x0), _p(U), _p(X))
+    if r != 0:
+        raise ValueError("bad system or network")
+    return U, X
+
+
 def extract(kind, params, X, U, lookahead=0):
     """(V-bar, V-bar_x, x_K) of the given trajectory X (T+1, n), U (T, m)."""
     params = _f64(params)

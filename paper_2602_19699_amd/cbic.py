@@ -63,6 +63,11 @@ class _ServerStats(C.Structure):
                 ("classes", C.c_int32), ("max_resident", C.c_int32)]
 
 
+class _Mlp(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("width", C.c_int32), ("depth", C.c_int32), ("out_dim", C.c_int32),
+                ("act", C.c_int32), ("out_act", C.c_int32), ("out_scale", C.c_double), ("params", C.c_void_p)]
+
+
 _lib = None
 
 # every entry point of include/cbic.h with its ctypes signature
@@ -83,6 +88,12 @@ _SIGS = {
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_calibrate_max_iter": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                             C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_mlp_param_count": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "cbic_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_bic_select": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_actor_rollout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_opts_default": (C.c_int32, [C.c_void_p]),
     "cbic_server_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_submit": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
@@ -308,6 +319,91 @@ def calibrate_max_iter(ctx: Context, sys: System, x0, T_max: int, T=None, opts: 
                                          cap, st, C.byref(p99), C.byref(p50),
                                          hist.ctypes.data_as(C.c_void_p)))
     return p99.value, p50.value, hist
+
+
+# ---------------------------------------------------------------- networks
+ACT_TANH, ACT_ELU, ACT_RELU = 0, 1, 2
+OUT_LINEAR, OUT_TANH, OUT_SOFTPLUS = 0, 1, 2
+
+
+@dataclass
+class Mlp:
+    """A perceptron for the biased initial-state selection and the actor warm
+    start: `params` is a float32 device tensor in the library's packed layout
+    (see cbic_mlp in include/cbic.h)."""
+    in_dim: int
+    width: int
+    depth: int
+    out_dim: int
+    params: object  # torch.Tensor, float32, on the device
+    act: int = ACT_TANH
+    out_act: int = OUT_LINEAR
+    out_scale: float = 1.0
+
+    def c(self) -> _Mlp:
+        import torch
+        if self.params.dtype != torch.float32 or not self.params.is_contiguous() or not self.params.is_cuda:
+            raise ValueError("network parameters must be a contiguous float32 device tensor")
+        m = _Mlp(self.in_dim, self.width, self.depth, self.out_dim, self.act, self.out_act, self.out_scale,
+                 self.params.data_ptr())
+        n = C.c_int64()
+        _check(lib().cbic_mlp_param_count(C.byref(m), C.byref(n)))
+        if self.params.numel() < n.value:
+            raise ValueError(f"the network needs {n.value} parameters, the tensor holds {self.params.numel()}")
+        return m
+
+    def param_count(self) -> int:
+        n = C.c_int64()
+        m = _Mlp(self.in_dim, self.width, self.depth, self.out_dim, self.act, self.out_act, self.out_scale, None)
+        _check(lib().cbic_mlp_param_count(C.byref(m), C.byref(n)))
+        return n.value
+
+
+def _stream(ctx, stream):
+    import torch
+    return stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", ctx.device)).cuda_stream
+
+
+def mlp_forward(ctx: Context, net: Mlp, x, stream=None):
+    """net(x) for float32 device rows x [B][in_dim]."""
+    import torch
+    x = x.to(dtype=torch.float32).contiguous()
+    y = torch.empty((x.shape[0], net.out_dim), dtype=torch.float32, device=x.device)
+    m = net.c()
+    _check(lib().cbic_mlp_forward(ctx.h, C.byref(m), x.shape[0], x.data_ptr(), y.data_ptr(), _stream(ctx, stream)))
+    return y
+
+
+def bic_select(ctx: Context, std_critic: Mlp, x, tau, N: int, stream=None):
+    """Biased initial-state selection (paper Sec. III-D): returns (scores, sel),
+    the std-critic's score of each candidate (x_i, tau_i) and the indices of the
+    N highest scores in ascending order.  x [Bc][n] and tau [Bc] (or None)
+    are device tensors."""
+    import torch
+    x = x.to(dtype=torch.float64).contiguous()
+    tau = None if tau is None else tau.to(device=x.device, dtype=torch.float64).contiguous()
+    Bc, n = x.shape
+    score = torch.empty(Bc, dtype=torch.float32, device=x.device)
+    sel = torch.empty(N, dtype=torch.int32, device=x.device)
+    m = std_critic.c()
+    _check(lib().cbic_bic_select(ctx.h, C.byref(m), Bc, n, x.data_ptr(), _dptr(tau), N, score.data_ptr(),
+                                 sel.data_ptr() if N > 0 else None, _stream(ctx, stream)))
+    return score, sel
+
+
+def actor_rollout(ctx: Context, sys: System, actor: Mlp, x0, T_max: int, T=None, states=False, stream=None):
+    """Actor warm start (paper Sec. II): U [B][T_max][m] (and X [B][T_max+1][n]
+    with states=True) of the rollouts u_k = actor(x_k, tau_k) from x0."""
+    import torch
+    x0 = x0.to(dtype=torch.float64).contiguous()
+    B = x0.shape[0]
+    T = None if T is None else T.to(device=x0.device, dtype=torch.int32).contiguous()
+    U = torch.empty((B, T_max, sys.m), dtype=torch.float64, device=x0.device)
+    X = torch.empty((B, T_max + 1, sys.n), dtype=torch.float64, device=x0.device) if states else None
+    m = actor.c()
+    _check(lib().cbic_actor_rollout(ctx.h, sys.h, C.byref(m), B, T_max, _dptr(T), x0.data_ptr(), U.data_ptr(),
+                                    _dptr(X), _stream(ctx, stream)))
+    return (U, X) if states else U
 
 
 # ---------------------------------------------------------------- serving

@@ -173,6 +173,47 @@ def lq_x0(B: int, n: int, seed: int = 1000) -> np.ndarray:
     return rng.uniform(-1.0, 1.0, (B, n))
 
 
+# ---------------------------------------------------------------- networks
+def mlp_param_count(in_dim: int, width: int, depth: int, out_dim: int) -> int:
+    return in_dim * width + width + (depth - 1) * (width * width + width) + width * out_dim + out_dim
+
+
+def mlp_params(in_dim: int, width: int, depth: int, out_dim: int, seed: int = 0,
+               bias_std: float = 0.1) -> np.ndarray:
+    """Random-initialised perceptron parameters in the packed layout of the
+    library (W_0, b_0, ..., W_out, b_out; row-major, y = x W + b), FP32:
+    weights N(0, 1/fan_in) (LeCun normal, the usual default of the paper's
+    network library), biases N(0, bias_std^2) so that the bias paths matter.
+    Stand-ins for trained networks, which the paper does not publish."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    fan = in_dim
+    for _ in range(depth):
+        parts += [rng.normal(0.0, 1.0 / np.sqrt(fan), (fan, width)).ravel(), rng.normal(0.0, bias_std, width)]
+        fan = width
+    parts += [rng.normal(0.0, 1.0 / np.sqrt(fan), (fan, out_dim)).ravel(), rng.normal(0.0, bias_std, out_dim)]
+    out = np.concatenate(parts).astype(np.float32)
+    assert out.size == mlp_param_count(in_dim, width, depth, out_dim)
+    return out
+
+
+def bic_candidates(name: str, Bc: int, seed: int = 3001):
+    """Candidate initial states of the biased selection (Sec. III-D): 10N
+    draws from the workload's initial-state distribution with a start time
+    tau = s / T_max, s uniform on 0..T_max-1 steps (the remaining horizon is
+    then T_max - s).  Returns (x [Bc][n], tau [Bc], T [Bc])."""
+    kind, params, _, T_max, _ = workload(name, B=1)
+    if kind == SYS_POINT_MASS:
+        x = point_mass_x0(Bc, seed)
+    elif kind == SYS_PLANAR3:
+        x = planar3_x0(Bc, seed)
+    else:
+        raise ValueError("candidates are drawn for the point mass and the arm")
+    rng = np.random.default_rng(seed + 1)
+    steps = rng.integers(0, T_max, Bc)
+    return x, steps / T_max, (T_max - steps).astype(np.int32)
+
+
 # ---------------------------------------------------------------- workloads
 def workload(name: str, B: int | None = None, sys_seed: int = 0):
     """Return (kind, params, x0, T_max, T_per_instance or None) for a named workload.
