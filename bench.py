@@ -252,6 +252,67 @@ def roofline_for(name, form, res, form_opts):
             "iterate_ms": round(res["iterate_ms"], 4)}
 
 
+def bic_pipeline(ctx, steps, warmup):
+    """One CACTO-BIC TO batch at the headline scale (paper Sec. III-D, II):
+    score 10N = 163840 point-mass candidate initial states (remaining horizons
+    uniform on 1..100) with the std-critic, keep the N = 16384 most uncertain,
+    roll the actor out from them as the warm start and solve the batch (mixed
+    form, relative-decrease stop 1e-7).  Random-weight networks (two hidden
+    layers of 64 tanh units; softplus std-critic, 10 tanh actor) stand in for
+    trained ones.  Each stage is timed with HIP events on the stream."""
+    import torch
+    from paper_2602_19699_amd import cbic, inputs as I
+    dev = torch.device("cuda", 0)
+    N, Bc = 16384, 163840
+    kind, params, _, T_max, _ = I.workload("pm16k", B=1)
+    x, T, _ = I.bic_candidates("pm16k", Bc)
+    xd, Td = torch.as_tensor(x, device=dev), torch.as_tensor(T, device=dev)
+    sysm = cbic.System(ctx, kind, params)
+    std = cbic.Mlp(5, 64, 2, 1, torch.as_tensor(I.mlp_params(5, 64, 2, 1, seed=101), device=dev), cbic.ACT_TANH,
+                   cbic.OUT_SOFTPLUS)
+    actor = cbic.Mlp(5, 64, 2, 2, torch.as_tensor(I.mlp_params(5, 64, 2, 2, seed=102), device=dev), cbic.ACT_TANH,
+                     cbic.OUT_TANH, 10.0)
+    opts = cbic.Options(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)
+    out = cbic.Outputs.allocate(N, T_max, sysm.n, sysm.m, dev, targets=True)
+    stream = torch.cuda.current_stream(dev)
+    cbic.autotune(ctx, sysm, xd[:N].contiguous(), T_max, T=Td[:N].contiguous(), opts=opts)
+
+    def step(ev=None):
+        if ev: ev[0].record(stream)
+        _, _, xs, Ts = cbic.bic_select(ctx, std, xd, Td, T_max, N, gather=True)
+        if ev: ev[1].record(stream)
+        U0 = cbic.actor_rollout(ctx, sysm, actor, xs, T_max, T=Ts)
+        if ev: ev[2].record(stream)
+        cbic.solve_batch(ctx, sysm, xs, T_max, T=Ts, U0=U0, opts=opts, out=out)
+        if ev: ev[3].record(stream)
+        return Ts
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for ev in evs:
+        Ts = step(ev)
+    torch.cuda.synchronize(dev)
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    st = np.array([[ev[i].elapsed_time(ev[i + 1]) for i in range(3)] for ev in evs])
+    med = np.median(st, axis=0)
+    iters = out.iters.float().mean().item()
+    # the same solve from the zero warm start, for the iteration count
+    cbic.solve_batch(ctx, sysm, out.X[:, 0].contiguous(), T_max, T=Ts, opts=opts, out=out)
+    torch.cuda.synchronize(dev)
+    iters0 = out.iters.float().mean().item()
+    sysm.close()
+    flops = 2.0 * Bc * (5 * 64 + 64 + 64 * 64 + 64 + 64 + 1)
+    return {"workload": "CACTO-BIC batch: 163840 point-mass candidates (T uniform 1..100) -> std-critic scores -> "
+                        "top 16384 -> actor warm start -> mixed solve (tol 1e-7); random-weight 2x64 tanh networks",
+            "ms_per_batch": round(wall, 4), "select_ms": round(float(med[0]), 4), "actor_ms": round(float(med[1]), 4),
+            "solve_ms": round(float(med[2]), 4), "mean_iters_actor_warm_start": round(iters, 4),
+            "mean_iters_zero_warm_start": round(iters0, 4), "select_scoring_flops": flops,
+            "steps": steps}
+
+
 def serving(ctx, rates, seconds):
     """Open-loop Poisson serving: requests drawn 50/30/20 from the point mass,
     the arm and the quadruped, horizons uniform on 20..200, FP64 with the
@@ -288,6 +349,7 @@ def main():
                     help="only three plain 512 MiB device copies (to scale the HBM byte counters)")
     ap.add_argument("--serving-sweep", action="store_true",
                     help="only the serving workload: Poisson rates 1k..50k/s, one JSON line")
+    ap.add_argument("--bic", action="store_true", help="only the CACTO-BIC batch pipeline, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the instances are independent and a "
@@ -310,6 +372,9 @@ def main():
     ctx = cbic.Context(0)
     if args.serving_sweep:
         print(json.dumps(serving(ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=2.0)))
+        return
+    if args.bic:
+        print(json.dumps(bic_pipeline(ctx, steps=args.steps, warmup=args.warmup)))
         return
 
     F = cbic.Options
@@ -355,6 +420,7 @@ def main():
           "quad1k": "quadruped-sized system (n=37, m=12), B=1024, T=100"}[nme]
     serve = None if (args.quick or args.only or args.workload) else serving(
         ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=1.5)
+    bic = None if (args.quick or args.only or args.workload) else bic_pipeline(ctx, steps=10, warmup=2)
     line = {
         "metric": METRIC,
         "value": round(h["converged_solves_per_s"], 1),
@@ -376,6 +442,7 @@ def main():
         "max_iter_calibration": entry["max_iter_calibration"],
         "workloads": other,
         "serving": serve,
+        "bic_pipeline": bic,
     }
     print(json.dumps(line))
 

@@ -361,14 +361,20 @@ cbic_status cbic_mlp_forward(cbic_context* ctx, const cbic_mlp* net, int32_t B, 
  * x~_i = (x_i, tau_i) with the std-critic, d_score[i] = V^std(x~_i), and write
  * to d_sel the indices of the N highest scores in ascending index order
  * (equal scores: lower index first; NaN scores rank lowest; -0 equals +0).
- * d_x [Bc][n] (FP64), d_tau [Bc] (FP64, or NULL: the network then takes
- * the state alone), d_score [Bc] (FP32, written), d_sel [N] (int32), all device
- * memory.  net->in_dim must be n + 1 with d_tau, n without; out_dim 1.
- * 0 <= N <= Bc.  The selection runs in one workgroup (it reads the scores a
- * few times over).  Asynchronous on `stream`.
+ * A candidate carries its remaining horizon T_i (1..T_max): it starts
+ * T_max - T_i steps into the episode, tau_i = (T_max - T_i) / T_max (the time
+ * convention of cbic_actor_rollout).  d_x [Bc][n] (FP64), d_T [Bc] (int32, or
+ * NULL: the network then takes the state alone), d_score [Bc] (FP32,
+ * written), d_sel [N] (int32); optional gathered outputs for the next TO
+ * batch: d_x_sel [N][n] (the selected states, in d_sel's order) and d_T_sel
+ * [N] (their horizons; requires d_T).  All device memory.  net->in_dim must
+ * be n + 1 with d_T, n without; out_dim 1.  0 <= N <= Bc.  The selection runs
+ * in one workgroup (it reads the scores a few times over).  Asynchronous on
+ * `stream`.
  * Errors: CBIC_E_INVALID (bad sizes or network, NULL pointer), CBIC_E_HIP. */
 cbic_status cbic_bic_select(cbic_context* ctx, const cbic_mlp* std_critic, int32_t Bc, int32_t n, const double* d_x,
-                            const double* d_tau, int32_t N, float* d_score, int32_t* d_sel, void* stream);
+                            const int32_t* d_T, int32_t T_max, int32_t N, float* d_score, int32_t* d_sel,
+                            double* d_x_sel, int32_t* d_T_sel, void* stream);
 
 /* Actor warm start (Sec. II): roll the system out from each initial state under
  * the actor, u_k = actor(x_k, tau_k) with tau_k = (T_max - T_b + k) / T_max

@@ -314,11 +314,17 @@ def top_n(scores, N):
     return np.sort(order[:N]).astype(np.int64)
 
 
-def bic_select(net: Net, x, tau, N):
+def bic_select(net: Net, x, T, T_max, N):
     """(scores, selected) of the biased initial-state selection: the std-critic's
-    score of every candidate (x_i, tau_i) in FP64 and the top-N indices."""
+    score of every candidate (x_i, tau_i), tau_i = (T_max - T_i) / T_max (a
+    candidate with remaining horizon T_i starts T_max - T_i steps into the
+    episode), in FP64, and the top-N indices.  T None: the state alone."""
     x = _f64(x)
-    inp = x if tau is None else np.concatenate([x, _f64(tau)[:, None]], axis=1)
+    if T is None:
+        inp = x
+    else:
+        tau = (T_max - np.asarray(T, dtype=np.float64)) / T_max
+        inp = np.concatenate([x, tau[:, None]], axis=1)
     sc = mlp_forward(net, inp)[:, 0]
     return sc, top_n(sc, N)
 

@@ -91,7 +91,8 @@ _SIGS = {
     "cbic_mlp_param_count": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "cbic_mlp_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_bic_select": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
-                                    C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+                                    C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]),
     "cbic_actor_rollout": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_server_opts_default": (C.c_int32, [C.c_void_p]),
@@ -374,21 +375,26 @@ def mlp_forward(ctx: Context, net: Mlp, x, stream=None):
     return y
 
 
-def bic_select(ctx: Context, std_critic: Mlp, x, tau, N: int, stream=None):
+def bic_select(ctx: Context, std_critic: Mlp, x, T, T_max: int, N: int, gather=False, stream=None):
     """Biased initial-state selection (paper Sec. III-D): returns (scores, sel),
-    the std-critic's score of each candidate (x_i, tau_i) and the indices of the
-    N highest scores in ascending order.  x [Bc][n] and tau [Bc] (or None)
-    are device tensors."""
+    the std-critic's score of each candidate (x_i, tau_i = (T_max - T_i) / T_max)
+    and the indices of the N highest scores in ascending order; with gather=True
+    also the selected states [N][n] and horizons [N] (the next TO batch).
+    x [Bc][n] and T [Bc] (or None: the network takes the state alone) are
+    device tensors."""
     import torch
     x = x.to(dtype=torch.float64).contiguous()
-    tau = None if tau is None else tau.to(device=x.device, dtype=torch.float64).contiguous()
+    T = None if T is None else T.to(device=x.device, dtype=torch.int32).contiguous()
     Bc, n = x.shape
     score = torch.empty(Bc, dtype=torch.float32, device=x.device)
     sel = torch.empty(N, dtype=torch.int32, device=x.device)
+    xs = torch.empty((N, n), dtype=torch.float64, device=x.device) if gather else None
+    Ts = torch.empty(N, dtype=torch.int32, device=x.device) if gather and T is not None else None
     m = std_critic.c()
-    _check(lib().cbic_bic_select(ctx.h, C.byref(m), Bc, n, x.data_ptr(), _dptr(tau), N, score.data_ptr(),
-                                 sel.data_ptr() if N > 0 else None, _stream(ctx, stream)))
-    return score, sel
+    _check(lib().cbic_bic_select(ctx.h, C.byref(m), Bc, n, x.data_ptr(), _dptr(T), T_max, N, score.data_ptr(),
+                                 sel.data_ptr() if N > 0 else None, _dptr(xs) if N > 0 else None,
+                                 _dptr(Ts) if N > 0 else None, _stream(ctx, stream)))
+    return (score, sel, xs, Ts) if gather else (score, sel)
 
 
 def actor_rollout(ctx: Context, sys: System, actor: Mlp, x0, T_max: int, T=None, states=False, stream=None):

@@ -21,32 +21,57 @@ namespace {
     }                                                                   \
   } while (0)
 
-constexpr int kScoreWG = 256;
+constexpr int kNetWG = 256;  // four waves of 16 samples
+
+// Dynamic LDS beyond 64 KiB (the largest networks take up to 79 KiB of the
+// CU's 160 KiB) has to be allowed per kernel before the launch.
+template <class K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(bytes));
+}
 constexpr int kSelectWG = 1024;
 
-// ------------------------------------------------------------------ scoring
-// score[b] = net(x_b, tau_b) for one candidate per lane (FP64 inputs rounded
-// to FP32, as the network computes in FP32).
+// score[b] = net(x_b, tau_b), tau_b = (T_max - T_b) / T_max (FP64 inputs
+// rounded to FP32, as the network computes in FP32); without T the network
+// takes the state alone.  16 candidates per wave.
 template <int W>
-__global__ void __launch_bounds__(kScoreWG) mlp_score(MlpDev net, int B, int n, const double* __restrict__ x,
-                                                      const double* __restrict__ tau, float* __restrict__ score) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const double* xb = x + size_t(b) * n;
-  mlp_eval<W, 0, 1>(
-      net, [&](int i) { return i < n ? float(xb[i]) : float(tau[b]); },
-      [&](int, float v) { score[b] = v; });
+__global__ void __launch_bounds__(kNetWG) mlp_score(MlpDev net, MlpLds L, int B, int n,
+                                                    const double* __restrict__ x, const int32_t* __restrict__ T,
+                                                    int Tmax, float* __restrict__ score) {
+  extern __shared__ float lds[];
+  mlp_stage(net, L, lds);
+  const int lane = threadIdx.x & 63;
+  const int b = (blockIdx.x * (kNetWG / 64) + (threadIdx.x >> 6)) * 16 + (lane & 15);
+  const bool valid = b < B;
+  const double* xb = x + size_t(valid ? b : 0) * n;
+  const float tau = (T && valid) ? float(Tmax - T[b]) * (1.0f / float(Tmax)) : 0.0f;
+  const nf4 y = mlp_tile<W, 0>(net, L, lds, [&](int s, int g) {
+    const int f = 4 * s + g;
+    return !valid ? 0.0f : (f < n ? float(xb[f]) : (f == n && T ? tau : 0.0f));
+  });
+  if (valid && lane < 16) score[b] = y[0];
 }
 
-// out[b][:] = net(in[b][:]) for FP32 rows.
+// out[b][:] = net(in[b][:]) for FP32 rows, 16 rows per wave.
 template <int W>
-__global__ void __launch_bounds__(kScoreWG) mlp_rows(MlpDev net, int B, const float* __restrict__ in,
-                                                     float* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const float* ib = in + size_t(b) * net.in_dim;
-  float* ob = out + size_t(b) * net.out_dim;
-  mlp_eval<W, 0, 0>(net, [&](int i) { return ib[i]; }, [&](int o, float v) { ob[o] = v; });
+__global__ void __launch_bounds__(kNetWG) mlp_rows(MlpDev net, MlpLds L, int B, const float* __restrict__ in,
+                                                   float* __restrict__ out) {
+  extern __shared__ float lds[];
+  mlp_stage(net, L, lds);
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int b = (blockIdx.x * (kNetWG / 64) + (threadIdx.x >> 6)) * 16 + (lane & 15);
+  const bool valid = b < B;
+  const float* ib = in + size_t(valid ? b : 0) * net.in_dim;
+  const nf4 y = mlp_tile<W, 0>(net, L, lds, [&](int s, int gg) {
+    const int f = 4 * s + gg;
+    return valid && f < net.in_dim ? ib[f] : 0.0f;
+  });
+  if (valid)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (4 * g + r < net.out_dim) out[size_t(b) * net.out_dim + 4 * g + r] = y[r];
 }
 
 // ------------------------------------------------------------------ selection
@@ -59,30 +84,41 @@ __device__ __forceinline__ uint32_t score_key(float s) {
   return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-// Exclusive prefix count of `flag` over the workgroup's threads (in thread
-// order) and the workgroup's total; `wtot` holds one slot per wave.
-__device__ __forceinline__ uint32_t block_scan(bool flag, uint32_t* wtot, uint32_t& total) {
+// Exclusive prefix sum of v over the workgroup's threads (in thread order)
+// and the workgroup's total; `wtot` holds one slot per wave.
+__device__ __forceinline__ uint32_t block_scan(uint32_t v, uint32_t* wtot, uint32_t& total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long bits = __ballot(flag);
-  const uint32_t below = __popcll(bits & ((1ull << lane) - 1ull));
-  if (lane == 0) wtot[wave] = __popcll(bits);
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t u = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += u;
+  }
+  if (lane == 63) wtot[wave] = inc;
   __syncthreads();
   uint32_t before = 0;
   total = 0;
-  for (int v = 0; v < kSelectWG / 64; ++v) {
-    const uint32_t t = wtot[v];
-    before += v < wave ? t : 0u;
+#pragma unroll
+  for (int w = 0; w < kSelectWG / 64; ++w) {
+    const uint32_t t = wtot[w];
+    before += w < wave ? t : 0u;
     total += t;
   }
   __syncthreads();
-  return before + below;
+  return before + inc - v;
 }
 
 // The N highest scores of Bc, in ascending index order (equal scores: lower
 // index first), by a radix select of the N-th largest key (11 + 11 + 10 bits)
-// and an order-preserving compaction.  One workgroup; 1 <= N <= Bc.
+// and an order-preserving compaction, which also gathers the selected rows of
+// x (n wide) and T when xs / Ts are given.  One workgroup; 1 <= N <= Bc.
 __global__ void __launch_bounds__(kSelectWG) topn_select(const float* __restrict__ score, int Bc, int N,
-                                                         int32_t* __restrict__ sel) {
+                                                         int32_t* __restrict__ sel, int n,
+                                                         const double* __restrict__ x,
+                                                         const int32_t* __restrict__ T, double* __restrict__ xs,
+                                                         int32_t* __restrict__ Ts) {
+  constexpr int U = 8;   // keys in flight per thread in the histogram passes
+  constexpr int E = 16;  // consecutive keys per thread in the compaction
   __shared__ uint32_t hist[2048];
   __shared__ uint32_t wtot[kSelectWG / 64];
   __shared__ uint32_t s_bin, s_left;
@@ -93,21 +129,52 @@ __global__ void __launch_bounds__(kSelectWG) topn_select(const float* __restrict
     const uint32_t nb = pass < 2 ? 2048u : 1024u;
     for (uint32_t i = t; i < nb; i += kSelectWG) hist[i] = 0u;
     __syncthreads();
-    for (int i = t; i < Bc; i += kSelectWG) {
-      const uint32_t k = score_key(score[i]);
-      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & (nb - 1u)], 1u);
+    for (int base = 0; base < Bc; base += kSelectWG * U) {
+      uint32_t k[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const int i = base + j * kSelectWG + t;
+        k[j] = i < Bc ? score_key(score[i]) : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j)
+        if (base + j * kSelectWG + t < Bc && (k[j] & mask) == prefix)
+          atomicAdd(&hist[(k[j] >> shift) & (nb - 1u)], 1u);
     }
     __syncthreads();
-    if (t == 0) {
-      // the bin holding the left-th largest remaining key, from the top
-      uint32_t above = 0;
-      int b = int(nb) - 1;
-      for (; b > 0; --b) {
-        if (above + hist[b] >= left) break;
-        above += hist[b];
+    // the bin holding the left-th largest key: thread t owns bins 2t + 1 and
+    // 2t (one bin, t, in the 1024-bin pass); the counts above them come from
+    // a scan over the threads in descending bin order
+    const int per = int(nb) / kSelectWG;
+    const int hi = per == 2 ? 2 * t + 1 : t;
+    const uint32_t mine = per == 2 ? hist[2 * t] + hist[2 * t + 1] : hist[t];
+    // suffix sum over the threads: the keys in the bins above thread t's
+    const uint32_t rev_excl = [&] {
+      const int lane = t & 63, wave = t >> 6;
+      uint32_t inc = mine;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_down(inc, o, 64);
+        if (lane + o < 64) inc += u;
       }
-      s_bin = uint32_t(b);
+      if (lane == 0) wtot[wave] = inc;
+      __syncthreads();
+      uint32_t after = 0;
+#pragma unroll
+      for (int w = 0; w < kSelectWG / 64; ++w) after += w > wave ? wtot[w] : 0u;
+      __syncthreads();
+      return after + inc - mine;
+    }();
+    uint32_t above = rev_excl;
+    if (above < left && left <= above + hist[hi]) {
+      s_bin = uint32_t(hi);
       s_left = left - above;
+    } else if (per == 2) {
+      above += hist[hi];
+      if (above < left && left <= above + hist[hi - 1]) {
+        s_bin = uint32_t(hi - 1);
+        s_left = left - above;
+      }
     }
     __syncthreads();
     prefix |= s_bin << shift;
@@ -115,78 +182,134 @@ __global__ void __launch_bounds__(kSelectWG) topn_select(const float* __restrict
     left = s_left;
     __syncthreads();
   }
-  // prefix is the N-th largest key; `left` keys equal to it are taken
+  // prefix is the N-th largest key; `left` keys equal to it are taken, the
+  // lowest indices first.  Thread t compacts keys [c + E t, c + E t + E).
   uint32_t out_base = 0, tie_base = 0;
-  for (int c = 0; c < Bc; c += kSelectWG) {
-    const int i = c + t;
-    const uint32_t k = i < Bc ? score_key(score[i]) : 0u;
-    const bool gt = i < Bc && k > prefix;
-    const bool eq = i < Bc && k == prefix;
+  for (int c = 0; c < Bc; c += kSelectWG * E) {
+    const int i0 = c + E * t;
+    uint32_t gt = 0, eq = 0, neq = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int i = i0 + j;
+      const uint32_t k = i < Bc ? score_key(score[i]) : 0u;
+      if (i < Bc && k > prefix) gt |= 1u << j;
+      if (i < Bc && k == prefix) {
+        eq |= 1u << j;
+        ++neq;
+      }
+    }
     uint32_t eq_total, take_total;
-    const uint32_t eq_rank = tie_base + block_scan(eq, wtot, eq_total);
-    const bool take = gt || (eq && eq_rank < left);
-    const uint32_t pos = out_base + block_scan(take, wtot, take_total);
-    if (take && pos < uint32_t(N)) sel[pos] = i;
+    uint32_t rank = tie_base + block_scan(neq, wtot, eq_total);
+    uint32_t take = gt, ntake = 0;
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if ((eq >> j) & 1u) {
+        if (rank < left) take |= 1u << j;
+        ++rank;
+      }
+    ntake = __popc(take);
+    uint32_t pos = out_base + block_scan(ntake, wtot, take_total);
+#pragma unroll
+    for (int j = 0; j < E; ++j)
+      if ((take >> j) & 1u) {
+        const int i = i0 + j;
+        if (pos < uint32_t(N)) {
+          sel[pos] = i;
+          if (xs)
+            for (int q = 0; q < n; ++q) xs[size_t(pos) * n + q] = x[size_t(i) * n + q];
+          if (Ts) Ts[pos] = T[i];
+        }
+        ++pos;
+      }
     out_base += take_total;
     tie_base += eq_total;
   }
 }
 
 // ------------------------------------------------------------------ actor rollout
-// One instance per lane: u_k = actor(x_k, tau_k) in FP32, x_{k+1} = f(x_k, u_k)
-// in FP64.  Outputs are zero past the horizon (all zero for a horizon outside
-// 1..T_max).
+// 16 instances per wave, four lanes per instance: the lanes of an instance
+// keep its state and step the FP64 dynamics redundantly, and the wave
+// evaluates u_k = actor(x_k, tau_k) for its 16 instances on the matrix cores.
+// The wave runs until its longest horizon; outputs are zero past each
+// horizon (all zero for a horizon outside 1..T_max).
 template <class Sys, int W>
-__global__ void __launch_bounds__(64) actor_rollout(const double* __restrict__ prm, MlpDev net, int B, int Tmax,
-                                                    const int32_t* __restrict__ Tin, const double* __restrict__ x0,
-                                                    double* __restrict__ U, double* __restrict__ X) {
+__global__ void __launch_bounds__(kNetWG) actor_rollout(const double* __restrict__ prm, MlpDev net, MlpLds L, int B,
+                                                        int Tmax, const int32_t* __restrict__ Tin,
+                                                        const double* __restrict__ x0, double* __restrict__ U,
+                                                        double* __restrict__ X) {
   constexpr int N = Sys::N, M = Sys::M;
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+  constexpr int IN4 = (N + 1 + 3) & ~3;
+  static_assert(M <= 4, "outputs of lane group 0");
+  extern __shared__ float lds[];
+  mlp_stage(net, L, lds);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int b = (blockIdx.x * (kNetWG / 64) + (threadIdx.x >> 6)) * 16 + c;
+  const bool valid = b < B;
   const typename Sys::template Model<double> mdl{prm};
-  const int Tr = Tin ? Tin[b] : Tmax;
+  const int Tr = valid ? (Tin ? Tin[b] : Tmax) : 0;
   const int T = (Tr < 1 || Tr > Tmax) ? 0 : Tr;
-  double* Ub = U + size_t(b) * Tmax * M;
-  double* Xb = X ? X + size_t(b) * (Tmax + 1) * N : nullptr;
+  int Tw = T;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) Tw = max(Tw, __shfl_xor(Tw, o, 64));
+  const bool writer = valid && g == 0;
+  double* Ub = U + size_t(valid ? b : 0) * Tmax * M;
+  double* Xb = X ? X + size_t(valid ? b : 0) * (Tmax + 1) * N : nullptr;
   double x[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = T > 0 ? x0[size_t(b) * N + i] : 0.0;
-  if (Xb)
+  if (writer && Xb)
 #pragma unroll
     for (int i = 0; i < N; ++i) Xb[i] = x[i];
   const float inv_T = 1.0f / float(Tmax);
-  for (int k = 0; k < T; ++k) {
-    const float tau = float(Tmax - T + k) * inv_T;
+  for (int k = 0; k < Tw; ++k) {
+    float f[IN4];
+#pragma unroll
+    for (int i = 0; i < IN4; ++i) f[i] = i < N ? float(x[i < N ? i : 0]) : (i == N ? float(Tmax - T + k) * inv_T : 0.0f);
+    const nf4 y = mlp_tile<W, IN4>(net, L, lds, [&](int s, int gg) {
+      return gg == 0 ? f[4 * s] : (gg == 1 ? f[4 * s + 1] : (gg == 2 ? f[4 * s + 2] : f[4 * s + 3]));
+    });
+    // outputs 0..M-1 of instance c sit in lane c (group 0), registers 0..M-1
     double u[M];
-    mlp_eval<W, N + 1, M>(
-        net, [&](int i) { return i < N ? float(x[i < N ? i : 0]) : tau; }, [&](int o, float v) { u[o] = double(v); });
-    double xn[N];
-    mdl.dyn(x, u, xn);
 #pragma unroll
-    for (int i = 0; i < M; ++i) Ub[size_t(k) * M + i] = u[i];
+    for (int o = 0; o < M; ++o) u[o] = double(__shfl(y[o], c, 64));
+    if (k < T) {
+      double xn[N];
+      mdl.dyn(x, u, xn);
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = xn[i];
-    if (Xb)
+      for (int i = 0; i < N; ++i) x[i] = xn[i];
+      if (writer) {
 #pragma unroll
-      for (int i = 0; i < N; ++i) Xb[size_t(k + 1) * N + i] = x[i];
+        for (int i = 0; i < M; ++i) Ub[size_t(k) * M + i] = u[i];
+        if (Xb)
+#pragma unroll
+          for (int i = 0; i < N; ++i) Xb[size_t(k + 1) * N + i] = x[i];
+      }
+    }
   }
-  for (int k = T; k < Tmax; ++k)
+  if (writer) {
+    for (int k = T; k < Tmax; ++k)
 #pragma unroll
-    for (int i = 0; i < M; ++i) Ub[size_t(k) * M + i] = 0.0;
-  if (Xb)
-    for (int k = T + 1; k <= Tmax; ++k)
+      for (int i = 0; i < M; ++i) Ub[size_t(k) * M + i] = 0.0;
+    if (Xb)
+      for (int k = T + 1; k <= Tmax; ++k)
 #pragma unroll
-      for (int i = 0; i < N; ++i) Xb[size_t(k) * N + i] = 0.0;
+        for (int i = 0; i < N; ++i) Xb[size_t(k) * N + i] = 0.0;
+  }
 }
 
 template <class Sys>
-hipError_t launch_actor(const double* prm, const MlpDev& net, int width, int B, int Tmax, const int32_t* d_T,
+hipError_t launch_actor(const double* prm, const MlpDev& net, const MlpLds& L, int B, int Tmax, const int32_t* d_T,
                         const double* x0, double* U, double* X, hipStream_t st) {
-  const dim3 grid((B + 63) / 64), block(64);
-  if (width == 32)
-    hipLaunchKernelGGL((actor_rollout<Sys, 32>), grid, block, 0, st, prm, net, B, Tmax, d_T, x0, U, X);
-  else
-    hipLaunchKernelGGL((actor_rollout<Sys, 64>), grid, block, 0, st, prm, net, B, Tmax, d_T, x0, U, X);
+  const dim3 grid((B + kNetWG / 4 - 1) / (kNetWG / 4)), block(kNetWG);
+  const size_t lds = size_t(L.total()) * sizeof(float);
+  hipError_t e;
+  if (L.W == 32) {
+    if ((e = allow_lds(actor_rollout<Sys, 32>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((actor_rollout<Sys, 32>), grid, block, lds, st, prm, net, L, B, Tmax, d_T, x0, U, X);
+  } else {
+    if ((e = allow_lds(actor_rollout<Sys, 64>, lds)) != hipSuccess) return e;
+    hipLaunchKernelGGL((actor_rollout<Sys, 64>), grid, block, lds, st, prm, net, L, B, Tmax, d_T, x0, U, X);
+  }
   return hipGetLastError();
 }
 
@@ -242,33 +365,51 @@ cbic_status cbic_mlp_forward(cbic_context* ctx, const cbic_mlp* net, int32_t B, 
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*net);
-  const dim3 grid((B + kScoreWG - 1) / kScoreWG), block(kScoreWG);
-  if (net->width == 32) hipLaunchKernelGGL((mlp_rows<32>), grid, block, 0, st, d, B, d_in, d_out);
-  else hipLaunchKernelGGL((mlp_rows<64>), grid, block, 0, st, d, B, d_in, d_out);
+  const MlpLds L = mlp_lds(net->in_dim, net->width, net->depth, net->out_dim);
+  const dim3 grid((B + kNetWG / 4 - 1) / (kNetWG / 4)), block(kNetWG);
+  const size_t lds = size_t(L.total()) * sizeof(float);
+  if (net->width == 32) {
+    HIP_TRY(allow_lds(mlp_rows<32>, lds));
+    hipLaunchKernelGGL((mlp_rows<32>), grid, block, lds, st, d, L, B, d_in, d_out);
+  } else {
+    HIP_TRY(allow_lds(mlp_rows<64>, lds));
+    hipLaunchKernelGGL((mlp_rows<64>), grid, block, lds, st, d, L, B, d_in, d_out);
+  }
   HIP_TRY(hipGetLastError());
   return CBIC_OK;
 }
 
 cbic_status cbic_bic_select(cbic_context* ctx, const cbic_mlp* net, int32_t Bc, int32_t n, const double* d_x,
-                            const double* d_tau, int32_t N, float* d_score, int32_t* d_sel, void* stream) {
+                            const int32_t* d_T, int32_t T_max, int32_t N, float* d_score, int32_t* d_sel,
+                            double* d_x_sel, int32_t* d_T_sel, void* stream) {
   if (cbic_status st = check_mlp(net)) return st;
-  if (!ctx || !net->params || Bc < 1 || n < 1 || N < 0 || N > Bc || !d_x || !d_score || (N > 0 && !d_sel)) {
-    set_error("ctx, params, d_x, d_score and d_sel are required; Bc >= 1, n >= 1, 0 <= N <= Bc");
+  if (!ctx || !net->params || Bc < 1 || n < 1 || N < 0 || N > Bc || !d_x || !d_score || (N > 0 && !d_sel) ||
+      (d_T && T_max < 1) || (d_T_sel && !d_T)) {
+    set_error("ctx, params, d_x, d_score and d_sel are required (d_T with d_T_sel, T_max >= 1 with d_T); "
+              "Bc >= 1, n >= 1, 0 <= N <= Bc");
     return CBIC_E_INVALID;
   }
-  if (net->in_dim != n + (d_tau ? 1 : 0) || net->out_dim != 1) {
-    set_error("the std-critic must take %d inputs and give one output", n + (d_tau ? 1 : 0));
+  if (net->in_dim != n + (d_T ? 1 : 0) || net->out_dim != 1) {
+    set_error("the std-critic must take %d inputs and give one output", n + (d_T ? 1 : 0));
     return CBIC_E_INVALID;
   }
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*net);
-  const dim3 grid((Bc + kScoreWG - 1) / kScoreWG), block(kScoreWG);
-  if (net->width == 32) hipLaunchKernelGGL((mlp_score<32>), grid, block, 0, st, d, Bc, n, d_x, d_tau, d_score);
-  else hipLaunchKernelGGL((mlp_score<64>), grid, block, 0, st, d, Bc, n, d_x, d_tau, d_score);
+  const MlpLds L = mlp_lds(net->in_dim, net->width, net->depth, net->out_dim);
+  const dim3 grid((Bc + kNetWG / 4 - 1) / (kNetWG / 4)), block(kNetWG);
+  const size_t lds = size_t(L.total()) * sizeof(float);
+  if (net->width == 32) {
+    HIP_TRY(allow_lds(mlp_score<32>, lds));
+    hipLaunchKernelGGL((mlp_score<32>), grid, block, lds, st, d, L, Bc, n, d_x, d_T, T_max, d_score);
+  } else {
+    HIP_TRY(allow_lds(mlp_score<64>, lds));
+    hipLaunchKernelGGL((mlp_score<64>), grid, block, lds, st, d, L, Bc, n, d_x, d_T, T_max, d_score);
+  }
   HIP_TRY(hipGetLastError());
   if (N > 0) {
-    hipLaunchKernelGGL(topn_select, dim3(1), dim3(kSelectWG), 0, st, d_score, Bc, N, d_sel);
+    hipLaunchKernelGGL(topn_select, dim3(1), dim3(kSelectWG), 0, st, d_score, Bc, N, d_sel, n, d_x, d_T, d_x_sel,
+                       d_T_sel);
     HIP_TRY(hipGetLastError());
   }
   return CBIC_OK;
@@ -289,7 +430,7 @@ cbic_status cbic_actor_rollout(cbic_context* ctx, const cbic_system* sys, const 
   HIP_TRY(hipSetDevice(ctx->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*actor);
-  const int w = actor->width;
+  const MlpLds w = mlp_lds(actor->in_dim, actor->width, actor->depth, actor->out_dim);
   hipError_t e;
   if (sys->kind == CBIC_SYS_POINT_MASS) {
     e = launch_actor<PointMass>(sys->d_prm, d, w, B, T_max, d_T, d_x0, d_U, d_X, st);

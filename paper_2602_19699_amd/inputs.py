@@ -198,10 +198,10 @@ def mlp_params(in_dim: int, width: int, depth: int, out_dim: int, seed: int = 0,
 
 
 def bic_candidates(name: str, Bc: int, seed: int = 3001):
-    """Candidate initial states of the biased selection (Sec. III-D): 10N
-    draws from the workload's initial-state distribution with a start time
-    tau = s / T_max, s uniform on 0..T_max-1 steps (the remaining horizon is
-    then T_max - s).  Returns (x [Bc][n], tau [Bc], T [Bc])."""
+    """Candidate initial states of the biased selection (Sec. III-D): draws
+    from the workload's initial-state distribution, each with a random start
+    s uniform on 0..T_max-1 steps into the episode, i.e. a remaining horizon
+    T = T_max - s.  Returns (x [Bc][n], T [Bc] int32, T_max)."""
     kind, params, _, T_max, _ = workload(name, B=1)
     if kind == SYS_POINT_MASS:
         x = point_mass_x0(Bc, seed)
@@ -211,7 +211,7 @@ def bic_candidates(name: str, Bc: int, seed: int = 3001):
         raise ValueError("candidates are drawn for the point mass and the arm")
     rng = np.random.default_rng(seed + 1)
     steps = rng.integers(0, T_max, Bc)
-    return x, steps / T_max, (T_max - steps).astype(np.int32)
+    return x, (T_max - steps).astype(np.int32), T_max
 
 
 # ---------------------------------------------------------------- workloads

@@ -65,14 +65,18 @@ def test_mlp_forward_all_shapes(ctx):
 def test_bic_select(ctx, Bc, N):
     import torch
     from paper_2602_19699_amd import cbic
-    x, tau, _ = I.bic_candidates("pm16k", Bc, seed=17)
+    x, T, T_max = I.bic_candidates("pm16k", Bc, seed=17)
     g, o = _nets(5, 64, 3, 1, seed=5, act=0, out_act=2)
-    sg, sel = cbic.bic_select(ctx, g, torch.as_tensor(x, device="cuda"), torch.as_tensor(tau, device="cuda"), N)
+    sg, sel, xs, Ts = cbic.bic_select(ctx, g, torch.as_tensor(x, device="cuda"), torch.as_tensor(T, device="cuda"),
+                                      T_max, N, gather=True)
     sg, sel = sg.cpu().numpy(), sel.cpu().numpy().astype(np.int64)
-    so, _ = orc.bic_select(o, x, tau, N)
+    so, _ = orc.bic_select(o, x, T, T_max, N)
     assert np.all(np.abs(sg - so) <= TOL * (1 + np.abs(so)))
     # the integer decision, taken on the kernel's FP32 scores, is the oracle's rule
     np.testing.assert_array_equal(sel, orc.top_n(sg.astype(np.float64), N))
+    # the gathered batch is the selected candidates' rows
+    np.testing.assert_array_equal(xs.cpu().numpy(), x[sel])
+    np.testing.assert_array_equal(Ts.cpu().numpy(), T[sel])
     # and valid against the FP64 scores up to the score tolerance
     if 0 < N < Bc:
         rest = np.setdiff1d(np.arange(Bc), sel)
@@ -82,13 +86,14 @@ def test_bic_select(ctx, Bc, N):
 def test_bic_select_ties_nan_and_state_only(ctx):
     import torch
     from paper_2602_19699_amd import cbic
-    x, tau, _ = I.bic_candidates("pm16k", 3000, seed=23)
+    x, T, T_max = I.bic_candidates("pm16k", 3000, seed=23)
     x[1000:2000] = x[:1000]  # duplicated candidates: exactly tied scores
-    tau[1000:2000] = tau[:1000]
+    T[1000:2000] = T[:1000]
     x[[2500, 2600, 2700]] = np.nan  # NaN scores rank lowest
     g, o = _nets(5, 32, 2, 1, seed=9, act=1, out_act=2)
     for N in (10, 1500, 2997, 2998, 3000):
-        sg, sel = cbic.bic_select(ctx, g, torch.as_tensor(x, device="cuda"), torch.as_tensor(tau, device="cuda"), N)
+        sg, sel = cbic.bic_select(ctx, g, torch.as_tensor(x, device="cuda"), torch.as_tensor(T, device="cuda"),
+                                  T_max, N)
         sg, sel = sg.cpu().numpy(), sel.cpu().numpy().astype(np.int64)
         assert np.array_equal(sg[:1000], sg[1000:2000])
         np.testing.assert_array_equal(sel, orc.top_n(sg.astype(np.float64), N))
@@ -97,8 +102,8 @@ def test_bic_select_ties_nan_and_state_only(ctx):
     # a network of the state alone (no time input)
     g2, o2 = _nets(4, 64, 1, 1, seed=3, out_act=2)
     xs = x[2000:2400]
-    sg, sel = cbic.bic_select(ctx, g2, torch.as_tensor(xs, device="cuda"), None, 50)
-    so, _ = orc.bic_select(o2, xs, None, 50)
+    sg, sel = cbic.bic_select(ctx, g2, torch.as_tensor(xs, device="cuda"), None, T_max, 50)
+    so, _ = orc.bic_select(o2, xs, None, T_max, 50)
     assert np.all(np.abs(sg.cpu().numpy() - so) <= TOL * (1 + np.abs(so)))
     np.testing.assert_array_equal(sel.cpu().numpy(), orc.top_n(sg.cpu().numpy().astype(np.float64), 50))
 
@@ -148,20 +153,33 @@ def test_actor_rollout(ctx, kind):
     sys_.close()
 
 
-def test_actor_warm_start_feeds_the_solver(ctx):
+def test_bic_pipeline_feeds_the_solver(ctx):
+    # select 64 of 640 candidates, roll the actor out from them, solve from that
+    # warm start; against the oracle's own pipeline on the candidates both pick
     import torch
     from paper_2602_19699_amd import cbic
-    kind, p, x0, T_max, _ = I.workload("pm64")
-    sys_ = cbic.System(ctx, kind, p)
+    kind, p, _, _, _ = I.workload("pm64")
+    x, T, T_max = I.bic_candidates("pm16k", 640, seed=41)
+    std, std_o = _nets(5, 64, 2, 1, seed=76, act=0, out_act=2)
     g, o = _nets(5, 64, 2, 2, seed=77, act=0, out_act=1, scale=10.0)
-    U0 = cbic.actor_rollout(ctx, sys_, g, torch.as_tensor(x0, device="cuda"), T_max).cpu().numpy()
+    sys_ = cbic.System(ctx, kind, p)
+    _, sel, xs, Ts = cbic.bic_select(ctx, std, torch.as_tensor(x, device="cuda"), torch.as_tensor(T, device="cuda"),
+                                     T_max, 64, gather=True)
+    U0 = cbic.actor_rollout(ctx, sys_, g, xs, T_max, T=Ts)
+    gs = gpu_solve(ctx, kind, p, xs.cpu().numpy(), T_max, T=Ts.cpu().numpy(), U0=U0.cpu().numpy(), max_iter=200,
+                   stop_mode=1, rtol=1e-12)
     sys_.close()
-    Uo, _ = orc.actor_rollout(kind, p, o, x0, T_max)
-    # the solve from the kernel's warm start against the oracle's solve from its own warm start
-    gs = gpu_solve(ctx, kind, p, x0, T_max, U0=U0, max_iter=200, stop_mode=1, rtol=1e-12)
-    r = orc.solve_batch(kind, p, x0, T_max, U0=Uo, opts=oracle_opts(max_iter=200, stop_mode=1, rtol=1e-12))
-    e = rel(gs["J"], r.J)
-    print(f"actor-warm-started solves: median rel cost {np.median(e):.2e}, max {e.max():.2e}")
+    _, sel_o = orc.bic_select(std_o, x, T, T_max, 64)
+    Uo, _ = orc.actor_rollout(kind, p, o, x[sel_o], T_max, T=T[sel_o])
+    r = orc.solve_batch(kind, p, x[sel_o], T_max, T=T[sel_o], U0=Uo,
+                        opts=oracle_opts(max_iter=200, stop_mode=1, rtol=1e-12))
+    sel = sel.cpu().numpy()
+    both = np.intersect1d(sel, sel_o)
+    assert len(both) >= 60
+    ig = np.searchsorted(sel, both)
+    io = np.searchsorted(sel_o, both)
+    e = rel(gs["J"][ig], r.J[io])
+    print(f"BIC pipeline: {len(both)} common candidates, median rel cost {np.median(e):.2e}, max {e.max():.2e}")
     assert (e <= 1e-6).mean() >= 0.9
 
 
@@ -190,6 +208,6 @@ def test_network_errors(ctx):
     assert g.param_count() == I.mlp_param_count(5, 32, 1, 2)
     with pytest.raises(cbic.CbicError) as e:  # N > Bc
         cbic.bic_select(ctx, _nets(5, 32, 1, 1, seed=2)[0], torch.zeros((10, 4), device="cuda"),
-                        torch.zeros(10, device="cuda"), 11)
+                        torch.ones(10, dtype=torch.int32, device="cuda"), 100, 11)
     assert e.value.code == cbic.E_INVALID
     sp.close()

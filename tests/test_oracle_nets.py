@@ -98,14 +98,17 @@ def test_top_n_definition(orc):
 
 
 def test_bic_select_takes_the_most_uncertain(orc):
-    x, tau, T = I.bic_candidates("pm16k", 1000, seed=11)
+    x, T, T_max = I.bic_candidates("pm16k", 1000, seed=11)
+    assert T_max == 100 and T.min() >= 1 and T.max() <= 100
     params = I.mlp_params(5, 32, 2, 1, seed=8)
     nt = net(orc, 5, 32, 2, 1, params, act=0, out_act=2)
-    sc, sel = orc.bic_select(nt, x, tau, 100)
+    sc, sel = orc.bic_select(nt, x, T, T_max, 100)
     assert np.all(sc > 0) and len(sel) == 100 and np.all(np.diff(sel) > 0)
     rest = np.setdiff1d(np.arange(1000), sel)
     assert sc[sel].min() >= sc[rest].max()
-    assert np.all(T == np.round(100 * (1 - tau)).astype(int))
+    # the time input of candidate i is (T_max - T_i) / T_max
+    ref = orc.mlp_forward(nt, np.concatenate([x, ((100 - T) / 100.0)[:, None]], axis=1))[:, 0]
+    np.testing.assert_array_equal(sc, ref)
 
 
 def test_constant_actor_rolls_out_constant_controls(orc):
