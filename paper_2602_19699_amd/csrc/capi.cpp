@@ -1,5 +1,6 @@
 // extern "C" entry points of include/cbic.h: argument validation, context and
 // system objects, workspace management and the batched solve.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -112,6 +113,28 @@ cbic_status ensure_ws(cbic_context* ctx, size_t need) {
 
 }  // namespace
 
+cbic_status context_aux(cbic_context* ctx, size_t need, void** p) {
+  if (need > ctx->aux_bytes) {
+    if (ctx->aux) {
+      HIP_TRY(hipDeviceSynchronize());
+      HIP_TRY(hipFree(ctx->aux));
+      ctx->aux = nullptr;
+      ctx->aux_bytes = 0;
+    }
+    const size_t bytes = std::max<size_t>(need, 64 << 10);
+    hipError_t e = hipMalloc(&ctx->aux, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->aux = nullptr;
+      set_error("hipMalloc of %zu scratch bytes failed: %s", bytes, hipGetErrorString(e));
+      return CBIC_E_OOM;
+    }
+    ctx->aux_bytes = bytes;
+  }
+  *p = ctx->aux;
+  return CBIC_OK;
+}
+
 extern "C" {
 
 const char* cbic_last_error(void) { return last_error(); }
@@ -176,6 +199,7 @@ cbic_status cbic_context_destroy(cbic_context* ctx) {
     if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
   }
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
   if (ctx->done_ev) (void)hipEventDestroy(ctx->done_ev);
   for (int i = 0; i < 4; ++i)
     if (ctx->phase_ev[i]) (void)hipEventDestroy(ctx->phase_ev[i]);

@@ -109,7 +109,16 @@ struct cbic_context {
   std::map<std::string, GraphEntry> graphs;
   // autotuned lanes per instance, keyed by problem class (see autotune.cpp)
   std::map<std::string, int> tuned;
+  // small device scratch of the calls beside the solver (the selection of
+  // biased initial states), grown on demand
+  void* aux = nullptr;
+  size_t aux_bytes = 0;
 };
+
+// At least `need` bytes of the context's auxiliary device scratch in *p
+// (allocated or grown here; the caller holds ctx->mu and orders its stream
+// after the context's previous call).
+cbic_status context_aux(cbic_context* ctx, size_t need, void** p);
 
 struct cbic_system {
   int kind = -1;
