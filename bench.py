@@ -5,9 +5,12 @@ Headline workload (one "step"): one batched solve of the 2-D point-mass OCP with
 through the C ABI, inputs already resident in device memory.  Forms timed:
 plain FP64 with the fixed 50-iteration budget, plain FP64 with the
 relative-decrease stop, and the mixed FP32/FP64 form with the
-relative-decrease stop.  A solve counts as converged when its cost is within
-1e-4 relative of the plain FP64 fixed-budget GPU solve of the same instance;
-`value` is the converged solves per second of the fastest form.
+relative-decrease stop at 1e-7 (its rounding floor) and at 1e-4 (the accuracy
+the metric asks for: iLQR converges quadratically, so a step that lowers J by
+less than 1e-4 leaves a gap far below it).  A solve counts as converged when
+its cost is within 1e-4 relative of the plain FP64 fixed-budget GPU solve of
+the same instance; `value` is the converged solves per second of the fastest
+form (instances outside the bar do not count).
 
 The same run measures the other workloads (64 point-mass instances for
 latency, 4096 arm instances with horizons 50..200, 1024 quadruped-sized
@@ -47,16 +50,16 @@ FETCH_SCALE = 524288.0 / 262159.0
 WRITE_SCALE = 524288.0 / 524288.0
 LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp")
 COUNTERS = {
-    ("pm16k", "mixed_tol1e-7", "lane_iterate<PointMass,float,8,false>"): {
+    ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
         "sha256": "ab28d1c75ed8950c8a58a3c8a2599023719c1dd3775e3013c60acfeef4d74da3",
-        "fetch_kib": 694613.6, "write_kib": 501618.3,
+        "fetch_kib": 460940.1, "write_kib": 361476.8,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
         "sha256": "568ab529b4a2f5a541579e6d693d546efc4a648964a09bc4cd6b193a6eecd10d",
-        "fetch_kib": 6180497.5, "write_kib": 16474956.7,
+        "fetch_kib": 6181044.1, "write_kib": 16487472.8,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
@@ -381,15 +384,18 @@ def main():
     forms = {
         "pm16k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                   "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+                  "mixed_tol1e-4": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-4),
                   "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM),
                   "mixed_tol1e-7_umax10": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=10.0)},
-        "pm64": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+        "pm64": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+                 "mixed_tol1e-4": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-4)},
         "arm4k": {"fp64_fixed50": F(max_iter=50), "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
                   "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                   "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM),
                   "mixed_tol1e-7_umax8": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=8.0)},
         "quad1k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
-                   "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7)},
+                   "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
+                   "mixed_tol1e-4": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-4)},
     }
     cpu_cfg = {"pm16k": (16384, "fp64_fixed50"), "pm64": (64, "fp64_fixed50"), "arm4k": (512, "fp64_fixed50"),
                "quad1k": (64, "fp64_tol1e-10")}
