@@ -721,15 +721,22 @@ struct FinalOut {
   int32_t* work;  // [B][2] or null
 };
 
-template <class Sys, class R>
+// GL lanes per instance (one group of a wave): the lanes split the output
+// copies and the stage costs by step; the costate recursion runs in every
+// lane of the group (a serial chain; lane 0 writes it), and lane 0 forms the
+// cost-to-go sums from the stage costs the group wrote, after a wave barrier.
+template <class Sys, class R, int GL>
 __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                  const int32_t* __restrict__ slots, int Tmax, int max_iter,
                                                  int lookahead, FinalOut o) {
   using LN = Lane<Sys, R>;
   constexpr int N = Sys::N, M = Sys::M;
+  static_assert(GL >= 1 && GL <= 64 && (GL & (GL - 1)) == 0, "group width");
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nslots) return;
-  const int s = slots ? slots[tid] : tid;
+  const int gi = tid / GL, r = tid & (GL - 1);
+  if (gi >= nslots) return;  // whole groups leave together
+  const int s = slots ? slots[gi] : gi;
+  const bool lead = r == 0;
   const typename LN::Model mdl{prm};
   const int b = w.inst[s];
   const int buf = w.cur[s];
@@ -739,24 +746,38 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
   const int T = (st & ST_BAD_INPUT) ? -1 : w.T[s];
   const double J = w.J[s];
   const int iters = w.iters[s];
-  o.J[b] = J;
-  o.iters[b] = iters;
-  o.status[b] = st;
-  if (o.work)
+  if (lead) {
+    o.J[b] = J;
+    o.iters[b] = iters;
+    o.status[b] = st;
+    if (o.work)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) o.work[4 * b + i] = w.work[4 * s + i];
+      for (int i = 0; i < 4; ++i) o.work[4 * b + i] = w.work[4 * s + i];
+  }
   if (o.trace)
-    for (int i = iters + 1; i <= max_iter; ++i) o.trace[size_t(b) * (max_iter + 1) + i] = J;
+    for (int i = iters + 1 + r; i <= max_iter; i += GL) o.trace[size_t(b) * (max_iter + 1) + i] = J;
+  // copies, step k by lane k % GL
   double* Xo = o.X + size_t(b) * (Tmax + 1) * N;
   double* Uo = o.U + size_t(b) * Tmax * M;
-  for (int k = 0; k <= Tmax; ++k) {
+  const int K = lookahead <= 0 ? T : lookahead;
+  double* xo = o.xK ? o.xK + size_t(b) * (Tmax + 1) * N : nullptr;
+  for (int k = r; k <= Tmax; k += GL) {
     if (k <= T) {
       const R* xs = LN::xp(w, buf, k, s);
 #pragma unroll
       for (int i = 0; i < N; ++i) Xo[k * N + i] = double(xs[i]);
+      if (xo) {
+        const int t = k + K < T ? k + K : T;
+        const R* xk = LN::xp(w, buf, t, s);
+#pragma unroll
+        for (int i = 0; i < N; ++i) xo[k * N + i] = double(xk[i]);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < N; ++i) Xo[k * N + i] = 0.0;
+      if (xo)
+#pragma unroll
+        for (int i = 0; i < N; ++i) xo[k * N + i] = 0.0;
     }
     if (k < Tmax) {
       if (k < T) {
@@ -769,35 +790,26 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       }
     }
   }
-  const int K = lookahead <= 0 ? T : lookahead;
-  if (o.xK) {
-    double* xo = o.xK + size_t(b) * (Tmax + 1) * N;
-    for (int k = 0; k <= Tmax; ++k) {
-      if (k <= T) {
-        const int t = k + K < T ? k + K : T;
-        const R* xs = LN::xp(w, buf, t, s);
-#pragma unroll
-        for (int i = 0; i < N; ++i) xo[k * N + i] = double(xs[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i) xo[k * N + i] = 0.0;
-      }
-    }
-  }
-  if (T < 0) {
-    if (o.Vbar)
-      for (int k = 0; k <= Tmax; ++k) o.Vbar[size_t(b) * (Tmax + 1) + k] = 0.0;
-    if (o.Vx)
-      for (int k = 0; k <= Tmax; ++k)
-#pragma unroll
-        for (int i = 0; i < N; ++i) o.Vx[(size_t(b) * (Tmax + 1) + k) * N + i] = 0.0;
-    return;
-  }
-  if (!o.Vbar && !o.Vx) return;
-  // backward pass over the final trajectory: stage costs and costate
-  // lambda_T = d l_T/dx, lambda_k = l_x + A_k^T lambda_{k+1}  (unclipped first derivatives)
   double* Vo = o.Vbar ? o.Vbar + size_t(b) * (Tmax + 1) : nullptr;
   double* Lo = o.Vx ? o.Vx + size_t(b) * (Tmax + 1) * N : nullptr;
+  // zero past the horizon (everything for an invalid one)
+  for (int k = (T < 0 ? 0 : T + 1) + r; k <= Tmax; k += GL) {
+    if (Vo) Vo[k] = 0.0;
+    if (Lo)
+#pragma unroll
+      for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = 0.0;
+  }
+  if (T < 0 || (!Vo && !Lo)) return;
+  // stage costs c_k (k < T), turned into cost-to-go sums below
+  if (Vo)
+    for (int k = r; k < T; k += GL) {
+      R x[N], u[M];
+      LN::ld(x, LN::xp(w, buf, k, s));
+      LN::ld(u, LN::up(w, buf, k, s));
+      Vo[k] = double(mdl.cost(x, u));
+    }
+  // costate lambda_T = d l_T/dx, lambda_k = l_x + A_k^T lambda_{k+1}
+  // (unclipped first derivatives)
   R lam[N];
   R xT[N];
   LN::ld(xT, LN::xp(w, buf, T, s));
@@ -806,19 +818,14 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
     mdl.term_derivs(xT, lam, Qd, R(0), false);
   }
   const double cT = double(mdl.term(xT));
-  if (Vo) Vo[T] = cT;
   if (Lo) {
+    if (lead)
 #pragma unroll
-    for (int i = 0; i < N; ++i) Lo[size_t(T) * N + i] = double(lam[i]);
-  }
-  for (int k = T - 1; k >= 0; --k) {
-    R x[N], u[M];
-    LN::ld(x, LN::xp(w, buf, k, s));
-    LN::ld(u, LN::up(w, buf, k, s));
-    if (Vo) {
-      Vo[k] = double(mdl.cost(x, u));  // stage cost, turned into window sums below
-    }
-    if (Lo) {
+      for (int i = 0; i < N; ++i) Lo[size_t(T) * N + i] = double(lam[i]);
+    for (int k = T - 1; k >= 0; --k) {
+      R x[N], u[M];
+      LN::ld(x, LN::xp(w, buf, k, s));
+      LN::ld(u, LN::up(w, buf, k, s));
       R A[N][N], B[N][M], lx[N], lu[M], Qd[N][N], Rd[M][M];
       mdl.jac(x, u, A, B);
       mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
@@ -832,36 +839,41 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
         ln[i] = v;
       }
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        lam[i] = ln[i];
-        Lo[size_t(k) * N + i] = double(ln[i]);
-      }
+      for (int i = 0; i < N; ++i) lam[i] = ln[i];
+      if (lead)
+#pragma unroll
+        for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = double(ln[i]);
     }
   }
   if (Vo) {
-    if (K >= T) {
-      // full cost-to-go: suffix sums
-      double acc = cT;
-      for (int k = T - 1; k >= 0; --k) {
-        acc = Vo[k] + acc;
-        Vo[k] = acc;
-      }
-    } else {
-      // K-step window: V_k = sum_{j=k}^{min(k+K,T)-1} c_j + [k+K >= T] c_T, in index order
-      for (int k = 0; k < T; ++k) {
-        const int end = k + K < T ? k + K : T;
-        double v = 0.0;
-        for (int j = k; j < end; ++j) v += Vo[j];
-        if (k + K >= T) v += cT;
-        Vo[k] = v;  // reads only indices >= k, which still hold stage costs
+    // the group's stage costs are in Vo (global memory): complete the stores
+    // and order them before lane 0's loads (workgroup-scope fences around a
+    // wave barrier)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (lead) {
+      if (K >= T) {
+        // full cost-to-go: suffix sums
+        double acc = cT;
+        Vo[T] = cT;
+        for (int k = T - 1; k >= 0; --k) {
+          acc = Vo[k] + acc;
+          Vo[k] = acc;
+        }
+      } else {
+        // K-step window: V_k = sum_{j=k}^{min(k+K,T)-1} c_j + [k+K >= T] c_T, in index order
+        Vo[T] = cT;
+        for (int k = 0; k < T; ++k) {
+          const int end = k + K < T ? k + K : T;
+          double v = 0.0;
+          for (int j = k; j < end; ++j) v += Vo[j];
+          if (k + K >= T) v += cT;
+          Vo[k] = v;  // reads only indices >= k, which still hold stage costs
+        }
       }
     }
-    for (int k = T + 1; k <= Tmax; ++k) Vo[k] = 0.0;
   }
-  if (Lo)
-    for (int k = T + 1; k <= Tmax; ++k)
-#pragma unroll
-      for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = 0.0;
 }
 
 }  // namespace cbic

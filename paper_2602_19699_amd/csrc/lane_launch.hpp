@@ -108,7 +108,10 @@ struct LaneLaunch {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
-    hipLaunchKernelGGL((lane_final<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
+    // eight lanes per instance share the output copies and the stage costs
+    constexpr int FG = 8;
+    const long total = long(nthreads) * FG;
+    hipLaunchKernelGGL((lane_final<Sys, R, FG>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
                        slots, Tmax, max_iter, lookahead, fo);
     return hipGetLastError();
   }
