@@ -722,8 +722,9 @@ struct FinalOut {
 };
 
 // GL lanes per instance (one group of a wave): the lanes split the output
-// copies and the stage costs by step; the costate recursion runs in every
-// lane of the group (a serial chain; lane 0 writes it), and lane 0 forms the
+// copies and the stage costs by step; the costate recursion walks back over
+// the final trajectory in every lane of the group, fed chunk by chunk by the
+// group's lanes (a serial chain; lane 0 writes it), and lane 0 forms the
 // cost-to-go sums from the stage costs the group wrote, after a wave barrier.
 template <class Sys, class R, int GL>
 __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
@@ -822,27 +823,50 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
     if (lead)
 #pragma unroll
       for (int i = 0; i < N; ++i) Lo[size_t(T) * N + i] = double(lam[i]);
-    for (int k = T - 1; k >= 0; --k) {
-      R x[N], u[M];
-      LN::ld(x, LN::xp(w, buf, k, s));
-      LN::ld(u, LN::up(w, buf, k, s));
-      R A[N][N], B[N][M], lx[N], lu[M], Qd[N][N], Rd[M][M];
-      mdl.jac(x, u, A, B);
-      mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
-      R ln[N];
+    // the chain walks back in chunks of GL steps: lane q of the group loads
+    // step kc - q (the next chunk is loaded while this one runs) and the chain
+    // takes each step's (x, u) from its lane by a wave shuffle
+    const int gbase = (threadIdx.x & 63) & ~(GL - 1);
+    R xq[N] = {}, uq[M] = {}, xn[N] = {}, un[M] = {};
+    if (T - 1 - r >= 0) {
+      LN::ld(xq, LN::xp(w, buf, T - 1 - r, s));
+      LN::ld(uq, LN::up(w, buf, T - 1 - r, s));
+    }
+    for (int kc = T - 1; kc >= 0; kc -= GL) {
+      if (kc - GL - r >= 0) {
+        LN::ld(xn, LN::xp(w, buf, kc - GL - r, s));
+        LN::ld(un, LN::up(w, buf, kc - GL - r, s));
+      }
+      const int qn = kc + 1 < GL ? kc + 1 : GL;
+      for (int q = 0; q < qn; ++q) {
+        const int k = kc - q;
+        R x[N], u[M];
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        R v = lx[i];
+        for (int i = 0; i < N; ++i) x[i] = __shfl(xq[i], gbase + q, 64);
 #pragma unroll
-        for (int t = 0; t < N; ++t)
-          if (Sys::a_nz(t, i)) v += A[t][i] * lam[t];
-        ln[i] = v;
+        for (int i = 0; i < M; ++i) u[i] = __shfl(uq[i], gbase + q, 64);
+        R A[N][N], B[N][M], lx[N], lu[M], Qd[N][N], Rd[M][M];
+        mdl.jac(x, u, A, B);
+        mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
+        R ln[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R v = lx[i];
+#pragma unroll
+          for (int t = 0; t < N; ++t)
+            if (Sys::a_nz(t, i)) v += A[t][i] * lam[t];
+          ln[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) lam[i] = ln[i];
+        if (lead)
+#pragma unroll
+          for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = double(ln[i]);
       }
 #pragma unroll
-      for (int i = 0; i < N; ++i) lam[i] = ln[i];
-      if (lead)
+      for (int i = 0; i < N; ++i) xq[i] = xn[i];
 #pragma unroll
-        for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = double(ln[i]);
+      for (int i = 0; i < M; ++i) uq[i] = un[i];
     }
   }
   if (Vo) {
@@ -854,10 +878,22 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (lead) {
       if (K >= T) {
-        // full cost-to-go: suffix sums
+        // full cost-to-go: suffix sums, the stage costs loaded eight at a
+        // time ahead of their updates (same summation order)
         double acc = cT;
         Vo[T] = cT;
-        for (int k = T - 1; k >= 0; --k) {
+        int k = T - 1;
+        for (; k >= 7; k -= 8) {
+          double c[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) c[j] = Vo[k - j];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            acc = c[j] + acc;
+            Vo[k - j] = acc;
+          }
+        }
+        for (; k >= 0; --k) {
           acc = Vo[k] + acc;
           Vo[k] = acc;
         }
