@@ -161,10 +161,10 @@ struct Lane {
         Qux[i][j] = q;
       }
     }
-    // Cholesky of Q_uu (+ mu I in the Levenberg-Marquardt variant) and the
-    // gains, in FP64 (one Newton step on the reciprocal pivots when the gains
-    // are rounded to FP32); the checks are on the gains as stored, so an FP32
-    // overflow is caught as well
+    // Cholesky of Q_uu (+ mu I in the Levenberg-Marquardt variant) in FP64
+    // (one Newton step on the reciprocal pivots when the gains are FP32) and
+    // the gains; the checks are on the gains as stored, so an FP32 overflow is
+    // caught as well
     if (mu != 0.0)
 #pragma unroll
       for (int i = 0; i < M; ++i) Quu[i][i] += mu;
@@ -173,7 +173,67 @@ struct Lane {
     if (!chol_fp64<M, NR>(Quu, Lc, invd)) return ST_CHOL_FAIL;
     R Kk[M][N], kk[M];
     bool fin = true;
-    {
+    bool solved = false;
+    if constexpr (sizeof(R) == 4) {
+      // mixed form: the gains are stored in FP32, so their triangular solves
+      // run in FP32 on the FP64 factor rounded to FP32 (a few ulps, as the
+      // rounding of FP64 solves to FP32 would give).  With a bound, this
+      // unconstrained step stands when it lies in the box (so a bound that
+      // does not bind changes nothing); otherwise the FP64 box QP below runs
+      float lf[M][M], ivf[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        ivf[i] = float(invd[i]);
+#pragma unroll
+        for (int j = 0; j < M; ++j) lf[i][j] = float(Lc[i][j]);
+      }
+      auto solve = [&](float (&b)[M]) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = 0; k2 < i; ++k2) v -= lf[i][k2] * b[k2];
+          b[i] = v * ivf[i];
+        }
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = i + 1; k2 < M; ++k2) v += lf[k2][i] * b[k2];
+          b[i] = v * -ivf[i];
+        }
+      };
+      float col[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) col[i] = Qu[i];
+      solve(col);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        kk[i] = col[i];
+        fin = fin && dfinite(kk[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) col[i] = Qux[i][j];
+        solve(col);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          Kk[i][j] = col[i];
+          fin = fin && dfinite(Kk[i][j]);
+        }
+      }
+      solved = true;
+      if constexpr (BOX) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const double d = double(kk[i]);
+          solved = solved && d >= -umax - double(u[i]) && d <= umax - double(u[i]);
+        }
+        if (!solved) fin = true;
+      }
+    }
+    if (!solved) {
       double col[M];
 #pragma unroll
       for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
