@@ -322,85 +322,6 @@ __device__ __forceinline__ void wave_jac(const Smem<R>& sm, const WaveScratch<R>
   }
 }
 
-// ------------------------------------------------------------------ Jacobians
-// f_x into sm.A and f_u into sm.Bm at (wv[0].x, wv[0].u); wave 0 must have run
-// wave_dyn on that point (L, a, sin/cos, W2 cos q in wv[0]).  All threads.
-template <class R>
-__device__ __forceinline__ void jacobians(Smem<R>& sm, R dt, int tid) {
-  const WaveScratch<R>& ws = sm.wv[0];
-  R* Z = &sm.PA[0][0];  // 18 x 48 right-hand sides, row stride 48
-  // RHS columns: 0..17 -dD/dq (a and v held), 18..35 -dD/dv, 36..47 S
-#pragma unroll 1
-  for (int idx = tid; idx < NV * 48; idx += NT) {
-    const int i = idx / 48, col = idx % 48;
-    R v;
-    if (col < NV) {
-      const int j = col;
-      v = -(sm.W1[i][j] * ws.c[j] - ws.x[NQ + i] * sm.W2[i][j] * ws.s[j]);
-      if (i == j) v -= R(0.1) * ws.c[i] * ws.a[i];
-    } else if (col < 2 * NV) {
-      v = (col - NV == i) ? -ws.w2c[i] : R(0);
-    } else {
-      v = (col - 2 * NV + 6 == i) ? R(1) : R(0);
-    }
-    Z[i * 48 + col] = v;
-  }
-  __syncthreads();
-  if (tid < 48) {  // column solves with L L^T; the column lives in registers
-    R y[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) y[i] = Z[i * 48 + tid];
-    // two partial sums per row halve the dependent chain
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      R v0 = y[i], v1 = R(0);
-#pragma unroll
-      for (int k = 0; k < i; ++k) {
-        if (k & 1) v1 += ws.L[i][k] * y[k];
-        else v0 -= ws.L[i][k] * y[k];
-      }
-      y[i] = (v0 - v1) * ws.Li[i];
-    }
-#pragma unroll
-    for (int i = NV - 1; i >= 0; --i) {
-      R v0 = y[i], v1 = R(0);
-#pragma unroll
-      for (int k = i + 1; k < NV; ++k) {
-        if (k & 1) v1 += ws.L[k][i] * y[k];
-        else v0 -= ws.L[k][i] * y[k];
-      }
-      y[i] = (v0 - v1) * ws.Li[i];
-    }
-#pragma unroll
-    for (int i = 0; i < NV; ++i) Z[i * 48 + tid] = y[i];
-  }
-  __syncthreads();
-  // d v+/d x and d v+/d u, then q rows: q+ = q + dt E v+
-#pragma unroll 1
-  for (int idx = tid; idx < N * (N + M); idx += NT) {
-    const int r = idx / (N + M), col = idx % (N + M);
-    auto dv = [&](int i) -> R {  // d v+_i / d (x, u)_col
-      if (col < NV) return dt * Z[i * 48 + col];
-      if (col == NV) return R(0);
-      if (col < N) return ((col - NQ) == i ? R(1) : R(0)) + dt * Z[i * 48 + NV + (col - NQ)];
-      return dt * Z[i * 48 + 2 * NV + (col - N)];
-    };
-    R v;
-    const R id = (col < N && col == r) ? R(1) : R(0);
-    if (r >= NQ) v = dv(r - NQ);
-    else if (r < NV) v = id + dt * dv(r);
-    else {
-      R s = R(0);
-#pragma unroll 2
-      for (int i = 0; i < NV; ++i) s += sm.e[i] * dv(i);
-      v = id + dt * s;
-    }
-    if (col < N) sm.A[r][col] = v;
-    else sm.Bm[r][col - N] = v;
-  }
-  __syncthreads();
-}
-
 // ------------------------------------------------------------------ FP64 Cholesky of Q_uu and the gains
 // Wave 0 factors Quu (rows on lanes); threads 0..37 solve for [K k].
 template <class R>
@@ -827,7 +748,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
 template <class R>
 __global__ void __launch_bounds__(NT, 2) quad_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                   const int32_t* __restrict__ slots, int Tmax, int max_iter,
-                                                  int lookahead, FinalOut o) {
+                                                  int lookahead, FinalOut o, R* __restrict__ dblk) {
   using Q = QW<R>;
   __shared__ Smem<R> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
@@ -895,30 +816,46 @@ __global__ void __launch_bounds__(NT, 2) quad_final(const double* __restrict__ p
     if (tid == 0) Vo[T] = cT;
   }
   __syncthreads();
+  // costate lambda_k = l_x + f_x^T lambda_{k+1}: the Jacobian blocks of the
+  // next CH steps are evaluated first, wave wid taking every fourth step
+  // (as in the backward sweep), then each step is a matrix-vector product
+  const int wid = tid >> 6, lane = tid & 63;
+  R* blk = dblk + size_t(s) * CH * DB;
   for (int k = T - 1; k >= 0; --k) {
+    const int q = (T - 1 - k) % CH;
+    if (Lo && q == 0) {
+      WaveScratch<R>& wsw = sm.wv[wid];
+      for (int qq = wid; qq < CH && k - qq >= 0; qq += NW) {
+        if (lane < N) wsw.x[lane] = Q::xp(w, buf, k - qq, s)[lane];
+        if (lane < M) wsw.u[lane] = Q::up(w, buf, k - qq, s)[lane];
+        wave_sync();
+        wave_dyn(sm, wsw, dt, lane);
+        wave_jac(sm, wsw, dt, lane, blk + qq * DB);
+        wave_sync();
+      }
+      __syncthreads();
+    }
     if (tid < N) w0.x[tid] = Q::xp(w, buf, k, s)[tid];
     if (tid < M) w0.u[tid] = Q::up(w, buf, k, s)[tid];
     __syncthreads();
-    if (tid < 64) {
+    if (Vo && tid < 64) {
       const double c = double(wave_cost(sm, w0.x, w0.u, prm, tid, false));
-      if (Vo && tid == 0) Vo[k] = c;
-      if (Lo) wave_dyn(sm, w0, dt, tid);
+      if (tid == 0) Vo[k] = c;
     }
-    __syncthreads();
     if (Lo) {
-      jacobians(sm, dt, tid);
       R v = R(0);
       if (tid < N) {
+        const R* Ab = blk + q * DB;  // row-major [f_x | f_u], 37 x 49
         v = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
-        for (int t = 0; t < N; ++t) v += sm.A[t][tid] * sm.p[t];
+        for (int t = 0; t < N; ++t) v += Ab[t * (N + M) + tid] * sm.p[t];
       }
       __syncthreads();
       if (tid < N) {
         sm.p[tid] = v;
         Lo[size_t(k) * N + tid] = double(v);
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
   __syncthreads();
   if (Vo && tid == 0) {
@@ -982,7 +919,7 @@ struct QuadLaunch {
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
     hipLaunchKernelGGL(quad_final<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, max_iter,
-                       lookahead, fo);
+                       lookahead, fo, blocks(base, Bcap, Tcap));
     return hipGetLastError();
   }
 
