@@ -52,14 +52,14 @@ LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_laun
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "ab28d1c75ed8950c8a58a3c8a2599023719c1dd3775e3013c60acfeef4d74da3",
-        "fetch_kib": 460940.1, "write_kib": 361476.8,
+        "sha256": "f3b1965e4b6b16aeefc2c5476b2f689bcf955d9991f7a3f60d4d2be65f793af5",
+        "fetch_kib": 461961.6, "write_kib": 361427.3,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "568ab529b4a2f5a541579e6d693d546efc4a648964a09bc4cd6b193a6eecd10d",
-        "fetch_kib": 6181044.1, "write_kib": 16487472.8,
+        "sha256": "96c7a01b55ba06f424ca2fb493e661bad320c48ef0aff1a23e65295a537c9a59",
+        "fetch_kib": 6142654.7, "write_kib": 16461842.5,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
