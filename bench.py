@@ -197,6 +197,16 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
     # problem with the control bound of eq. 1; neither is the headline form
     best = max((k for k in results if not k.endswith("_lm") and "_umax" not in k),
                key=lambda k: results[k]["converged_solves_per_s"])
+    if Tb is not None:
+        # lockstep efficiency of a ragged batch: the horizon sort puts 64 / GL
+        # instances of similar horizon in a wave, and a wave steps as long as
+        # its longest; useful steps / stepped lane-steps for the best form
+        gl = results[best]["lanes_per_instance"] or 1
+        per = max(1, 64 // gl)
+        srt = np.sort(Tb.astype(np.int64))[::-1]
+        stepped = sum(int(srt[i]) * min(per, len(srt) - i) for i in range(0, len(srt), per))
+        for r in results.values():
+            r["lockstep_efficiency"] = float(srt.sum() / stepped)
     for fname in [k for k in results if k.endswith("_lm")]:
         base = fname[:-3]
         if base in results:
@@ -232,6 +242,13 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
                "sample": f"{'all' if ns == B else 'first %d of the' % ns} {B} instances, FP64, "
                          f"{'tolerance stop rtol=%g' % oo.rtol if oo.stop_mode else 'fixed %d iterations' % oo.max_iter}"
                          f", {threads} OpenMP threads, {dt:.2f} s"}
+        # the same oracle on one core, on an eighth of that sample
+        n1 = max(1, ns // 8)
+        t0 = time.perf_counter()
+        orc.solve_batch(kind, params, x0[:n1], T, T=None if Tb is None else Tb[:n1], opts=oo, nthreads=1)
+        d1 = time.perf_counter() - t0
+        cpu["single_core"] = {"value": round(n1 / d1, 2), "unit": "solves/s", "sample": f"first {n1} instances, "
+                              f"{d1:.2f} s"}
     sysm.close()
     return results, best, cpu, calib
 
