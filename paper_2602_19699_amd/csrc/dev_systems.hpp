@@ -25,6 +25,9 @@ struct PointMass {
   // a rollout step costs little next to the stores of GL trial trajectories:
   // the line search writes only alpha = 1 and re-rolls another accepted step
   static constexpr bool kOwnTrialBuffers = false;
+  // two identical double integrators (one per plane axis) coupled only through
+  // the position Hessian of the cost: the backward sweep splits by axis
+  static constexpr bool kAxisPairs = true;
   // structural nonzeros of f_x and f_u (A = [[I, dt I], [0, I]], B = [[dt^2 I], [dt I]])
   __host__ __device__ static constexpr bool a_nz(int i, int j) { return i == j || j == i + 2; }
   __host__ __device__ static constexpr bool b_nz(int i, int j) { return (i & 1) == j; }
@@ -111,6 +114,9 @@ struct PointMass {
 
     // Per-step derivative block for the backward sweep, evaluated ahead of the
     // serial recursion: l_x (2 nonzero), clipped position Hessian (3), l_u (2).
+    // Axis h's own entries are D[h] (position gradient), D[2 + 2h] (its
+    // diagonal Hessian entry) and D[5 + h] (control gradient); D[3] is the
+    // cross-axis Hessian entry.
     static constexpr int ND = 7;
     CBIC_HD __forceinline__ void pack_derivs(const R* x, const R* u, R* D, R eps) const {
       R lx[N], lu[M], Q[N][N], Ru[M][M];
@@ -134,6 +140,12 @@ struct PointMass {
       const R ru = dmax(R(2) * R(p[1]), eps);
       Ru[0][0] = ru; Ru[0][1] = R(0); Ru[1][0] = R(0); Ru[1][1] = ru;
     }
+
+    // constants of the per-axis Riccati step: dt, the clipped control Hessian
+    // (2 w_u) and the clipped velocity Hessian (zero)
+    CBIC_HD __forceinline__ R step_dt() const { return R(p[0]); }
+    CBIC_HD __forceinline__ R ctrl_hess(R eps) const { return dmax(R(2) * R(p[1]), eps); }
+    CBIC_HD __forceinline__ R vel_hess(R eps) const { return dmax(R(0), eps); }
 
     CBIC_HD __forceinline__ void term_derivs(const R* x, R lx[N], R Q[N][N], R eps, bool hess) const {
       const R w2 = R(2) * R(p[3]);
@@ -170,6 +182,7 @@ struct Arm3 {
   // a rollout step is expensive: every trial lane writes its own trajectory
   // so that an accepted step needs no second rollout
   static constexpr bool kOwnTrialBuffers = true;
+  static constexpr bool kAxisPairs = false;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 
@@ -494,6 +507,7 @@ struct LinQuad {
                        NPRM = OQTC + N * N;
   static constexpr bool kNonNegCost = false;
   static constexpr bool kOwnTrialBuffers = false;
+  static constexpr bool kAxisPairs = false;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 

@@ -294,6 +294,259 @@ struct Lane {
     return 0;
   }
 
+  // ------------------------------------------------------------------ backward, axis pairs
+  // For two identical double integrators, one per plane axis, coupled only
+  // through the cross-axis entry of the cost's position Hessian (the point
+  // mass; state (p_0, p_1, v_0, v_1)), A is a = [[1, dt], [0, 1]] and B is
+  // b = (dt^2, dt) on each axis' (position, velocity) pair.  P is then held as
+  // its diagonal blocks P_hh and its cross block, and one Riccati step splits
+  // by axis: lanes 2j and 2j + 1 of a group take axis r & 1 each and swap
+  // (DPP) the few values the other axis needs.  Everything the two lanes hold
+  // in common comes from formulas that are symmetric in the two axes, so the
+  // pair's copies agree bit for bit; the cross block of the update is
+  // sym(Q_xx + Q_ux^T K), the mean of the pair's two products.  A one-lane
+  // group runs both axes with the same formulas, so the result does not depend
+  // on the group width.
+  struct AxisP {
+    R pp, pv, vv;          // diagonal block P_hh: (pos, pos), (pos, vel), (vel, vel)
+    R xpp, xpv, xvp, xvv;  // cross block: rows this axis (pos, vel), columns the other axis
+    R qp, qv;              // p on this axis: (pos, vel)
+  };
+  struct AxisQ {
+    R s, qu, q01;              // b^T P_hh b, Q_u of this axis' control, b^T P_01 b
+    R ga_p, ga_v, gb_p, gb_v;  // Q_ux on this axis' columns: this control's row, the other's
+    R Qpp, Qpv, Qvv;           // Q_xx diagonal block
+    R Xpp, Xpv, Xvp, Xvv;      // Q_xx cross block, this axis' orientation
+    R Qxp, Qxv;                // Q_x
+  };
+
+  // the value held by the other lane of the pair (2j, 2j + 1): DPP quad_perm
+  // [1, 0, 3, 2] (bound_ctrl set: never out of range here, and it lets the
+  // swap fold into the instruction that uses it)
+  __device__ static __forceinline__ float pair_swap(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+  }
+  __device__ static __forceinline__ double pair_swap(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp(int(b), 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), 0xB1, 0xF, 0xF, true);
+    return __longlong_as_double(static_cast<long long>(static_cast<unsigned>(lo)) |
+                                (static_cast<long long>(hi) << 32));
+  }
+
+  // the quantities of one axis that need only that axis' P blocks; lx, hd, hx,
+  // lu: position gradient, diagonal and cross-axis position Hessian entries,
+  // control gradient
+  __device__ static __forceinline__ void axis_q(const AxisP& P, R dt, R dt2, R ev, R lx, R hd, R hx, R lu,
+                                                AxisQ& q) {
+    const R g0 = P.pp * dt2 + P.pv * dt;  // P_hh b
+    const R g1 = P.pv * dt2 + P.vv * dt;
+    q.s = g0 * dt2 + g1 * dt;
+    q.ga_p = g0;
+    q.ga_v = g0 * dt + g1;
+    const R w0 = P.xpp * dt2 + P.xpv * dt;  // (cross block) b
+    const R w1 = P.xvp * dt2 + P.xvv * dt;
+    q.gb_p = w0;
+    q.gb_v = w0 * dt + w1;
+    q.q01 = dt2 * (P.xpp * dt2 + (P.xpv + P.xvp) * dt + P.xvv);
+    q.qu = lu + (P.qp * dt2 + P.qv * dt);
+    q.Qxp = lx + P.qp;
+    q.Qxv = P.qp * dt + P.qv;
+    q.Qpp = hd + P.pp;
+    q.Qpv = P.pp * dt + P.pv;
+    q.Qvv = ev + (q.Qpv * dt + (P.pv * dt + P.vv));
+    q.Xpp = hx + P.xpp;
+    q.Xpv = P.xpp * dt + P.xpv;
+    q.Xvp = P.xpp * dt + P.xvp;
+    q.Xvv = (P.xpp * dt + (P.xpv + P.xvp)) * dt + P.xvv;
+  }
+
+  // One Riccati step at time k on the axis blocks AP (both axes for GL = 1,
+  // axis h otherwise) from the staged derivative block D (model layout: D[h]
+  // position gradient, D[2 + 2h] diagonal and D[3] cross-axis position Hessian
+  // entries, D[5 + h] control gradient).  ev, ru: the clipped velocity and
+  // control Hessians.  Gains, the bounded step (BOX, u the iterate's control)
+  // and the Levenberg-Marquardt shift as in riccati_step; `store` only on the
+  // group's lead lane, which holds axis 0.
+  template <int GL, bool BOX>
+  __device__ static __forceinline__ uint32_t axis_step(const LaneState<R>& w, int s, int k, const R* D,
+                                                       const R (&u)[M], AxisP (&AP)[GL == 1 ? 2 : 1], int h,
+                                                       R dt, R dt2, R ev, R ru, bool store, double mu,
+                                                       double umax) {
+    static_assert(N == 4 && M == 2, "axis pairs: two axes of (position, velocity) and one control each");
+    constexpr int NA = GL == 1 ? 2 : 1;
+    AxisQ q[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int ax = GL == 1 ? a : h;
+      axis_q(AP[a], dt, dt2, ev, D[ax], D[2 + 2 * ax], D[3], D[5 + ax], q[a]);
+    }
+    // Q_uu and Q_u in control order
+    const bool first0 = GL == 1 || h == 0;  // the lane's first axis is axis 0
+    const R so = GL == 1 ? q[NA - 1].s : pair_swap(q[0].s);
+    const R uo = GL == 1 ? q[NA - 1].qu : pair_swap(q[0].qu);
+    const R S0 = first0 ? q[0].s : so, S1 = first0 ? so : q[0].s;
+    const R U0 = first0 ? q[0].qu : uo, U1 = first0 ? uo : q[0].qu;
+    double Quu[M][M];
+    Quu[0][0] = double(ru + S0);
+    Quu[0][1] = double(q[0].q01);
+    Quu[1][0] = Quu[0][1];
+    Quu[1][1] = double(ru + S1);
+    // the Levenberg-Marquardt shift (zero otherwise: adding it changes no bit
+    // of a diagonal that is not -0, and a -0 pivot fails either way)
+    Quu[0][0] += mu;
+    Quu[1][1] += mu;
+    constexpr int NR = sizeof(R) == 4 ? 1 : 2;
+    double Lc[M][M], invd[M];
+    if (!chol_fp64<M, NR>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    // Q_ux on the lane's axes in control order: G[a][c][j], j = 0 position, 1 velocity
+    R G[NA][M][2];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const bool a0 = GL == 1 ? a == 0 : h == 0;
+      G[a][0][0] = a0 ? q[a].ga_p : q[a].gb_p;
+      G[a][1][0] = a0 ? q[a].gb_p : q[a].ga_p;
+      G[a][0][1] = a0 ? q[a].ga_v : q[a].gb_v;
+      G[a][1][1] = a0 ? q[a].gb_v : q[a].ga_v;
+    }
+    R kk[M], Kc[NA][M][2];
+    bool solved = false;
+    if constexpr (sizeof(R) == 4) {
+      // FP32 solves on the FP64 factor rounded to FP32 (as in riccati_step)
+      float lf[M][M], ivf[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        ivf[i] = float(invd[i]);
+#pragma unroll
+        for (int j = 0; j < M; ++j) lf[i][j] = float(Lc[i][j]);
+      }
+      auto solve = [&](float (&b)[M]) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = 0; k2 < i; ++k2) v -= lf[i][k2] * b[k2];
+          b[i] = v * ivf[i];
+        }
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = i + 1; k2 < M; ++k2) v += lf[k2][i] * b[k2];
+          b[i] = v * -ivf[i];
+        }
+      };
+      float col[M] = {U0, U1};
+      solve(col);
+      kk[0] = col[0];
+      kk[1] = col[1];
+      solved = true;
+      if constexpr (BOX) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const double d = double(kk[i]);
+          solved = solved && d >= -umax - double(u[i]) && d <= umax - double(u[i]);
+        }
+      }
+      if (solved) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            float c2[M] = {G[a][0][j], G[a][1][j]};
+            solve(c2);
+            Kc[a][0][j] = c2[0];
+            Kc[a][1][j] = c2[1];
+          }
+      }
+    }
+    if (!solved) {
+      double col[M] = {double(U0), double(U1)};
+      chol_solve_neg_fp64<M>(Lc, invd, col);
+      unsigned held = 0;
+      if constexpr (BOX) {
+        double g[M], lo[M], hi[M];
+        g[0] = double(U0);
+        g[1] = double(U1);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          lo[i] = -umax - double(u[i]);
+          hi[i] = umax - double(u[i]);
+        }
+        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd)) return ST_CHOL_FAIL;
+      }
+      kk[0] = R(col[0]);
+      kk[1] = R(col[1]);
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          double c2[M];
+#pragma unroll
+          for (int i = 0; i < M; ++i) c2[i] = ((held >> i) & 1u) ? 0.0 : double(G[a][i][j]);
+          chol_solve_neg_fp64<M>(Lc, invd, c2);
+          Kc[a][0][j] = R(c2[0]);
+          Kc[a][1][j] = R(c2[1]);
+        }
+    }
+    // the other axis' gain columns
+    R Ko[NA][M][2];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) Ko[a][c][j] = GL == 1 ? Kc[NA - 1 - a][c][j] : pair_swap(Kc[a][c][j]);
+    // all ten checked without branches (the pair checks the same values)
+    bool fin = dfinite(kk[0]) & dfinite(kk[1]);
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fin = fin & dfinite(Kc[0][c][j]) & dfinite(Ko[0][c][j]);
+    if (!fin) return ST_NONFINITE;
+    if (store) {
+      // K row c over (p_0, p_1, v_0, v_1); the lead lane's own axis is axis 0
+      R* dK = Kp(w, k, s);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        dK[c * N + 0] = Kc[0][c][0];
+        dK[c * N + 1] = Ko[0][c][0];
+        dK[c * N + 2] = Kc[0][c][1];
+        dK[c * N + 3] = Ko[0][c][1];
+      }
+      st(kp(w, k, s), kk);
+    }
+    // Q_ux^T K on (this axis, other axis), then the update
+    R S[NA][2][2];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) S[a][i][j] = G[a][0][i] * Ko[a][0][j] + G[a][1][i] * Ko[a][1][j];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      // the other axis' products, transposed into this axis' orientation
+      R Tt[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) Tt[i][j] = GL == 1 ? S[NA - 1 - a][j][i] : pair_swap(S[a][j][i]);
+      AxisP& P = AP[a];
+      const AxisQ& Q = q[a];
+      P.pp = Q.Qpp + (G[a][0][0] * Kc[a][0][0] + G[a][1][0] * Kc[a][1][0]);
+      P.pv = Q.Qpv + (G[a][0][0] * Kc[a][0][1] + G[a][1][0] * Kc[a][1][1]);
+      P.vv = Q.Qvv + (G[a][0][1] * Kc[a][0][1] + G[a][1][1] * Kc[a][1][1]);
+      P.xpp = Q.Xpp + R(0.5) * (S[a][0][0] + Tt[0][0]);
+      P.xpv = Q.Xpv + R(0.5) * (S[a][0][1] + Tt[0][1]);
+      P.xvp = Q.Xvp + R(0.5) * (S[a][1][0] + Tt[1][0]);
+      P.xvv = Q.Xvv + R(0.5) * (S[a][1][1] + Tt[1][1]);
+      P.qp = Q.Qxp + (G[a][0][0] * kk[0] + G[a][1][0] * kk[1]);
+      P.qv = Q.Qxv + (G[a][0][1] * kk[0] + G[a][1][1] * kk[1]);
+    }
+    return 0;
+  }
+
   __device__ static __forceinline__ void stage_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -325,6 +578,30 @@ struct Lane {
       mdl.term_derivs(xT, p, P, eps, true);
     }
     if constexpr (staged) {
+      // axis-pair systems: the blocks of the terminal P, p for the lane's axes
+      constexpr int NA = GL == 1 ? 2 : 1;
+      const int h = GL == 1 ? 0 : (r & 1);
+      AxisP AP[NA];
+      R dt = R(0), dt2 = R(0), ev = R(0), ru = R(0);
+      if constexpr (Sys::kAxisPairs) {
+        dt = mdl.step_dt();
+        dt2 = dt * dt;
+        ev = mdl.vel_hess(eps);
+        ru = mdl.ctrl_hess(eps);
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+          const bool one = (GL == 1 ? a : h) == 1;
+          AP[a].pp = one ? P[1][1] : P[0][0];
+          AP[a].pv = one ? P[1][3] : P[0][2];
+          AP[a].vv = one ? P[3][3] : P[2][2];
+          AP[a].xpp = one ? P[1][0] : P[0][1];
+          AP[a].xpv = one ? P[1][2] : P[0][3];
+          AP[a].xvp = one ? P[3][0] : P[2][1];
+          AP[a].xvv = one ? P[3][2] : P[2][3];
+          AP[a].qp = one ? p[1] : p[0];
+          AP[a].qv = one ? p[3] : p[2];
+        }
+      }
       // (x_k, u_k) of the lane's steps of the next chunk are loaded while the
       // current chunk's recursion runs
       constexpr int PB = C / GL > 0 ? C / GL : 1;
@@ -355,11 +632,18 @@ struct Lane {
         stage_sync();
         const int cn = kc + 1 < C ? kc + 1 : C;
         for (int q = 0; q < cn; ++q) {
-          R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M], uq[M];
-          mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
+          R uq[M] = {};
           if constexpr (BOX) ld(uq, stage + C * ND + q * M);
-          const uint32_t bad = riccati_step<BOX>(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store, mu, uq, umax);
-          if (bad) return bad;
+          if constexpr (Sys::kAxisPairs) {
+            const uint32_t bad =
+                axis_step<GL, BOX>(w, s, kc - q, stage + q * ND, uq, AP, h, dt, dt2, ev, ru, store, mu, umax);
+            if (bad) return bad;
+          } else {
+            R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
+            mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
+            const uint32_t bad = riccati_step<BOX>(w, s, kc - q, A, B, lx, lu, Qc, Rc, P, p, store, mu, uq, umax);
+            if (bad) return bad;
+          }
         }
         stage_sync();
       }
