@@ -1,9 +1,11 @@
 // Lane-per-instance batched iLQR (paper Sec. II and IV): every lane of a
 // 64-wide wavefront owns one TO instance and runs its whole solve with the
 // small per-instance matrices (P, A, B, gains) in registers.  Trajectories and
-// gains live in HBM in a step-major layout [k][slot][component], so that for
-// a fixed step the 64 lanes of a wave touch one contiguous span: every load
-// and store of the sweeps is coalesced across the batch.
+// gains live in HBM slot-major, [slot][k][component] with each slot's block
+// padded to whole 128-byte lines: the lanes of an instance's group load
+// consecutive steps of that instance, so a group's load fills whole cache
+// lines whatever the other groups of its wave are doing (an instance that has
+// converged leaves no partly used lines behind).
 //
 // Three kernels share per-slot state in a workspace:
 //   lane_init     warm start (U0 or zeros) and the initial rollout, J^0;
@@ -36,11 +38,12 @@ struct LaneState {
   int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
   double* mu;        // Levenberg-Marquardt parameter (that variant only)
   // trajectories and gains, step-major
-  R* X;   // [nbuf][Tcap+1][Bcap][N]: the iterate (buffer cur) and trial trajectories
-  R* U;   // [nbuf][Tcap][Bcap][M]
-  R* K;   // [Tcap][Bcap][M][N]
-  R* kf;  // [Tcap][Bcap][M]
+  R* X;   // [nbuf][Bcap][xs]: x_k at k N; the iterate (buffer cur) and trial trajectories
+  R* U;   // [nbuf][Bcap][us]: u_k at k M
+  R* K;   // [Bcap][Ks]: K_k (M x N, row-major) at k M N
+  R* kf;  // [Bcap][ks]: k_k at k M
   int Bcap, Tcap, nbuf;
+  int xs, us, Ks, ks;  // per-slot strides (elements), whole cache lines
 };
 
 struct SolveParams {
@@ -62,16 +65,16 @@ struct Lane {
   using Model = typename Sys::template Model<R>;
 
   __device__ static __forceinline__ R* xp(const LaneState<R>& w, int buf, int k, int s) {
-    return w.X + ((size_t(buf) * (w.Tcap + 1) + k) * w.Bcap + s) * N;
+    return w.X + (size_t(buf) * w.Bcap + s) * w.xs + k * N;
   }
   __device__ static __forceinline__ R* up(const LaneState<R>& w, int buf, int k, int s) {
-    return w.U + ((size_t(buf) * w.Tcap + k) * w.Bcap + s) * M;
+    return w.U + (size_t(buf) * w.Bcap + s) * w.us + k * M;
   }
   __device__ static __forceinline__ R* Kp(const LaneState<R>& w, int k, int s) {
-    return w.K + (size_t(k) * w.Bcap + s) * (M * N);
+    return w.K + size_t(s) * w.Ks + k * (M * N);
   }
   __device__ static __forceinline__ R* kp(const LaneState<R>& w, int k, int s) {
-    return w.kf + (size_t(k) * w.Bcap + s) * M;
+    return w.kf + size_t(s) * w.ks + k * M;
   }
 
   template <int L>
@@ -800,42 +803,74 @@ struct Lane {
 };
 
 // ====================================================================== kernels
-template <class Sys, class R>
+// Warm start and initial rollout, GL lanes per instance: group g initialises
+// slot slots[g] (or g) from caller instance perm[g] (or g).  The rollout runs
+// in chunks of GL steps; every lane of the group steps through the chunk (the
+// dynamics are a few operations per step) and lane r keeps step kc + r: it
+// evaluates that step's stage cost and writes its (u_k, x_{k+1}), so that the
+// group's stores fill whole lines of the slot-major workspace.  The stage
+// costs are added in index order.  The warm start's controls are clamped into
+// [-umax, umax] (eq. 1; umax may be infinite).
+template <class Sys, class R, int GL>
 __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, LaneState<R> w, int nthreads,
                                                 const int32_t* __restrict__ slots, int Tmax,
                                                 const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
                                                 const double* __restrict__ x0, const double* __restrict__ U0,
                                                 int max_iter, double* __restrict__ trace, double umax) {
-  // thread t initialises slot slots[t] (or t) from caller instance perm[t] (or t);
-  // the warm start's controls are clamped into [-umax, umax] (eq. 1; umax may
-  // be infinite)
   using LN = Lane<Sys, R>;
   constexpr int N = Sys::N, M = Sys::M;
+  static_assert(GL >= 1 && GL <= 64 && (GL & (GL - 1)) == 0, "group width");
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= nthreads) return;
-  const int s = slots ? slots[tid] : tid;
+  const int gi = tid / GL, r = tid & (GL - 1);
+  if (gi >= nthreads) return;  // whole groups leave together
+  const int gbase = (threadIdx.x & 63) & ~(GL - 1);
+  const int s = slots ? slots[gi] : gi;
   const typename LN::Model mdl{prm};
-  const int b = perm ? perm[tid] : tid;
+  const int b = perm ? perm[gi] : gi;
   const int Tr = Tin ? Tin[b] : Tmax;
   const bool badT = Tr < 1 || Tr > Tmax || Tr > w.Tcap;
   const int T = badT ? 0 : Tr;  // an out-of-range horizon is never used as an index
   R x[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = R(x0[size_t(b) * N + i]);
-  for (int b = 0; b < w.nbuf; ++b) LN::st(LN::xp(w, b, 0, s), x);
+  for (int q = r; q < w.nbuf; q += GL) LN::st(LN::xp(w, q, 0, s), x);
   double J = 0.0;
-  for (int k = 0; k < T; ++k) {
-    R u[M];
+  for (int kc = 0; kc < T; kc += GL) {
+    const int kr = kc + r;
+    const int cn = T - kc < GL ? T - kc : GL;
+    R ur[M], xr[N], xr1[N];
 #pragma unroll
-    for (int i = 0; i < M; ++i) u[i] = clamp_nan(U0 ? R(U0[(size_t(b) * Tmax + k) * M + i]) : R(0), R(umax));
-    LN::st(LN::up(w, 0, k, s), u);
-    J += double(mdl.cost(x, u));
-    R xn[N];
-    mdl.dyn(x, u, xn);
+    for (int i = 0; i < M; ++i)
+      ur[i] = kr < T ? clamp_nan(U0 ? R(U0[(size_t(b) * Tmax + kr) * M + i]) : R(0), R(umax)) : R(0);
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = xn[i];
-    LN::st(LN::xp(w, 0, k + 1, s), x);
+    for (int q = 0; q < GL; ++q) {
+      if (q < cn) {
+        R u[M], xn[N];
+#pragma unroll
+        for (int i = 0; i < M; ++i) u[i] = GL == 1 ? ur[i] : __shfl(ur[i], gbase + q, 64);
+        mdl.dyn(x, u, xn);
+        if (q == r) {
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+            xr[i] = x[i];
+            xr1[i] = xn[i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = xn[i];
+      }
+    }
+    double c = 0.0;
+    if (r < cn) {
+      c = double(mdl.cost(xr, ur));
+      LN::st(LN::up(w, 0, kr, s), ur);
+      LN::st(LN::xp(w, 0, kr + 1, s), xr1);
+    }
+#pragma unroll
+    for (int q = 0; q < GL; ++q)
+      if (q < cn) J += GL == 1 ? c : __shfl(c, gbase + q, 64);
   }
+  if (r != 0) return;
   J += double(mdl.term(x));
   uint32_t st = isfinite(J) ? 0u : ST_NONFINITE;
   if (badT) {

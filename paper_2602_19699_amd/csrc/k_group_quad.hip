@@ -391,18 +391,18 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
 }
 
 template <class R>
-struct QW {  // workspace accessors (same layout as the lane schedule)
+struct QW {  // workspace accessors (the lane schedule's slot-major layout)
   static __device__ __forceinline__ R* xp(const LaneState<R>& w, int buf, int k, int s) {
-    return w.X + ((size_t(buf) * (w.Tcap + 1) + k) * w.Bcap + s) * N;
+    return w.X + (size_t(buf) * w.Bcap + s) * w.xs + k * N;
   }
   static __device__ __forceinline__ R* up(const LaneState<R>& w, int buf, int k, int s) {
-    return w.U + ((size_t(buf) * w.Tcap + k) * w.Bcap + s) * M;
+    return w.U + (size_t(buf) * w.Bcap + s) * w.us + k * M;
   }
   static __device__ __forceinline__ R* Kp(const LaneState<R>& w, int k, int s) {
-    return w.K + (size_t(k) * w.Bcap + s) * (M * N);
+    return w.K + size_t(s) * w.Ks + k * (M * N);
   }
   static __device__ __forceinline__ R* kp(const LaneState<R>& w, int k, int s) {
-    return w.kf + (size_t(k) * w.Bcap + s) * M;
+    return w.kf + size_t(s) * w.ks + k * M;
   }
 };
 

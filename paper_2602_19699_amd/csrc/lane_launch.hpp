@@ -32,6 +32,10 @@ inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap, int
   w.Bcap = Bcap;
   w.Tcap = Tcap;
   w.nbuf = nbuf;
+  w.xs = lane_stride((Tcap + 1) * N, int(sizeof(R)));
+  w.us = lane_stride(Tcap * M, int(sizeof(R)));
+  w.Ks = lane_stride(Tcap * M * N, int(sizeof(R)));
+  w.ks = lane_stride(Tcap * M, int(sizeof(R)));
   return w;
 }
 
@@ -66,7 +70,10 @@ struct LaneLaunch {
                          int max_iter, double* trace, double umax, hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
-    hipLaunchKernelGGL((lane_init<Sys, R>), dim3((nthreads + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
+    // eight lanes per instance share the stage costs and the stores
+    constexpr int IG = 8;
+    const long total = long(nthreads) * IG;
+    hipLaunchKernelGGL((lane_init<Sys, R, IG>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w, nthreads,
                        slots, Tmax, Tin, perm, x0, U0, max_iter, trace, umax);
     return hipGetLastError();
   }

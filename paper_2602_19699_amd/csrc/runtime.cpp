@@ -40,10 +40,11 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf) {
   L.cur = o; o = align256(o + 4 * B);
   L.work = o; o = align256(o + 16 * B);
   L.mu = o; o = align256(o + 8 * B);
-  L.X = o; o = align256(o + size_t(elem) * nbuf * (Tcap + 1) * B * N);
-  L.U = o; o = align256(o + size_t(elem) * nbuf * Tcap * B * M);
-  L.K = o; o = align256(o + size_t(elem) * Tcap * B * M * N);
-  L.kf = o; o = align256(o + size_t(elem) * Tcap * B * M);
+  // slot-major, each slot's block padded to whole cache lines
+  L.X = o; o = align256(o + size_t(elem) * nbuf * B * lane_stride((Tcap + 1) * N, elem));
+  L.U = o; o = align256(o + size_t(elem) * nbuf * B * lane_stride(Tcap * M, elem));
+  L.K = o; o = align256(o + size_t(elem) * B * lane_stride(Tcap * M * N, elem));
+  L.kf = o; o = align256(o + size_t(elem) * B * lane_stride(Tcap * M, elem));
   L.total = o;
   return L;
 }

@@ -18,6 +18,11 @@ void set_error(const char* fmt, ...);
 
 struct SolveParams;  // ilqr_lane.hpp
 
+// Per-slot stride, in elements of `elem` bytes, of `count` elements padded to
+// whole 128-byte cache lines (the lane schedule's trajectories and gains are
+// slot-major, so that one slot's steps fill whole lines).
+inline int lane_stride(int count, int elem) { return int((size_t(count) * elem + 127) / 128 * 128 / elem); }
+
 // Byte offsets of the per-slot state, trajectories and gains inside one
 // workspace allocation (lane schedule).  All sub-arrays are 256-byte aligned.
 struct LaneLayout {
