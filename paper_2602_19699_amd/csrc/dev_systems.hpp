@@ -28,6 +28,8 @@ struct PointMass {
   // two identical double integrators (one per plane axis) coupled only through
   // the position Hessian of the cost: the backward sweep splits by axis
   static constexpr bool kAxisPairs = true;
+  // f_x and f_u do not depend on (x, u)
+  static constexpr bool kConstJac = true;
   // structural nonzeros of f_x and f_u (A = [[I, dt I], [0, I]], B = [[dt^2 I], [dt I]])
   __host__ __device__ static constexpr bool a_nz(int i, int j) { return i == j || j == i + 2; }
   __host__ __device__ static constexpr bool b_nz(int i, int j) { return (i & 1) == j; }
@@ -183,6 +185,7 @@ struct Arm3 {
   // so that an accepted step needs no second rollout
   static constexpr bool kOwnTrialBuffers = true;
   static constexpr bool kAxisPairs = false;
+  static constexpr bool kConstJac = false;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 
@@ -508,6 +511,7 @@ struct LinQuad {
   static constexpr bool kNonNegCost = false;
   static constexpr bool kOwnTrialBuffers = false;
   static constexpr bool kAxisPairs = false;
+  static constexpr bool kConstJac = true;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 

@@ -1136,37 +1136,39 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
   }
   if (o.trace)
     for (int i = iters + 1 + r; i <= max_iter; i += GL) o.trace[size_t(b) * (max_iter + 1) + i] = J;
-  // copies, step k by lane k % GL
+  // copies, step k by lane k % GL; a lane issues the loads of CB of its
+  // steps before their stores, so that it waits for memory once per batch
   double* Xo = o.X + size_t(b) * (Tmax + 1) * N;
   double* Uo = o.U + size_t(b) * Tmax * M;
   const int K = lookahead <= 0 ? T : lookahead;
   double* xo = o.xK ? o.xK + size_t(b) * (Tmax + 1) * N : nullptr;
-  for (int k = r; k <= Tmax; k += GL) {
-    if (k <= T) {
-      const R* xs = LN::xp(w, buf, k, s);
+  constexpr int CB = 4;
+  for (int k0 = r; k0 <= Tmax; k0 += GL * CB) {
+    R xv[CB][N], xkv[CB][N], uv[CB][M];
 #pragma unroll
-      for (int i = 0; i < N; ++i) Xo[k * N + i] = double(xs[i]);
-      if (xo) {
-        const int t = k + K < T ? k + K : T;
-        const R* xk = LN::xp(w, buf, t, s);
-#pragma unroll
-        for (int i = 0; i < N; ++i) xo[k * N + i] = double(xk[i]);
+    for (int c = 0; c < CB; ++c) {
+      const int k = k0 + c * GL;
+      if (k <= T) {
+        LN::ld(xv[c], LN::xp(w, buf, k, s));
+        if (xo) LN::ld(xkv[c], LN::xp(w, buf, k + K < T ? k + K : T, s));
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < N; ++i) Xo[k * N + i] = 0.0;
-      if (xo)
-#pragma unroll
-        for (int i = 0; i < N; ++i) xo[k * N + i] = 0.0;
+      if (k < T) LN::ld(uv[c], LN::up(w, buf, k, s));
     }
-    if (k < Tmax) {
-      if (k < T) {
-        const R* us = LN::up(w, buf, k, s);
 #pragma unroll
-        for (int i = 0; i < M; ++i) Uo[k * M + i] = double(us[i]);
-      } else {
+    for (int c = 0; c < CB; ++c) {
+      const int k = k0 + c * GL;
+      if (k <= Tmax) {
+        const bool in = k <= T;
 #pragma unroll
-        for (int i = 0; i < M; ++i) Uo[k * M + i] = 0.0;
+        for (int i = 0; i < N; ++i) Xo[k * N + i] = in ? double(xv[c][i]) : 0.0;
+        if (xo)
+#pragma unroll
+          for (int i = 0; i < N; ++i) xo[k * N + i] = in ? double(xkv[c][i]) : 0.0;
+      }
+      if (k < Tmax) {
+        const bool in = k < T;
+#pragma unroll
+        for (int i = 0; i < M; ++i) Uo[k * M + i] = in ? double(uv[c][i]) : 0.0;
       }
     }
   }
@@ -1180,8 +1182,11 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = 0.0;
   }
   if (T < 0 || (!Vo && !Lo)) return;
-  // stage costs c_k (k < T), turned into cost-to-go sums below
-  if (Vo)
+  // stage costs c_k (k < T), turned into cost-to-go sums below (written by
+  // the costate walk's per-step pass where it has one)
+  const bool costs_in_walk = Sys::kConstJac && Lo;
+  const bool sums_in_walk = costs_in_walk && Vo && K >= T;
+  if (Vo && !costs_in_walk)
     for (int k = r; k < T; k += GL) {
       R x[N], u[M];
       LN::ld(x, LN::xp(w, buf, k, s));
@@ -1204,8 +1209,18 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       for (int i = 0; i < N; ++i) Lo[size_t(T) * N + i] = double(lam[i]);
     // the chain walks back in chunks of GL steps: lane q of the group loads
     // step kc - q (the next chunk is loaded while this one runs) and the chain
-    // takes each step's (x, u) from its lane by a wave shuffle
+    // takes each step's (x, u) from its lane by a wave shuffle.  When f_x does
+    // not depend on (x, u), lane q evaluates the cost gradient of its step for
+    // the chunk at once and the chain takes that instead.
     const int gbase = (threadIdx.x & 63) & ~(GL - 1);
+    R Ac[N][N] = {};
+    if constexpr (Sys::kConstJac) {
+      R Bc[N][M];
+      mdl.jac(xT, nullptr, Ac, Bc);
+    }
+    // full cost-to-go as suffix sums in the walk's own (backward) order
+    double vacc = cT;
+    if (sums_in_walk && lead) Vo[T] = cT;
     R xq[N] = {}, uq[M] = {}, xn[N] = {}, un[M] = {};
     if (T - 1 - r >= 0) {
       LN::ld(xq, LN::xp(w, buf, T - 1 - r, s));
@@ -1217,16 +1232,40 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
         LN::ld(un, LN::up(w, buf, kc - GL - r, s));
       }
       const int qn = kc + 1 < GL ? kc + 1 : GL;
+      R lq[N] = {};
+      double cq = 0.0;
+      if constexpr (Sys::kConstJac) {
+        if (kc - r >= 0) {
+          R lu[M], Qd[N][N], Rd[M][M];
+          mdl.cost_derivs(xq, uq, lq, lu, Qd, Rd, R(0), false);
+          cq = double(mdl.cost(xq, uq));
+          if (Vo && !sums_in_walk) Vo[kc - r] = cq;
+        }
+      }
       for (int q = 0; q < qn; ++q) {
         const int k = kc - q;
-        R x[N], u[M];
+        R A[N][N], lx[N];
+        if constexpr (Sys::kConstJac) {
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = __shfl(xq[i], gbase + q, 64);
+          for (int i = 0; i < N; ++i) {
+            lx[i] = __shfl(lq[i], gbase + q, 64);
 #pragma unroll
-        for (int i = 0; i < M; ++i) u[i] = __shfl(uq[i], gbase + q, 64);
-        R A[N][N], B[N][M], lx[N], lu[M], Qd[N][N], Rd[M][M];
-        mdl.jac(x, u, A, B);
-        mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
+            for (int j = 0; j < N; ++j) A[i][j] = Ac[i][j];
+          }
+          if (sums_in_walk) {
+            vacc = __shfl(cq, gbase + q, 64) + vacc;
+            if (lead) Vo[k] = vacc;
+          }
+        } else {
+          R x[N], u[M];
+#pragma unroll
+          for (int i = 0; i < N; ++i) x[i] = __shfl(xq[i], gbase + q, 64);
+#pragma unroll
+          for (int i = 0; i < M; ++i) u[i] = __shfl(uq[i], gbase + q, 64);
+          R B[N][M], lu[M], Qd[N][N], Rd[M][M];
+          mdl.jac(x, u, A, B);
+          mdl.cost_derivs(x, u, lx, lu, Qd, Rd, R(0), false);
+        }
         R ln[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -1248,7 +1287,7 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       for (int i = 0; i < M; ++i) uq[i] = un[i];
     }
   }
-  if (Vo) {
+  if (Vo && !sums_in_walk) {
     // the group's stage costs are in Vo (global memory): complete the stores
     // and order them before lane 0's loads (workgroup-scope fences around a
     // wave barrier)
