@@ -48,18 +48,18 @@ METRIC = "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latenc
 # sha256 is recorded); otherwise traffic is reported as null.
 FETCH_SCALE = 524288.0 / 262159.0
 WRITE_SCALE = 524288.0 / 524288.0
-LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp")
+LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.hpp")
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "f3b1965e4b6b16aeefc2c5476b2f689bcf955d9991f7a3f60d4d2be65f793af5",
-        "fetch_kib": 461961.6, "write_kib": 361427.3,
+        "sha256": "86f0247953f9d46963215fb5a33de86b963e063910c6b319f5a2eed5b81f39f1",
+        "fetch_kib": 225413.3, "write_kib": 312938.8,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "96c7a01b55ba06f424ca2fb493e661bad320c48ef0aff1a23e65295a537c9a59",
-        "fetch_kib": 6142654.7, "write_kib": 16461842.5,
+        "sha256": "449d0acc2a58101b7f005b8588a6621334445dcf7e257e9c65a859cd29ce4364",
+        "fetch_kib": 1474202.5, "write_kib": 12010970.6,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }

@@ -48,13 +48,23 @@ struct PointMass {
       xn[3] = vy;
     }
 
+    // the obstacle bump exp(-d2 / r_i^2): in FP32 the hardware base-2
+    // exponential with log2(e) folded into the parameter (one multiply fewer)
+    CBIC_HD __forceinline__ R bump(R d2, int i) const {
+      if constexpr (sizeof(R) == 4) {
+        return __builtin_amdgcn_exp2f(-d2 * float(p[9 + 3 * i] * 1.4426950408889634));
+      } else {
+        return dexp(-d2 * R(p[9 + 3 * i]));
+      }
+    }
+
     CBIC_HD __forceinline__ R cost(const R* x, const R* u) const {
       const R ex = x[0] - R(p[5]), ey = x[1] - R(p[6]);
       R l = R(p[1]) * (u[0] * u[0] + u[1] * u[1]) + R(p[2]) * (ex * ex + ey * ey);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
         const R dx = x[0] - R(p[7 + 3 * i]), dy = x[1] - R(p[8 + 3 * i]);
-        l += R(p[4]) * dexp(-(dx * dx + dy * dy) * R(p[9 + 3 * i]));
+        l += R(p[4]) * bump(dx * dx + dy * dy, i);
       }
       return l;
     }
@@ -86,7 +96,7 @@ struct PointMass {
       for (int i = 0; i < 3; ++i) {
         const R ir2 = R(p[9 + 3 * i]);
         const R dx = x[0] - R(p[7 + 3 * i]), dy = x[1] - R(p[8 + 3 * i]);
-        const R e = R(p[4]) * dexp(-(dx * dx + dy * dy) * ir2);
+        const R e = R(p[4]) * bump(dx * dx + dy * dy, i);
         const R e2 = R(-2) * e * ir2;
         gx += e2 * dx;
         gy += e2 * dy;
