@@ -369,8 +369,9 @@ struct Lane {
   // position gradient, D[2 + 2h] diagonal and D[3] cross-axis position Hessian
   // entries, D[5 + h] control gradient).  ev, ru: the clipped velocity and
   // control Hessians.  Gains, the bounded step (BOX, u the iterate's control)
-  // and the Levenberg-Marquardt shift as in riccati_step; `store` only on the
-  // group's lead lane, which holds axis 0.
+  // and the Levenberg-Marquardt shift as in riccati_step; with `store` (every
+  // lane of the group) each lane writes its axis' gain columns.  Returns the
+  // first failure's status bit; the step's results are then not used.
   template <int GL, bool BOX>
   __device__ static __forceinline__ uint32_t axis_step(const LaneState<R>& w, int s, int k, const R* D,
                                                        const R (&u)[M], AxisP (&AP)[GL == 1 ? 2 : 1], int h,
@@ -401,7 +402,9 @@ struct Lane {
     Quu[1][1] += mu;
     constexpr int NR = sizeof(R) == 4 ? 1 : 2;
     double Lc[M][M], invd[M];
-    if (!chol_fp64<M, NR>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    // a failure is recorded and the step runs on (the sweep stops at the end
+    // of its chunk): no branch per step
+    uint32_t bad = chol_fp64<M, NR>(Quu, Lc, invd) ? 0u : ST_CHOL_FAIL;
     // Q_ux on the lane's axes in control order: G[a][c][j], j = 0 position, 1 velocity
     R G[NA][M][2];
 #pragma unroll
@@ -476,7 +479,7 @@ struct Lane {
           lo[i] = -umax - double(u[i]);
           hi[i] = umax - double(u[i]);
         }
-        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd)) return ST_CHOL_FAIL;
+        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd) && !bad) bad = ST_CHOL_FAIL;
       }
       kk[0] = R(col[0]);
       kk[1] = R(col[1]);
@@ -506,16 +509,20 @@ struct Lane {
     for (int c = 0; c < M; ++c)
 #pragma unroll
       for (int j = 0; j < 2; ++j) fin = fin & dfinite(Kc[0][c][j]) & dfinite(Ko[0][c][j]);
-    if (!fin) return ST_NONFINITE;
+    if (!fin && !bad) bad = ST_NONFINITE;
     if (store) {
-      // K row c over (p_0, p_1, v_0, v_1); the lead lane's own axis is axis 0
+      // K row c over (p_0, p_1, v_0, v_1): every lane stores its own axis'
+      // columns (the group's pairs store the same values at the same
+      // addresses), so no lane waits on a branch
       R* dK = Kp(w, k, s);
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        dK[c * N + 0] = Kc[0][c][0];
-        dK[c * N + 1] = Ko[0][c][0];
-        dK[c * N + 2] = Kc[0][c][1];
-        dK[c * N + 3] = Ko[0][c][1];
+      for (int a = 0; a < NA; ++a) {
+        const int ax = GL == 1 ? a : h;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          dK[c * N + ax] = Kc[a][c][0];
+          dK[c * N + ax + 2] = Kc[a][c][1];
+        }
       }
       st(kp(w, k, s), kk);
     }
@@ -547,7 +554,7 @@ struct Lane {
       P.qp = Q.Qxp + (G[a][0][0] * kk[0] + G[a][1][0] * kk[1]);
       P.qv = Q.Qxv + (G[a][0][1] * kk[0] + G[a][1][1] * kk[1]);
     }
-    return 0;
+    return bad;
   }
 
   __device__ static __forceinline__ void stage_sync() {
@@ -617,6 +624,7 @@ struct Lane {
           ld(pu[q], up(w, buf, k, s));
         }
       }
+      uint32_t chunk_bad = 0;  // first failure in the chunk (axis-pair steps)
       for (int kc = T - 1; kc >= 0; kc -= C) {
 #pragma unroll
         for (int q = 0; q < PB; ++q)
@@ -638,9 +646,9 @@ struct Lane {
           R uq[M] = {};
           if constexpr (BOX) ld(uq, stage + C * ND + q * M);
           if constexpr (Sys::kAxisPairs) {
-            const uint32_t bad =
-                axis_step<GL, BOX>(w, s, kc - q, stage + q * ND, uq, AP, h, dt, dt2, ev, ru, store, mu, umax);
-            if (bad) return bad;
+            const uint32_t b =
+                axis_step<GL, BOX>(w, s, kc - q, stage + q * ND, uq, AP, h, dt, dt2, ev, ru, true, mu, umax);
+            if (!chunk_bad) chunk_bad = b;
           } else {
             R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
             mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
@@ -649,6 +657,7 @@ struct Lane {
           }
         }
         stage_sync();
+        if (chunk_bad) return chunk_bad;
       }
       return 0;
     }

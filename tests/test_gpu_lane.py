@@ -217,3 +217,42 @@ def test_group_widths_give_identical_results(ctx, kind):
         g = gpu_solve(ctx, kind, p, x0, T, T=Tb, max_iter=15, group_lanes=gl)
         for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"):
             np.testing.assert_array_equal(ref[k], g[k], err_msg=f"group_lanes={gl} field {k}")
+
+
+@pytest.mark.parametrize("kind", [PM, P3], ids=["pm", "arm"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("K", [0, 7], ids=["full", "K7"])
+def test_partial_targets_identical(ctx, kind, prec, K):
+    # every subset of the critic targets (V-bar, V-bar_x, x_{k+K}) is the same
+    # bits as the full request: the finalize kernel takes other branches when
+    # some are not requested (the costate walk, the stage costs and the sums)
+    import torch
+    from paper_2602_19699_amd import cbic
+    if kind == PM:
+        p, x0, T_max, Tb = I.point_mass_params(0), I.point_mass_x0(100, 31), 60, I.horizons(100, 1, 60, seed=2)
+    else:
+        p, x0, T_max, Tb = I.planar3_params(0), I.planar3_x0(40, 32), 80, I.horizons(40, 20, 80, seed=4)
+    dev = torch.device("cuda", ctx.device)
+    sys_ = cbic.System(ctx, kind, p)
+    o = cbic.Options(max_iter=10, precision=prec, lookahead_K=K)
+    x0t = torch.as_tensor(x0, device=dev)
+    Tt = torch.as_tensor(Tb, device=dev)
+    B = len(x0)
+
+    def run(**keep):
+        out = cbic.Outputs.allocate(B, T_max, sys_.n, sys_.m, dev, targets=True)
+        for f in ("Vbar", "Vx", "xK"):
+            if not keep.get(f, False):
+                setattr(out, f, None)
+        cbic.solve_batch(ctx, sys_, x0t, T_max, T=Tt, opts=o, out=out)
+        torch.cuda.synchronize(dev)
+        return {f: None if getattr(out, f) is None else getattr(out, f).cpu().numpy()
+                for f in ("X", "U", "J", "Vbar", "Vx", "xK")}
+
+    full = run(Vbar=True, Vx=True, xK=True)
+    for keep in (dict(Vbar=True), dict(Vx=True), dict(xK=True), dict(Vbar=True, xK=True), {}):
+        part = run(**keep)
+        for f, v in part.items():
+            if v is not None:
+                np.testing.assert_array_equal(v, full[f], err_msg=f"{keep} field {f}")
+    sys_.close()
