@@ -30,6 +30,7 @@ struct PointMass {
   static constexpr bool kAxisPairs = true;
   // f_x and f_u do not depend on (x, u)
   static constexpr bool kConstJac = true;
+  static constexpr bool kSemiImplicit = false;  // (constant Jacobians: nothing to factor)
   // structural nonzeros of f_x and f_u (A = [[I, dt I], [0, I]], B = [[dt^2 I], [dt I]])
   __host__ __device__ static constexpr bool a_nz(int i, int j) { return i == j || j == i + 2; }
   __host__ __device__ static constexpr bool b_nz(int i, int j) { return (i & 1) == j; }
@@ -196,6 +197,8 @@ struct Arm3 {
   static constexpr bool kOwnTrialBuffers = true;
   static constexpr bool kAxisPairs = false;
   static constexpr bool kConstJac = false;
+  // q+ = q + dt qd+: the backward sweep takes the Jacobians in factored form
+  static constexpr bool kSemiImplicit = true;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 
@@ -269,7 +272,12 @@ struct Arm3 {
       }
     }
 
-    CBIC_HD __forceinline__ void jac(const R* x, const R* u, R A[N][N], R B[N][M]) const {
+    CBIC_HD __forceinline__ R step_dt() const { return R(p[0]); }
+
+    // Jacobians of the velocity update qd+ = qd + dt qdd: V = d qd+ / d(q, qd)
+    // (3 x 6), W = d qd+ / d tau (3 x 3).  With q+ = q + dt qd+ the full
+    // Jacobians are f_x = S + C V and f_u = C W, S = diag(I, 0), C = [dt I; I].
+    CBIC_HD __forceinline__ void jac_v(const R* x, const R* u, R V[3][N], R W[3][M]) const {
       const R dt = R(p[0]);
       const R h12 = R(p[4]), h13 = R(p[5]), h23 = R(p[6]);
       Trig t;
@@ -322,19 +330,34 @@ struct Arm3 {
         Av[0][j] = Dv[0][j]; Av[1][j] = Dv[1][j] - Dv[0][j]; Av[2][j] = Dv[2][j] - Dv[1][j];
         At[0][j] = Dt[0][j]; At[1][j] = Dt[1][j] - Dt[0][j]; At[2][j] = Dt[2][j] - Dt[1][j];
       }
-      const R dt2 = dt * dt;
 #pragma unroll
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           const R id = (i == j) ? R(1) : R(0);
-          A[i][j] = id + dt2 * Aq[i][j];
-          A[i][3 + j] = dt * id + dt2 * Av[i][j];
-          A[3 + i][j] = dt * Aq[i][j];
-          A[3 + i][3 + j] = id + dt * Av[i][j];
-          B[i][j] = dt2 * At[i][j];
-          B[3 + i][j] = dt * At[i][j];
+          V[i][j] = dt * Aq[i][j];
+          V[i][3 + j] = id + dt * Av[i][j];
+          W[i][j] = dt * At[i][j];
         }
+    }
+
+    CBIC_HD __forceinline__ void jac(const R* x, const R* u, R A[N][N], R B[N][M]) const {
+      const R dt = R(p[0]);
+      R V[3][N], W[3][M];
+      jac_v(x, u, V, W);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          A[i][j] = (i == j ? R(1) : R(0)) + dt * V[i][j];
+          A[3 + i][j] = V[i][j];
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          B[i][j] = dt * W[i][j];
+          B[3 + i][j] = W[i][j];
+        }
+      }
     }
 
     // end effector, its joint Jacobian and the per-link terms for the Hessian
@@ -434,45 +457,45 @@ struct Arm3 {
       }
     }
 
-    // Per-step derivative block: f_x (36), f_u (18), l_q (3), clipped q-block
-    // Hessian (6, upper triangle), l_u (3).
-    static constexpr int ND = 66;
+    // Per-step derivative block: the velocity-update Jacobians V (18) and W
+    // (9), l_q (3), clipped q-block Hessian (6, upper triangle), l_u (3).
+    static constexpr int ND = 39;
     CBIC_HD __forceinline__ void pack_derivs(const R* x, const R* u, R* D, R eps) const {
-      R A[N][N], B[N][M], lx[N], lu[M], Q[N][N], Ru[M][M];
-      jac(x, u, A, B);
+      R V[3][N], W[3][M], lx[N], lu[M], Q[N][N], Ru[M][M];
+      jac_v(x, u, V, W);
       cost_derivs(x, u, lx, lu, Q, Ru, eps, true);
 #pragma unroll
-      for (int i = 0; i < N; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < N; ++j) D[i * N + j] = A[i][j];
+        for (int j = 0; j < N; ++j) D[i * N + j] = V[i][j];
 #pragma unroll
-      for (int i = 0; i < N; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < M; ++j) D[36 + i * M + j] = B[i][j];
-      D[54] = lx[0]; D[55] = lx[1]; D[56] = lx[2];
-      D[57] = Q[0][0]; D[58] = Q[0][1]; D[59] = Q[0][2]; D[60] = Q[1][1]; D[61] = Q[1][2]; D[62] = Q[2][2];
-      D[63] = lu[0]; D[64] = lu[1]; D[65] = lu[2];
+        for (int j = 0; j < M; ++j) D[18 + i * M + j] = W[i][j];
+      D[27] = lx[0]; D[28] = lx[1]; D[29] = lx[2];
+      D[30] = Q[0][0]; D[31] = Q[0][1]; D[32] = Q[0][2]; D[33] = Q[1][1]; D[34] = Q[1][2]; D[35] = Q[2][2];
+      D[36] = lu[0]; D[37] = lu[1]; D[38] = lu[2];
     }
-    CBIC_HD __forceinline__ void unpack_derivs(const R* D, R A[N][N], R B[N][M], R lx[N], R lu[M], R Q[N][N],
-                                               R Ru[M][M], R eps) const {
+    CBIC_HD __forceinline__ void unpack_derivs_si(const R* D, R V[3][N], R W[3][M], R lx[N], R lu[M], R Q[N][N],
+                                                  R Ru[M][M], R eps) const {
 #pragma unroll
-      for (int i = 0; i < N; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < N; ++j) A[i][j] = D[i * N + j];
+        for (int j = 0; j < N; ++j) V[i][j] = D[i * N + j];
 #pragma unroll
-      for (int i = 0; i < N; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int j = 0; j < M; ++j) B[i][j] = D[36 + i * M + j];
-      lx[0] = D[54]; lx[1] = D[55]; lx[2] = D[56]; lx[3] = R(0); lx[4] = R(0); lx[5] = R(0);
+        for (int j = 0; j < M; ++j) W[i][j] = D[18 + i * M + j];
+      lx[0] = D[27]; lx[1] = D[28]; lx[2] = D[29]; lx[3] = R(0); lx[4] = R(0); lx[5] = R(0);
 #pragma unroll
       for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int j = 0; j < N; ++j) Q[i][j] = R(0);
-      Q[0][0] = D[57]; Q[0][1] = D[58]; Q[0][2] = D[59]; Q[1][1] = D[60]; Q[1][2] = D[61]; Q[2][2] = D[62];
-      Q[1][0] = D[58]; Q[2][0] = D[59]; Q[2][1] = D[61];
+      Q[0][0] = D[30]; Q[0][1] = D[31]; Q[0][2] = D[32]; Q[1][1] = D[33]; Q[1][2] = D[34]; Q[2][2] = D[35];
+      Q[1][0] = D[31]; Q[2][0] = D[32]; Q[2][1] = D[34];
       const R ev = dmax(R(0), eps);
       Q[3][3] = ev; Q[4][4] = ev; Q[5][5] = ev;
-      lu[0] = D[63]; lu[1] = D[64]; lu[2] = D[65];
+      lu[0] = D[36]; lu[1] = D[37]; lu[2] = D[38];
       const R ru = dmax(R(2) * R(p[10]), eps);
 #pragma unroll
       for (int i = 0; i < M; ++i)
@@ -522,6 +545,7 @@ struct LinQuad {
   static constexpr bool kOwnTrialBuffers = false;
   static constexpr bool kAxisPairs = false;
   static constexpr bool kConstJac = true;
+  static constexpr bool kSemiImplicit = false;
   __host__ __device__ static constexpr bool a_nz(int, int) { return true; }
   __host__ __device__ static constexpr bool b_nz(int, int) { return true; }
 

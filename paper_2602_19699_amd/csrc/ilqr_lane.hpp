@@ -164,10 +164,105 @@ struct Lane {
         Qux[i][j] = q;
       }
     }
-    // Cholesky of Q_uu (+ mu I in the Levenberg-Marquardt variant) in FP64
-    // (one Newton step on the reciprocal pivots when the gains are FP32) and
-    // the gains; the checks are on the gains as stored, so an FP32 overflow is
-    // caught as well
+    return gains_update<BOX>(w, s, k, Qx, Qu, Qxx, Quu, Qux, P, p, store, mu, u, umax);
+  }
+
+  // One Riccati step for a semi-implicit Euler system (q+ = q + dt v+, the
+  // state (q, v) with NQ = N / 2 positions): the dynamics Jacobians factor as
+  // A = S + C V and B = C W with S = diag(I, 0), C = [dt I; I] and V (NQ x N),
+  // W (NQ x M) the Jacobians of the velocity update, so the products go
+  // through P C, C^T P A and C^T P B (about 60 % of the dense count).
+  template <bool BOX>
+  __device__ static __forceinline__ uint32_t riccati_step_si(const LaneState<R>& w, int s, int k, R dt,
+                                                             const R (&V)[N / 2][N], const R (&W)[N / 2][M],
+                                                             const R (&lx)[N], const R (&lu)[M],
+                                                             const R (&Qc)[N][N], const R (&Rc)[M][M],
+                                                             R (&P)[N][N], R (&p)[N], bool store, double mu,
+                                                             const R (&u)[M], double umax) {
+    constexpr int NQ = N / 2;
+    R PC[N][NQ];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) PC[i][c] = dt * P[i][c] + P[i][NQ + c];
+    R PA[N][N], PB[N][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R v = j < NQ ? P[i][j] : R(0);
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) v += PC[i][c] * V[c][j];
+        PA[i][j] = v;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        R v = R(0);
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) v += PC[i][c] * W[c][m];
+        PB[i][m] = v;
+      }
+    }
+    R CPA[NQ][N], CPB[NQ][M], Cp[NQ];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) CPA[c][j] = dt * PA[c][j] + PA[NQ + c][j];
+#pragma unroll
+      for (int m = 0; m < M; ++m) CPB[c][m] = dt * PB[c][m] + PB[NQ + c][m];
+      Cp[c] = dt * p[c] + p[NQ + c];
+    }
+    R Qx[N], Qu[M], Qxx[N][N], Qux[M][N];
+    double Quu[M][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R v = lx[i] + (i < NQ ? p[i] : R(0));
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) v += V[c][i] * Cp[c];
+      Qx[i] = v;
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        R q = Qc[i][j] + (i < NQ ? PA[i][j] : R(0));
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += V[c][i] * CPA[c][j];
+        Qxx[i][j] = q;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      R v = lu[m];
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) v += W[c][m] * Cp[c];
+      Qu[m] = v;
+#pragma unroll
+      for (int n = m; n < M; ++n) {
+        R q = Rc[m][n];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += W[c][m] * CPB[c][n];
+        Quu[m][n] = double(q);
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R q = R(0);
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += W[c][m] * CPA[c][j];
+        Qux[m][j] = q;
+      }
+    }
+    return gains_update<BOX>(w, s, k, Qx, Qu, Qxx, Quu, Qux, P, p, store, mu, u, umax);
+  }
+
+  // The control step and the (P, p) update from the step's Q blocks (Q_xx
+  // and Q_uu upper triangles): Cholesky of Q_uu (+ mu I in the
+  // Levenberg-Marquardt variant) in FP64 (one Newton step on the reciprocal
+  // pivots when the gains are FP32) and the gains; the checks are on the
+  // gains as stored, so an FP32 overflow is caught as well.
+  template <bool BOX>
+  __device__ static __forceinline__ uint32_t gains_update(const LaneState<R>& w, int s, int k, const R (&Qx)[N],
+                                                          const R (&Qu)[M], const R (&Qxx)[N][N],
+                                                          double (&Quu)[M][M], const R (&Qux)[M][N], R (&P)[N][N],
+                                                          R (&p)[N], bool store, double mu, const R (&u)[M],
+                                                          double umax) {
     if (mu != 0.0)
 #pragma unroll
       for (int i = 0; i < M; ++i) Quu[i][i] += mu;
@@ -593,6 +688,7 @@ struct Lane {
       const int h = GL == 1 ? 0 : (r & 1);
       AxisP AP[NA];
       R dt = R(0), dt2 = R(0), ev = R(0), ru = R(0);
+      if constexpr (Sys::kSemiImplicit) dt = mdl.step_dt();
       if constexpr (Sys::kAxisPairs) {
         dt = mdl.step_dt();
         dt2 = dt * dt;
@@ -649,6 +745,12 @@ struct Lane {
             const uint32_t b =
                 axis_step<GL, BOX>(w, s, kc - q, stage + q * ND, uq, AP, h, dt, dt2, ev, ru, true, mu, umax);
             if (!chunk_bad) chunk_bad = b;
+          } else if constexpr (Sys::kSemiImplicit) {
+            R V[N / 2][N], W[N / 2][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
+            mdl.unpack_derivs_si(stage + q * ND, V, W, lx, lu, Qc, Rc, eps);
+            const uint32_t bad =
+                riccati_step_si<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, store, mu, uq, umax);
+            if (bad) return bad;
           } else {
             R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
             mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
