@@ -1330,7 +1330,8 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       mdl.jac(xT, nullptr, Ac, Bc);
     }
     // full cost-to-go as suffix sums in the walk's own (backward) order
-    double vacc = cT;
+    double vacc = cT, vmine = 0.0;
+    R lmine[N] = {};
     if (sums_in_walk && lead) Vo[T] = cT;
     R xq[N] = {}, uq[M] = {}, xn[N] = {}, un[M] = {};
     if (T - 1 - r >= 0) {
@@ -1365,7 +1366,7 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
           }
           if (sums_in_walk) {
             vacc = __shfl(cq, gbase + q, 64) + vacc;
-            if (lead) Vo[k] = vacc;
+            if (q == r) vmine = vacc;
           }
         } else {
           R x[N], u[M];
@@ -1388,9 +1389,18 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
         }
 #pragma unroll
         for (int i = 0; i < N; ++i) lam[i] = ln[i];
-        if (lead)
+        // every lane walks the chain; lane q keeps step kc - q for the
+        // chunk's stores below
+        if (q == r)
 #pragma unroll
-          for (int i = 0; i < N; ++i) Lo[size_t(k) * N + i] = double(ln[i]);
+          for (int i = 0; i < N; ++i) lmine[i] = ln[i];
+      }
+      // the chunk's costates (and cost-to-go) by the lanes of their steps:
+      // contiguous stores instead of one lane's per-step pieces
+      if (kc - r >= 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) Lo[size_t(kc - r) * N + i] = double(lmine[i]);
+        if (sums_in_walk) Vo[kc - r] = vmine;
       }
 #pragma unroll
       for (int i = 0; i < N; ++i) xq[i] = xn[i];
