@@ -256,7 +256,9 @@ struct Lane {
   // and Q_uu upper triangles): Cholesky of Q_uu (+ mu I in the
   // Levenberg-Marquardt variant) in FP64 (one Newton step on the reciprocal
   // pivots when the gains are FP32) and the gains; the checks are on the
-  // gains as stored, so an FP32 overflow is caught as well.
+  // gains as stored, so an FP32 overflow is caught as well.  Returns the first
+  // failure's status bit (the step's results are then not used) without
+  // leaving early, so the step has no branch.
   template <bool BOX>
   __device__ static __forceinline__ uint32_t gains_update(const LaneState<R>& w, int s, int k, const R (&Qx)[N],
                                                           const R (&Qu)[M], const R (&Qxx)[N][N],
@@ -268,7 +270,8 @@ struct Lane {
       for (int i = 0; i < M; ++i) Quu[i][i] += mu;
     constexpr int NR = sizeof(R) == 4 ? 1 : 2;
     double Lc[M][M], invd[M];
-    if (!chol_fp64<M, NR>(Quu, Lc, invd)) return ST_CHOL_FAIL;
+    // a failure is recorded and the step runs on; the caller acts on it
+    uint32_t bad = chol_fp64<M, NR>(Quu, Lc, invd) ? 0u : ST_CHOL_FAIL;
     R Kk[M][N], kk[M];
     bool fin = true;
     bool solved = false;
@@ -345,7 +348,7 @@ struct Lane {
           lo[i] = -umax - double(u[i]);
           hi[i] = umax - double(u[i]);
         }
-        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd)) return ST_CHOL_FAIL;
+        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd) && !bad) bad = ST_CHOL_FAIL;
       }
 #pragma unroll
       for (int i = 0; i < M; ++i) {
@@ -364,7 +367,7 @@ struct Lane {
         }
       }
     }
-    if (!fin) return ST_NONFINITE;
+    if (!fin && !bad) bad = ST_NONFINITE;
     if (store) {
       R* dK = Kp(w, k, s);
 #pragma unroll
@@ -389,7 +392,7 @@ struct Lane {
         P[j][i] = q;
       }
     }
-    return 0;
+    return bad;
   }
 
   // ------------------------------------------------------------------ backward, axis pairs
@@ -748,9 +751,12 @@ struct Lane {
           } else if constexpr (Sys::kSemiImplicit) {
             R V[N / 2][N], W[N / 2][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
             mdl.unpack_derivs_si(stage + q * ND, V, W, lx, lu, Qc, Rc, eps);
-            const uint32_t bad =
-                riccati_step_si<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, store, mu, uq, umax);
-            if (bad) return bad;
+            // every lane stores the gains (the group's lanes hold the same
+            // values): no branch per step; a failure ends the sweep at the
+            // end of the chunk
+            const uint32_t b =
+                riccati_step_si<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, true, mu, uq, umax);
+            if (!chunk_bad) chunk_bad = b;
           } else {
             R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
             mdl.unpack_derivs(stage + q * ND, A, B, lx, lu, Qc, Rc, eps);
