@@ -52,14 +52,14 @@ LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_laun
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "86f0247953f9d46963215fb5a33de86b963e063910c6b319f5a2eed5b81f39f1",
-        "fetch_kib": 225413.3, "write_kib": 312938.8,
+        "sha256": "9e5192e9760c0edaf6018ea2d3056b38a62224c84cbef0de5c8a10d872255096",
+        "fetch_kib": 222970.7, "write_kib": 312895.4,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "449d0acc2a58101b7f005b8588a6621334445dcf7e257e9c65a859cd29ce4364",
-        "fetch_kib": 1474202.5, "write_kib": 12010970.6,
+        "sha256": "69f13ea61044a1936df5ebc7ff2b41097c67960de33445545b580acb1a5d93b0",
+        "fetch_kib": 1477050.5, "write_kib": 12073811.7,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
