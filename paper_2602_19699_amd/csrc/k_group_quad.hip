@@ -81,6 +81,19 @@ __device__ __forceinline__ void wave_sync() {
 __device__ __forceinline__ float bcast(float v, int j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
+// 1/sqrt(d) from the hardware estimate and Newton steps y <- y (3 - d y^2) / 2,
+// each squaring the relative error: two in FP64, one in FP32 (the pivots of
+// the Cholesky factors below are then d * (1/sqrt(d)), without a division)
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * (1.5 - 0.5 * d * y * y);
+  return y * (1.5 - 0.5 * d * y * y);
+}
+__device__ __forceinline__ float rsqrt_nr(float d) {
+  const float y = __builtin_amdgcn_rsqf(d);
+  return y * (1.5f - 0.5f * d * y * y);
+}
+
 __device__ __forceinline__ double bcast(double v, int j) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
@@ -133,8 +146,8 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
 #pragma unroll
   for (int j = 0; j < NV; ++j) {
     const R piv = bcast(m[j], j);
-    const R ljj = dsqrt(piv);
-    const R inv = R(1) / ljj;
+    const R inv = rsqrt_nr(piv);
+    const R ljj = piv * inv;
     if (lane == 0) ws.Li[j] = inv;
     const R lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : R(0));
     m[j] = lij;
@@ -338,8 +351,8 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
     for (int j = 0; j < M; ++j) {
       const double piv = bcast(m[j], j);
       ok = ok && (piv > 0.0) && isfinite(piv);
-      const double ljj = sqrt(piv);
-      const double inv = 1.0 / ljj;
+      const double inv = rsqrt_nr(piv);
+      const double ljj = piv * inv;
       if (lane == 0) sm.Lqi[j] = inv;
       const double lij = (lane == j) ? ljj : (lane > j && row ? m[j] * inv : 0.0);
       m[j] = lij;
