@@ -52,13 +52,13 @@ LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_laun
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "9e5192e9760c0edaf6018ea2d3056b38a62224c84cbef0de5c8a10d872255096",
+        "sha256": "0e10cae758886918fdff3391054d6f135fea88b7f2666ca508ff4c2769cfe615",
         "fetch_kib": 222970.7, "write_kib": 312895.4,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "69f13ea61044a1936df5ebc7ff2b41097c67960de33445545b580acb1a5d93b0",
+        "sha256": "a8f4e96a81197bebb04df0b64233ae91c0e61c937b15bfad1260cf7a6afd1498",
         "fetch_kib": 1477050.5, "write_kib": 12073811.7,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },

@@ -1008,12 +1008,15 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 
 // Up to `iters` iterations for every active slot, with GL lanes per instance.
 // The GL lanes of a group run the backward sweep redundantly (identical
-// arithmetic on identical data; one lane stores the gains) and split the line
-// search: in round q lane r tries alpha_j, j = q*GL + r.  The first j whose
-// J_hat < J is taken (a wave ballot over the group), which is exactly the
-// sequential rule.  Every lane writes its trial into a trajectory buffer of
-// its own, and the accepted lane's buffer becomes the iterate.  `slots`
-// (optional) maps the group index to a slot, for sparse slot sets.
+// arithmetic on identical data; the point mass splits each step over lane
+// pairs by axis, and lanes holding the same gains all store them) and split
+// the line search: in round q lane r tries alpha_j, j = q*GL + r.  The first
+// j whose J_hat < J is taken (a wave ballot over the group), which is exactly
+// the sequential rule.  Systems with their own trial buffers have every lane
+// write its trial and the accepted lane's buffer becomes the iterate; the
+// others write alpha = 1 while trying it and roll another accepted step out
+// once more to write it.  `slots` (optional) maps the group index to a slot,
+// for sparse slot sets.
 //
 // BOX selects the variant with the control bound of eq. 1 (sp.umax finite).
 template <class Sys, class R, int GL, bool BOX>
