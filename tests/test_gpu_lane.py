@@ -256,3 +256,29 @@ def test_partial_targets_identical(ctx, kind, prec, K):
             if v is not None:
                 np.testing.assert_array_equal(v, full[f], err_msg=f"{keep} field {f}")
     sys_.close()
+
+
+@pytest.mark.parametrize("kind", [PM, P3], ids=["pm", "arm"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_cholesky_failure_inside_a_chunk(ctx, kind, prec):
+    # zero cost weights and a zero clipping floor make Q_uu = 0 at the sweep's
+    # first step: the kernel records the failure, finishes the chunk and freezes
+    # the instance with its warm start and status CHOL_FAIL, as the oracle does
+    # (the point mass takes the axis-pair step, the arm the factored one)
+    B, T = 20, 40
+    if kind == PM:
+        p = I.point_mass_params(0, w_u=0.0)
+        p[2:5] = 0.0  # position, terminal and obstacle weights
+        x0, m = I.point_mass_x0(B, 5), 2
+    else:
+        p = I.planar3_params(0, w_u=0.0, w_ee=0.0, w_T=0.0, w_obs=0.0)
+        x0, m = I.planar3_x0(B, 6), 3
+    U0 = np.random.default_rng(1).normal(size=(B, T, m)) * 0.1
+    r = orc.solve_batch(kind, p, x0, T, U0=U0, opts=oracle_opts(psd_eps=0.0))
+    assert np.all(r.status == orc.ST_CHOL_FAIL) and np.all(r.iters == 0)
+    Uw = U0 if prec == 0 else U0.astype(np.float32).astype(np.float64)
+    for gl in (1, 2, 8):
+        g = gpu_solve(ctx, kind, p, x0, T, U0=U0, psd_eps=0.0, precision=prec, group_lanes=gl)
+        assert np.all(g["status"] == orc.ST_CHOL_FAIL), (gl, g["status"])
+        assert np.all(g["iters"] == 0)
+        np.testing.assert_array_equal(g["U"], Uw)
