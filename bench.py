@@ -53,13 +53,13 @@ COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
         "sha256": "0e10cae758886918fdff3391054d6f135fea88b7f2666ca508ff4c2769cfe615",
-        "fetch_kib": 222970.7, "write_kib": 312895.4,
+        "fetch_kib": 222977.4, "write_kib": 312875.2,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
         "sha256": "a8f4e96a81197bebb04df0b64233ae91c0e61c937b15bfad1260cf7a6afd1498",
-        "fetch_kib": 1477050.5, "write_kib": 12073811.7,
+        "fetch_kib": 1477092.8, "write_kib": 12074038.4,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
 }
