@@ -829,79 +829,88 @@ __global__ void __launch_bounds__(NT, 2) quad_final(const double* __restrict__ p
     if (tid == 0) Vo[T] = cT;
   }
   __syncthreads();
-  // costate lambda_k = l_x + f_x^T lambda_{k+1} by wave 0, through the
-  // adjoint of the semi-implicit step instead of f_x itself: with
+  // costate lambda_k = l_x + f_x^T lambda_{k+1} through the adjoint of the
+  // semi-implicit step instead of f_x itself: with
   // mu = lambda_v+ + dt E^T lambda_q+ and nu = M^-1 mu (M's factor from the
   // dynamics at (x_k, u_k); M is symmetric),
   //   f_x^T lambda+ = [lambda_q+ + dt g ; mu - dt (W2 cos q) . nu],
   //   g_j = -cos q_j (W1^T nu)_j + sin q_j (W2^T (nu . v))_j - 0.1 cos q_j a_j nu_j  (j < 18),
   // and nothing from the dynamics for q_18: one solve per step instead of the
-  // 48 columns of [f_x | f_u].  The stage costs come from the same wave.
+  // 48 columns of [f_x | f_u].
+  // The dynamics at a step (M's factor, accelerations, sin/cos) do not depend
+  // on lambda: the four waves evaluate them for four steps at once (wave w
+  // for step kc - w, with that step's stage cost), then wave 0 walks the four
+  // steps.
   (void)dblk;
-  if (tid < 64) {
-    const int lane = tid;
-    WaveScratch<R>& ws = w0;
+  {
+    const int wid = tid >> 6, lane = tid & 63;
     const bool row = lane < NV;
     const int ri = row ? lane : 0;
-    // (x_k, u_k) of the next step are loaded while this one runs
-    R xr = lane < N ? Q::xp(w, buf, T - 1, s)[lane] : R(0);
-    R ur = lane < M ? Q::up(w, buf, T - 1, s)[lane] : R(0);
-    for (int k = T - 1; k >= 0; --k) {
-      if (lane < N) ws.x[lane] = xr;
-      if (lane < M) ws.u[lane] = ur;
-      if (k > 0) {
-        if (lane < N) xr = Q::xp(w, buf, k - 1, s)[lane];
-        if (lane < M) ur = Q::up(w, buf, k - 1, s)[lane];
-      }
-      wave_sync();
-      if (Vo) {
-        const double c = double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
-        if (lane == 0) Vo[k] = c;
-      }
-      if (!Lo) continue;
-      wave_dyn(sm, ws, dt, lane);
-      // nu = M^-1 mu: L z = mu, then L^T nu = z (rows on lanes)
-      R y = row ? sm.p[NQ + ri] + dt * (sm.p[ri] + sm.e[ri] * sm.p[NV]) : R(0);
-#pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const R yj = bcast(y, j) * ws.Li[j];
-        if (lane == j) y = yj;
-        else if (lane > j) y -= ws.L[ri][j] * yj;
-      }
-#pragma unroll
-      for (int j = NV - 1; j >= 0; --j) {
-        const R zj = bcast(y, j) * ws.Li[j];
-        if (lane == j) y = zj;
-        else if (lane < j) y -= ws.L[j][ri] * zj;
-      }
-      if (row) ws.dx[ri] = y;
-      wave_sync();
-      R ln = R(0);
-      if (lane < N) {
-        ln = R(2) * (lane < NQ ? wq : wv) * (ws.x[lane] - sm.xnom[lane]);
-        if (lane < NV) {
-          R g1 = R(0), g2 = R(0);
-#pragma unroll 6
-          for (int i = 0; i < NV; ++i) {
-            g1 += sm.W1[i][lane] * ws.dx[i];
-            g2 += sm.W2[i][lane] * (ws.dx[i] * ws.x[NQ + i]);
+    for (int kc = T - 1; kc >= 0; kc -= NW) {
+      {
+        const int k = kc - wid;
+        WaveScratch<R>& ws = sm.wv[wid];
+        if (k >= 0) {
+          if (lane < N) ws.x[lane] = Q::xp(w, buf, k, s)[lane];
+          if (lane < M) ws.u[lane] = Q::up(w, buf, k, s)[lane];
+          wave_sync();
+          if (Vo) {
+            const double c = double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
+            if (lane == 0) Vo[k] = c;
           }
-          const R gq = -ws.c[lane] * g1 + ws.s[lane] * g2 - R(0.1) * ws.c[lane] * ws.a[lane] * ws.dx[lane];
-          ln += sm.p[lane] + dt * gq;
-        } else if (lane == NV) {
-          ln += sm.p[NV];
-        } else {
-          const int i = lane - NQ;
-          const R mu = sm.p[lane] + dt * (sm.p[i] + sm.e[i] * sm.p[NV]);
-          ln += mu - dt * ws.w2c[i] * ws.dx[i];
+          if (Lo) wave_dyn(sm, ws, dt, lane);
         }
       }
-      wave_sync();  // every read of lambda_{k+1} is done before it is replaced
-      if (lane < N) {
-        sm.p[lane] = ln;
-        Lo[size_t(k) * N + lane] = double(ln);
+      __syncthreads();
+      if (Lo && wid == 0) {
+        for (int q = 0; q < NW && kc - q >= 0; ++q) {
+          const int k = kc - q;
+          WaveScratch<R>& ws = sm.wv[q];
+          // nu = M^-1 mu: L z = mu, then L^T nu = z (rows on lanes)
+          R y = row ? sm.p[NQ + ri] + dt * (sm.p[ri] + sm.e[ri] * sm.p[NV]) : R(0);
+#pragma unroll
+          for (int j = 0; j < NV; ++j) {
+            const R yj = bcast(y, j) * ws.Li[j];
+            if (lane == j) y = yj;
+            else if (lane > j) y -= ws.L[ri][j] * yj;
+          }
+#pragma unroll
+          for (int j = NV - 1; j >= 0; --j) {
+            const R zj = bcast(y, j) * ws.Li[j];
+            if (lane == j) y = zj;
+            else if (lane < j) y -= ws.L[j][ri] * zj;
+          }
+          if (row) ws.dx[ri] = y;
+          wave_sync();
+          R ln = R(0);
+          if (lane < N) {
+            ln = R(2) * (lane < NQ ? wq : wv) * (ws.x[lane] - sm.xnom[lane]);
+            if (lane < NV) {
+              R g1 = R(0), g2 = R(0);
+#pragma unroll 6
+              for (int i = 0; i < NV; ++i) {
+                g1 += sm.W1[i][lane] * ws.dx[i];
+                g2 += sm.W2[i][lane] * (ws.dx[i] * ws.x[NQ + i]);
+              }
+              const R gq = -ws.c[lane] * g1 + ws.s[lane] * g2 - R(0.1) * ws.c[lane] * ws.a[lane] * ws.dx[lane];
+              ln += sm.p[lane] + dt * gq;
+            } else if (lane == NV) {
+              ln += sm.p[NV];
+            } else {
+              const int i = lane - NQ;
+              const R mu = sm.p[lane] + dt * (sm.p[i] + sm.e[i] * sm.p[NV]);
+              ln += mu - dt * ws.w2c[i] * ws.dx[i];
+            }
+          }
+          wave_sync();  // every read of lambda_{k+1} is done before it is replaced
+          if (lane < N) {
+            sm.p[lane] = ln;
+            Lo[size_t(k) * N + lane] = double(ln);
+          }
+          wave_sync();
+        }
       }
-      wave_sync();
+      __syncthreads();
     }
   }
   __syncthreads();
