@@ -362,10 +362,61 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
     if (row)
 #pragma unroll
       for (int j = 0; j < M; ++j) sm.Lq[ri][j] = m[j];
+    if constexpr (sizeof(R) == 4) {
+      // mixed form: the factor rounded to FP32 for the gain solves, in the
+      // storage of Q_uu (read above, not needed again)
+      float* lf = reinterpret_cast<float*>(&sm.Quu[0][0]);
+      if (row)
+#pragma unroll
+        for (int j = 0; j < M; ++j) lf[ri * (M + 1) + j] = float(m[j]);
+      wave_sync();  // the reciprocal pivots were stored by lane 0
+      if (lane < M) lf[M * (M + 1) + lane] = float(sm.Lqi[lane]);
+    }
     if (lane == 0) sm.flag = ok ? 0 : 1;
   }
   __syncthreads();
   if (sm.flag) return false;
+  if constexpr (sizeof(R) == 4) {
+    // mixed form: the gains are stored in FP32, so their triangular solves run
+    // in FP32 on the FP64 factor rounded to FP32 (as in the lane kernels)
+    if (tid <= N) {
+      const float* lf = reinterpret_cast<const float*>(&sm.Quu[0][0]);
+      const float* lfi = lf + M * (M + 1);
+      float y[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) y[i] = tid < N ? sm.Qux[i][tid] : sm.Qu[i];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        float v0 = y[i], v1 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < i; ++k) {
+          if (k & 1) v1 += lf[i * (M + 1) + k] * y[k];
+          else v0 -= lf[i * (M + 1) + k] * y[k];
+        }
+        y[i] = (v0 - v1) * lfi[i];
+      }
+#pragma unroll
+      for (int i = M - 1; i >= 0; --i) {
+        float v0 = y[i], v1 = 0.0f;
+#pragma unroll
+        for (int k = i + 1; k < M; ++k) {
+          if (k & 1) v1 += lf[k * (M + 1) + i] * y[k];
+          else v0 -= lf[k * (M + 1) + i] * y[k];
+        }
+        y[i] = (v0 - v1) * lfi[i];
+      }
+      bool fin = true;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        fin = fin && isfinite(y[i]);
+        if (tid < N) sm.Kg[i][tid] = R(-y[i]);
+        else sm.kk[i] = R(-y[i]);
+      }
+      if (!fin) sm.flag = 2;
+    }
+    __syncthreads();
+    return sm.flag == 0;
+  }
   if (tid <= N) {  // column tid of [Q_ux | Q_u]; the column lives in registers
     double y[M];
 #pragma unroll
