@@ -604,19 +604,42 @@ __device__ __forceinline__ double wave_trial(Smem<R>& sm, const double* __restri
   wave_sync();
   double Jh = 0.0;
   steps = T;
+  // the iterate's step data (x_k; lane (c, part): entries part, part + 4, ...
+  // of row c of K_k; u_k and k_k for c) are loaded one step ahead of their use
+  constexpr int KQ = (N + 3) / 4;
+  const int c = lane >> 2, part = lane & 3;
+  R xq = R(0), uq = R(0), kq = R(0), Kq[KQ];
+  auto load = [&](int k) {
+    if (lane < N) xq = Q::xp(w, buf, k, s)[lane];
+    if (c < M) {
+      const R* Kr = Q::Kp(w, k, s) + c * N;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) Kq[q] = part + 4 * q < N ? Kr[part + 4 * q] : R(0);
+      if (part == 0) {
+        uq = Q::up(w, buf, k, s)[c];
+        kq = Q::kp(w, k, s)[c];
+      }
+    }
+  };
+  load(0);
   for (int k = 0; k < T; ++k) {
-    if (lane < N) ws.dx[lane] = ws.x[lane] - Q::xp(w, buf, k, s)[lane];
+    const R xk = xq, uk = uq, kk = kq;
+    R Kc[KQ];
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) Kc[q] = Kq[q];
+    if (k + 1 < T) load(k + 1);
+    if (lane < N) ws.dx[lane] = ws.x[lane] - xk;
     wave_sync();
     {
-      const int c = lane >> 2, part = lane & 3;
       R acc = R(0);
       if (c < M) {
-        const R* Kr = Q::Kp(w, k, s) + c * N;
-        for (int j = part; j < N; j += 4) acc += Kr[j] * ws.dx[j];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q)
+          if (part + 4 * q < N) acc += Kc[q] * ws.dx[part + 4 * q];
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
-      if (c < M && part == 0) ws.u[c] = Q::up(w, buf, k, s)[c] + alpha * Q::kp(w, k, s)[c] + acc;
+      if (c < M && part == 0) ws.u[c] = uk + alpha * kk + acc;
     }
     wave_sync();
     Jh += double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
