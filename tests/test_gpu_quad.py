@@ -70,3 +70,69 @@ def test_quad_1k_sampled(ctx):
     compare(g, r, idx=idx, label="quad1k")
     _check_targets(g, kind, p, x0, T, idx[:3])
     assert np.all(np.isfinite(g["J"]))
+
+
+def test_quad_edge_cases(ctx):
+    p = I.quad_params(0)
+    x0 = I.quad_x0(5, p, seed=3)
+    x0[2, 1] = np.nan
+    # one instance, horizon 1, both forms
+    r = orc.solve_batch(QUAD, p, x0[:1], 1, opts=oracle_opts())
+    compare(gpu_solve(ctx, QUAD, p, x0[:1], 1), r, label="quad T=1")
+    gm = gpu_solve(ctx, QUAD, p, x0[:1], 1, precision=1)
+    assert rel(gm["J"], r.J).max() <= 1e-4
+    # NaN initial state: frozen NONFINITE, the others unaffected
+    g = gpu_solve(ctx, QUAD, p, x0, 20)
+    r = orc.solve_batch(QUAD, p, x0, 20, opts=oracle_opts())
+    assert g["status"][2] == orc.ST_NONFINITE and g["iters"][2] == 0
+    ok = [0, 1, 3, 4]
+    assert np.all(rel(g["J"][ok], r.J[ok]) <= 1e-9)
+    # no line-search trials: LS_FAILED at once, the zero warm start returned
+    g = gpu_solve(ctx, QUAD, p, x0[:2], 20, ls_max_trials=0)
+    assert np.all(g["status"] == orc.ST_LS_FAILED) and np.all(g["U"] == 0)
+    # zero budget
+    g = gpu_solve(ctx, QUAD, p, x0[:2], 20, max_iter=0)
+    assert np.all(g["status"] == orc.ST_MAX_ITER) and np.all(g["iters"] == 0)
+    # horizons outside 1..T_max are flagged and never indexed
+    g = gpu_solve(ctx, QUAD, p, x0[[0, 1, 3]], 20, T=np.array([5, 0, 21], np.int32))
+    assert g["status"][1] == 32 and g["status"][2] == 32
+    assert np.isnan(g["J"][1]) and np.isnan(g["J"][2])
+    assert np.all(g["X"][1:] == 0) and np.all(g["U"][1:] == 0)
+    r = orc.solve_batch(QUAD, p, x0[:1], 20, T=np.array([5], np.int32), opts=oracle_opts())
+    compare(g, r, idx=[0], label="quad T=5 beside bad horizons")
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_quad_cholesky_failure_keeps_warm_start(ctx, prec):
+    # zero cost weights and a zero clipping floor make Q_uu = 0 at the sweep's
+    # first step: the instance is frozen with its warm start and CHOL_FAIL, as
+    # in the oracle
+    B, T = 3, 20
+    p = I.quad_params(0, w_u=0.0, w_T=0.0, w_q=0.0, w_v=0.0)
+    x0 = I.quad_x0(B, p, seed=4)
+    U0 = np.random.default_rng(2).normal(size=(B, T, 12)) * 0.1
+    r = orc.solve_batch(QUAD, p, x0, T, U0=U0, opts=oracle_opts(psd_eps=0.0))
+    assert np.all(r.status == orc.ST_CHOL_FAIL) and np.all(r.iters == 0)
+    g = gpu_solve(ctx, QUAD, p, x0, T, U0=U0, psd_eps=0.0, precision=prec)
+    assert np.all(g["status"] == orc.ST_CHOL_FAIL) and np.all(g["iters"] == 0)
+    Uw = U0 if prec == 0 else U0.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(g["U"], Uw)
+
+
+def test_quad_chunk_boundaries(ctx):
+    # the sweep evaluates derivative blocks 16 steps at a time and the finalize
+    # four: horizons on either side of those boundaries, in one ragged batch
+    p = I.quad_params(1)
+    T = np.array([15, 16, 17, 32, 33, 3, 4, 5], np.int32)
+    x0 = I.quad_x0(len(T), p, seed=9)
+    g = gpu_solve(ctx, QUAD, p, x0, 33, T=T)
+    r = orc.solve_batch(QUAD, p, x0, 33, T=T, opts=oracle_opts())
+    compare(g, r, label="quad chunk boundaries")
+    for b in range(len(T)):
+        Tb = int(T[b])
+        Vb, Vx, xK = orc.extract(QUAD, p, g["X"][b, :Tb + 1], g["U"][b, :Tb])
+        assert np.abs(g["Vbar"][b, :Tb + 1] - Vb).max() <= 1e-11 * np.abs(Vb).max()
+        assert np.abs(g["Vx"][b, :Tb + 1] - Vx).max() <= 1e-9 * (np.abs(Vx).max() + 1e-300)
+        assert np.all(g["X"][b, Tb + 1:] == 0) and np.all(g["U"][b, Tb:] == 0)
+    gm = gpu_solve(ctx, QUAD, p, x0, 33, T=T, precision=1, stop_mode=1, rtol=1e-7)
+    assert rel(gm["J"], r.J).max() <= 1e-4
