@@ -48,6 +48,7 @@ struct WaveScratch {
 
 template <class R>
 struct Smem {
+  using real = R;
   R M0[NV][NV + 1];
   R W1[NV][NV + 1];
   R W2[NV][NV + 1];
@@ -69,6 +70,21 @@ struct Smem {
   int wok[NW];
   int flag;
   WaveScratch<R> wv[NW];
+};
+
+// Shared memory of the kernels that need only the constants, one vector and
+// the scratch of NWV waves (the initial rollout, the finalize): small enough
+// for every instance of a CU's share of the batch to be resident at once
+template <class R, int NWV>
+struct WaveSmem {
+  using real = R;
+  R M0[NV][NV + 1];
+  R W1[NV][NV + 1];
+  R W2[NV][NV + 1];
+  R e[NV];
+  R xnom[LD];
+  R p[LD];  // the finalize's costate
+  WaveScratch<R> wv[NWV];
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -109,9 +125,10 @@ __device__ __forceinline__ R wave_sum(R v) {
 }
 
 // ------------------------------------------------------------------ constants
-template <class R>
-__device__ __forceinline__ void stage_constants(Smem<R>& sm, const double* __restrict__ prm, int tid) {
-  for (int i = tid; i < NV * NV; i += NT) {
+template <class S>
+__device__ __forceinline__ void stage_constants(S& sm, const double* __restrict__ prm, int tid, int nt = NT) {
+  using R = typename S::real;
+  for (int i = tid; i < NV * NV; i += nt) {
     const int r = i / NV, c = i % NV;
     sm.M0[r][c] = R(prm[O_M0 + i]);
     sm.W1[r][c] = R(prm[O_W1 + i]);
@@ -124,8 +141,8 @@ __device__ __forceinline__ void stage_constants(Smem<R>& sm, const double* __res
 // ------------------------------------------------------------------ wave-level dynamics
 // One semi-implicit Euler step for wave scratch ws: reads ws.x and ws.u,
 // writes ws.xn; leaves L (factor of M), a, sin/cos and W2 cos q in ws.
-template <class R>
-__device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, R dt, int lane) {
+template <class R, class S>
+__device__ __forceinline__ void wave_dyn(const S& sm, WaveScratch<R>& ws, R dt, int lane) {
   if (lane < NV) {
     R sn, cs;
     dsincos_lib(ws.x[lane], &sn, &cs);
@@ -203,8 +220,8 @@ __device__ __forceinline__ void wave_dyn(const Smem<R>& sm, WaveScratch<R>& ws, 
 }
 
 // running cost l(x, u) of the wave's (x, u); the same value in every lane
-template <class R>
-__device__ __forceinline__ R wave_cost(const Smem<R>& sm, const R* x, const R* u, const double* __restrict__ prm, int lane,
+template <class R, class S>
+__device__ __forceinline__ R wave_cost(const S& sm, const R* x, const R* u, const double* __restrict__ prm, int lane,
                        bool terminal) {
   R v = R(0);
   if (lane < N) {
@@ -660,14 +677,15 @@ __device__ __forceinline__ double wave_trial(Smem<R>& sm, const double* __restri
 }
 
 // ------------------------------------------------------------------ kernels
+// Initial rollout: one wave per instance, a serial chain of T dynamics steps
 template <class R>
-__global__ void __launch_bounds__(NT) quad_init(const double* __restrict__ prm, LaneState<R> w, int nthreads,
+__global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, LaneState<R> w, int nthreads,
                                                  const int32_t* __restrict__ slots, int Tmax,
                                                  const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
                                                  const double* __restrict__ x0, const double* __restrict__ U0,
                                                  int max_iter, double* __restrict__ trace) {
   using Q = QW<R>;
-  __shared__ Smem<R> sm;
+  __shared__ WaveSmem<R, 1> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
   if (g >= nthreads) return;
   const int s = slots ? slots[g] : g;
@@ -675,9 +693,8 @@ __global__ void __launch_bounds__(NT) quad_init(const double* __restrict__ prm, 
   const int Tr = Tin ? Tin[b] : Tmax;
   const bool badT = Tr < 1 || Tr > Tmax || Tr > w.Tcap;
   const int T = badT ? 0 : Tr;
-  stage_constants(sm, prm, tid);
+  stage_constants(sm, prm, tid, 64);
   __syncthreads();
-  if (tid >= 64) return;
   const int lane = tid;
   WaveScratch<R>& ws = sm.wv[0];
   const R dt = R(prm[O_DT]);
@@ -837,7 +854,7 @@ __global__ void __launch_bounds__(NT, 2) quad_final(const double* __restrict__ p
                                                   const int32_t* __restrict__ slots, int Tmax, int max_iter,
                                                   int lookahead, FinalOut o, R* __restrict__ dblk) {
   using Q = QW<R>;
-  __shared__ Smem<R> sm;
+  __shared__ WaveSmem<R, NW> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
   if (g >= nslots) return;
   const int s = slots ? slots[g] : g;
@@ -1027,7 +1044,8 @@ struct QuadLaunch {
                          hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
-    hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,
+    // one wave per instance (quad_init is built for 64-thread workgroups)
+    hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(64), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,
                        x0, U0, max_iter, trace);
     return hipGetLastError();
   }
