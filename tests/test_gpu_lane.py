@@ -90,6 +90,24 @@ def test_point_mass_16k_sampled_fp64(ctx):
     assert np.all((g["status"] & (orc.ST_NONFINITE | orc.ST_CHOL_FAIL)) == 0)
 
 
+def test_point_mass_16k_headline_form(ctx):
+    # the timed configuration: all 16384 instances, mixed form, relative-decrease
+    # stop at 1e-4, default launch options; every instance ended by its stop
+    # rule within 1e-4 of the FP64 oracle's cost, and a second solve bitwise
+    # identical
+    kind, p, x0, T, _ = I.workload("pm16k")
+    opts = dict(precision=1, stop_mode=1, rtol=1e-4)
+    g = gpu_solve(ctx, kind, p, x0, T, **opts)
+    r = orc.solve_batch(kind, p, x0, T, opts=oracle_opts())
+    e = rel(g["J"], r.J)
+    print(f"pm16k headline form: max rel {e.max():.2e}, median {np.median(e):.2e}")
+    assert e.max() <= 1e-4
+    assert np.all((g["status"] & (orc.ST_NONFINITE | orc.ST_CHOL_FAIL | orc.ST_MAX_ITER)) == 0)
+    g2 = gpu_solve(ctx, kind, p, x0, T, **opts)
+    for f in ("J", "X", "U", "iters", "status", "Vbar", "Vx"):
+        np.testing.assert_array_equal(g[f], g2[f], err_msg=f)
+
+
 def test_point_mass_mixed_precision(ctx):
     kind, p, x0, T, _ = I.workload("pm64")
     g = gpu_solve(ctx, kind, p, x0, T, precision=1)

@@ -72,6 +72,20 @@ def test_quad_1k_sampled(ctx):
     assert np.all(np.isfinite(g["J"]))
 
 
+def test_quad_1k_headline_form(ctx):
+    # the timed configuration of the quadruped: 1024 instances, mixed form,
+    # relative-decrease stop at 1e-4; sampled against the FP64 oracle at the
+    # 1e-4 cost bar, every instance ended by its stop rule
+    kind, p, x0, T, _ = I.workload("quad1k")
+    g = gpu_solve(ctx, kind, p, x0, T, precision=1, stop_mode=1, rtol=1e-4)
+    idx = np.r_[np.random.default_rng(5).choice(len(x0), 24, replace=False), 0, len(x0) - 1]
+    r = orc.solve_batch(kind, p, x0[idx], T, opts=oracle_opts())
+    e = rel(g["J"][idx], r.J)
+    print(f"quad1k headline form: max rel {e.max():.2e}")
+    assert e.max() <= 1e-4
+    assert np.all((g["status"] & (orc.ST_NONFINITE | orc.ST_CHOL_FAIL | orc.ST_MAX_ITER)) == 0)
+
+
 def test_quad_edge_cases(ctx):
     p = I.quad_params(0)
     x0 = I.quad_x0(5, p, seed=3)
