@@ -61,8 +61,8 @@ struct Smem {
   R PB[N][LDB]; // P f_u
   R Kg[M][LD];  // feedback gain (m x n)
   R Qux[M][LD];
-  R p[LD], Qx[LD], lx[LD];
-  R Qu[16], kk[16], lu[16];
+  R p[LD], Qx[LD];
+  R Qu[16], kk[16];
   double Quu[M][M + 1];
   double Lq[M][M + 1];
   double Lqi[M];  // reciprocals of the diagonal of Lq
@@ -534,9 +534,6 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       }
     }
     __syncthreads();
-    // cost derivatives (diagonal Hessians)
-    if (tid < N) sm.lx[tid] = R(2) * (tid < NQ ? wq : wv) * (w0.x[tid] - sm.xnom[tid]);
-    if (tid < M) sm.lu[tid] = R(2) * wu * w0.u[tid];
     // PA = P A, PB = P B
     // nine 16 x 16 tiles of P A and three of P B over the four waves
     for (int t = tid >> 6; t < 12; t += NW) {
@@ -547,20 +544,24 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
         mfma_tile<N, false, false>(&sm.PB[0][0], LDB, &sm.P[0][0], LD, &sm.Bm[0][0], LDB, (const R*)nullptr, 0, N, M,
                                    (t - 9) * 16, 0, tid & 63);
     }
-    __syncthreads();
-    // Q_x = l_x + A^T p, Q_u = l_u + B^T p (before P is overwritten)
-    if (tid < N + M) {
-      R v;
-      if (tid < N) {
-        v = sm.lx[tid];
-        for (int t = 0; t < N; ++t) v += sm.A[t][tid] * sm.p[t];
-      } else {
-        const int c = tid - N;
-        v = sm.lu[c];
-        for (int t = 0; t < N; ++t) v += sm.Bm[t][c] * sm.p[t];
+    // in the same phase, on the last wave: Q_x = l_x + A^T p, Q_u = l_u + B^T p
+    // (p is replaced only after the gains), with the cost gradients (diagonal
+    // Hessians) formed in registers
+    {
+      const int r = tid - (NW - 1) * 64;
+      if (r >= 0 && r < N + M) {
+        R v;
+        if (r < N) {
+          v = R(2) * (r < NQ ? wq : wv) * (w0.x[r] - sm.xnom[r]);
+          for (int t = 0; t < N; ++t) v += sm.A[t][r] * sm.p[t];
+        } else {
+          const int c = r - N;
+          v = R(2) * wu * w0.u[c];
+          for (int t = 0; t < N; ++t) v += sm.Bm[t][c] * sm.p[t];
+        }
+        if (r < N) sm.Qx[r] = v;
+        else sm.Qu[r - N] = v;
       }
-      if (tid < N) sm.Qx[tid] = v;
-      else sm.Qu[tid - N] = v;
     }
     __syncthreads();
     // Q_xx = clip(l_xx) + A^T (P A) into P; Q_uu = clip(l_uu) + B^T (P B); Q_ux = B^T (P A)
