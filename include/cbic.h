@@ -14,7 +14,8 @@
  * fixed iteration budget shared by the whole batch (Sec. IV-A), and at the end
  * the critic targets of Sec. II: the K-step partial cost-to-go V-bar of every
  * state, its gradient V-bar_x from the backward (costate) pass, and the state
- * K steps later.  The control bound |u| <= u_max of eq. 1 is not supported.
+ * K steps later.  The control bound |u| <= u_max of eq. 1 is an option
+ * (cbic_solve_opts.u_max, unbounded by default).
  *
  * Conventions for every call
  *  - Return value: CBIC_OK (0) on success, CBIC_NOT_READY (1) for a pending
@@ -164,7 +165,11 @@ typedef struct {
  * Vx[B][T_max+1][n], xK[B][T_max+1][n], cost_trace[B][max_iter+1] (J after each
  * accepted iteration, then repeated), work[B][4] (int32: backward sweeps,
  * line-search rollout passes, rollout steps read, rollout steps written -- the
- * traffic that instance caused; lanes sharing an instance share its reads). */
+ * traffic that instance caused; lanes sharing an instance share its reads),
+ * jtrace[B][max_iter] (int32: for each iteration the accepted line-search
+ * index j, alpha = ls_beta^j; -1 for the iteration in which the instance was
+ * frozen by a failure (no accepted step, Cholesky failure, non-finite gains);
+ * -2 for iterations not run). */
 typedef struct {
   double* X;
   double* U;
@@ -176,6 +181,7 @@ typedef struct {
   double* xK;
   double* cost_trace;
   int32_t* work;
+  int32_t* jtrace;
 } cbic_outputs;
 
 /* Last error message of the calling thread ("" if none). */

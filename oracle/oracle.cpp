@@ -834,7 +834,17 @@ struct Opts {
   double mu0, mu_factor, mu_max;
   // control bound |u_k,i| <= umax (eq. 1); infinite: none
   double umax;
+  // sensitivity probe, off by default: 1 rounds every quantity that the
+  // mixed-precision form keeps in FP32 to FP32 where it is produced (see
+  // solve_one); the arithmetic itself stays FP64
+  int32_t round32;
 };
+
+// v rounded to FP32 and back when `on`
+inline void to_f32(double* v, int len, bool on) {
+  if (on)
+    for (int i = 0; i < len; ++i) v[i] = (double)(float)v[i];
+}
 
 // the symmetric part of H (no clipping)
 void sym_part(int n, const double* H, double* out) {
@@ -849,13 +859,14 @@ bool all_finite(const double* v, int k) {
 }
 
 // J = sum_{k<T} l(x_k,u_k) + l_T(x_T), summed in index order; X = rollout of U.
-double rollout(const Sys& s, int T, const double* x0, const double* U, double* X) {
+double rollout(const Sys& s, int T, const double* x0, const double* U, double* X, bool r32 = false) {
   const int n = s.n, m = s.m;
   for (int i = 0; i < n; ++i) X[i] = x0[i];
   double J = 0.0;
   for (int k = 0; k < T; ++k) {
     J += cost<double>(s, X + k * n, U + k * m);
     dyn<double>(s, X + k * n, U + k * m, X + (k + 1) * n);
+    to_f32(X + (k + 1) * n, n, r32);
   }
   J += term<double>(s, X + T * n);
   return J;
@@ -928,7 +939,7 @@ struct Out {
   const int32_t* force_j;  // max_iter or null: replay these accepted j (-1 = none)
 };
 
-void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Opts& o, Out r) {
+void solve_one(const Sys& s, int T, const double* x0_in, const double* U0, const Opts& o, Out r) {
   const int n = s.n, m = s.m;
   std::vector<double> X((T + 1) * n), U(T * m, 0.0), Xn((T + 1) * n), Un(T * m);
   std::vector<double> Kg(T * m * n), kf(T * m);
@@ -938,7 +949,15 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
   auto clamp_u = [&](double v) { return v < -o.umax ? -o.umax : (v > o.umax ? o.umax : v); };
   if (bounded)
     for (auto& v : U) v = clamp_u(v);
-  double J = rollout(s, T, x0, U.data(), X.data());
+  // the FP32-storage probe (round32): the initial state, the warm start, every
+  // rolled-out state and control, the derivative blocks, the clipped Hessians,
+  // P and p after each backward step and the gains are rounded to FP32
+  const bool r32 = o.round32 != 0;
+  std::vector<double> x0v(x0_in, x0_in + n);
+  to_f32(x0v.data(), n, r32);
+  to_f32(U.data(), T * m, r32);
+  const double* x0 = x0v.data();
+  double J = rollout(s, T, x0, U.data(), X.data(), r32);
   uint32_t status = 0;
   int iters = 0;
   bool frozen = false;
@@ -967,11 +986,17 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
     term_derivs(s, X.data() + T * n, p.data(), lxx.data());
     if (lm) sym_part(n, lxx.data(), P.data());
     else psd_clip(n, lxx.data(), o.eps, P.data());
+    to_f32(p.data(), n, r32);
+    to_f32(P.data(), n * n, r32);
     for (int k = T - 1; k >= 0; --k) {
       const double* xk = X.data() + k * n;
       const double* uk = U.data() + k * m;
       dyn_jac(s, xk, uk, A.data(), B.data());
       cost_derivs(s, xk, uk, lx.data(), lu.data(), lxx.data(), luu.data(), lux.data());
+      to_f32(A.data(), n * n, r32);
+      to_f32(B.data(), n * m, r32);
+      to_f32(lx.data(), n, r32);
+      to_f32(lu.data(), m, r32);
       if (lm) {
         sym_part(n, lxx.data(), Qc.data());
         sym_part(m, luu.data(), Rc.data());
@@ -979,6 +1004,8 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
         psd_clip(n, lxx.data(), o.eps, Qc.data());
         psd_clip(m, luu.data(), o.eps, Rc.data());
       }
+      to_f32(Qc.data(), n * n, r32);
+      to_f32(Rc.data(), m * m, r32);
       // PA = P A, PB = P B
       for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j) {
@@ -1069,6 +1096,10 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
       }
       for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) P[i * n + j] = 0.5 * (PA[i * n + j] + PA[j * n + i]);
+      to_f32(Kk, m * n, r32);
+      to_f32(kk, m, r32);
+      to_f32(p.data(), n, r32);
+      to_f32(P.data(), n * n, r32);
     }
     return 0u;
   };
@@ -1096,8 +1127,10 @@ void solve_one(const Sys& s, int T, const double* x0, const double* U0, const Op
           for (int t = 0; t < n; ++t) v += Kk[i * n + t] * (Xn[k * n + t] - X[k * n + t]);
           Un[k * m + i] = bounded ? clamp_u(v) : v;
         }
+        to_f32(Un.data() + k * m, m, r32);
         Jh += cost<double>(s, Xn.data() + k * n, Un.data() + k * m);
         dyn<double>(s, Xn.data() + k * n, Un.data() + k * m, Xn.data() + (k + 1) * n);
+        to_f32(Xn.data() + (k + 1) * n, n, r32);
       }
       Jh += term<double>(s, Xn.data() + T * n);
       if (std::isfinite(Jh)) margin = std::min(margin, std::fabs(Jh - J) / std::max(std::fabs(J), 1e-300));
@@ -1187,6 +1220,7 @@ struct orc_opts {
   int32_t reg;
   double mu0, mu_factor, mu_max;
   double umax;
+  int32_t round32;
 };
 
 const char* orc_last_error() { return g_err; }
@@ -1413,7 +1447,7 @@ int orc_solve_batch(int kind, const double* p, int np, int B, int Tmax, const in
   }
   const int n = s.n, m = s.m;
   Opts o{opt->max_iter, opt->ls_trials, opt->stop_mode, opt->lookahead, opt->eps, opt->beta, opt->rtol,
-         opt->reg, opt->mu0, opt->mu_factor, opt->mu_max, opt->umax};
+         opt->reg, opt->mu0, opt->mu_factor, opt->mu_max, opt->umax, opt->round32};
   const size_t sx = (size_t)(Tmax + 1) * n, su = (size_t)Tmax * m;
   std::memset(X, 0, sizeof(double) * sx * B);
   std::memset(U, 0, sizeof(double) * su * B);

@@ -35,7 +35,7 @@ class _Opts(C.Structure):
                 ("stop_mode", C.c_int32), ("lookahead", C.c_int32),
                 ("eps", C.c_double), ("beta", C.c_double), ("rtol", C.c_double),
                 ("reg", C.c_int32), ("mu0", C.c_double), ("mu_factor", C.c_double),
-                ("mu_max", C.c_double), ("umax", C.c_double)]
+                ("mu_max", C.c_double), ("umax", C.c_double), ("round32", C.c_int32)]
 
 
 _lib = None
@@ -75,11 +75,15 @@ class Options:
     mu_max: float = 1e10
     # control bound |u_k,i| <= umax of eq. 1 (infinite: unbounded)
     umax: float = float("inf")
+    # sensitivity probe for the mixed-precision form, off by default: round
+    # what that form keeps in FP32 (states, controls, derivative blocks,
+    # clipped Hessians, P and p, gains) to FP32 where it is produced
+    round32: int = 0
 
     def c(self):
         return _Opts(self.max_iter, self.ls_trials, self.stop_mode, self.lookahead,
                      self.eps, self.beta, self.rtol, self.reg, self.mu0, self.mu_factor,
-                     self.mu_max, self.umax)
+                     self.mu_max, self.umax, self.round32)
 
 
 def dims(kind, params):

@@ -43,7 +43,7 @@ class _Opts(C.Structure):
 
 class _Outputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("X", "U", "J", "iters", "status", "Vbar", "Vx", "xK",
-                                            "cost_trace", "work")]
+                                            "cost_trace", "work", "jtrace")]
 
 
 class _ServerOpts(C.Structure):
@@ -231,6 +231,7 @@ class Outputs:
     xK: object = None
     cost_trace: object = None
     work: object = None
+    jtrace: object = None
 
     @staticmethod
     def allocate(B, T_max, n, m, device, targets=True, trace_iters=None, work=True):
@@ -244,7 +245,8 @@ class Outputs:
             Vx=torch.empty(B, T_max + 1, n, **f64) if targets else None,
             xK=torch.empty(B, T_max + 1, n, **f64) if targets else None,
             cost_trace=torch.empty(B, trace_iters + 1, **f64) if trace_iters is not None else None,
-            work=torch.empty(B, 4, **i32) if work else None)
+            work=torch.empty(B, 4, **i32) if work else None,
+            jtrace=torch.empty(B, max(trace_iters, 1), **i32) if trace_iters is not None else None)
 
     def c(self) -> _Outputs:
         o = _Outputs()

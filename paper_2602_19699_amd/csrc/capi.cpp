@@ -288,14 +288,16 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
     return CBIC_E_INVALID;
   }
   const void* ptrs[] = {d_T, d_x0, d_U0, out->X, out->U, out->J, out->iters, out->status,
-                        out->Vbar, out->Vx, out->xK, out->cost_trace, out->work};
+                        out->Vbar, out->Vx, out->xK, out->cost_trace, out->work, out->jtrace};
   for (const void* p : ptrs)
-    if (p && !aligned8(p) && p != d_T && p != out->iters && p != out->status && p != out->work) {
+    if (p && !aligned8(p) && p != d_T && p != out->iters && p != out->status && p != out->work &&
+        p != out->jtrace) {
       set_error("device pointers must be 8-byte aligned");
       return CBIC_E_INVALID;
     }
   if ((d_T && (reinterpret_cast<uintptr_t>(d_T) & 3u)) || (reinterpret_cast<uintptr_t>(out->iters) & 3u) ||
-      (reinterpret_cast<uintptr_t>(out->status) & 3u) || (out->work && (reinterpret_cast<uintptr_t>(out->work) & 3u))) {
+      (reinterpret_cast<uintptr_t>(out->status) & 3u) || (out->work && (reinterpret_cast<uintptr_t>(out->work) & 3u)) ||
+      (out->jtrace && (reinterpret_cast<uintptr_t>(out->jtrace) & 3u))) {
     set_error("int32 device pointers must be 4-byte aligned");
     return CBIC_E_INVALID;
   }
@@ -341,6 +343,10 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
 
   const bool timing = (opts->flags & CBIC_FLAG_TIMING) != 0;
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[0], stream));
+  // iterations that never run keep the marker -2
+  if (out->jtrace && opts->max_iter > 0)
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(out->jtrace), -2, size_t(B) * opts->max_iter, stream));
+  const IterTrace tr{out->cost_trace, out->jtrace};
   HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, sp.umax, stream));
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
@@ -355,21 +361,21 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
     const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
     if (!graph) {
       for (int c = 0; c < chunks; ++c)
-        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream));
+        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
     } else {
       char key[512];
       std::snprintf(key, sizeof key,
-                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%d|%.17g|%.17g|%.17g|%.17g",
+                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
                     (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
                     sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
-                    sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
+                    (void*)out->jtrace, sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
       auto it = ctx->graphs.find(key);
       if (it == ctx->graphs.end()) {
         cbic_context::GraphEntry ge;
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int c = 0; c < chunks && e == hipSuccess; ++c)
-          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, out->cost_trace, stream);
+          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {

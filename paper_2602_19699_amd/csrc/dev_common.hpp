@@ -20,20 +20,41 @@ enum : uint32_t {
   ST_BAD_INPUT = 32u,
 };
 
+// Optional per-iteration records of a solve, written by the iteration kernels
+// into the caller's arrays (indexed by instance).
+struct IterTrace {
+  double* J;   // [B][max_iter + 1]: cost after each accepted iteration, or null
+  int32_t* j;  // [B][max_iter]: accepted line-search index j (alpha = beta^j) of
+               // each iteration, -1 where the iteration failed, or null
+};
+
 // ---------------------------------------------------------------- math by precision
 // FP64 (the plain form) uses the correctly rounded library functions.  FP32
 // (the mixed form's rollouts and derivatives, device only) uses the hardware
-// exponential and sine/cosine: their error, a few ulp for exp and about 2^-20
-// absolute for sin/cos at the angles met here, stays far below the mixed
-// form's cost tolerance.
+// exponential (a few ulp) and the hardware sine/cosine after an additive
+// range reduction to [-pi, pi] (Cody and Waite's method: 2 pi split in two
+// FP32 parts, the multiple subtracted with fused multiply-adds), which keeps
+// the error near 2^-21 absolute whatever the angle; the hardware pair alone
+// scales its argument by 1/(2 pi) in FP32 and so loses |v| 2^-24 of absolute
+// accuracy, about 1e-4 at the joint angles a spinning arm reaches.  From
+// |v| = 2^23 on, an FP32 angle holds no fraction of a radian and its sine has
+// no meaning: the reduction returns NaN there, so that a rollout that spins
+// up that far is non-finite, as its FP64 counterpart (which overflows on the
+// way) is.
 CBIC_HD __forceinline__ double dexp(double v) { return exp(v); }
 __device__ __forceinline__ float dexp(float v) { return __expf(v); }
+__device__ __forceinline__ float reduce_2pi(float v) {
+  const float k = rintf(v * 0.159154943091895336f);  // nearest multiple of 2 pi
+  const float r = fmaf(-k, 6.28318548202514648f, v);  // 2 pi rounded to FP32
+  const float t = fmaf(-k, -1.74845553e-07f, r);      // 2 pi minus that rounding
+  return fabsf(v) < 8388608.0f ? t : __builtin_nanf("");
+}
 CBIC_HD __forceinline__ double dsin(double v) { return sin(v); }
-__device__ __forceinline__ float dsin(float v) { return __sinf(v); }
+__device__ __forceinline__ float dsin(float v) { return __sinf(reduce_2pi(v)); }
 CBIC_HD __forceinline__ double dcos(double v) { return cos(v); }
-__device__ __forceinline__ float dcos(float v) { return __cosf(v); }
+__device__ __forceinline__ float dcos(float v) { return __cosf(reduce_2pi(v)); }
 CBIC_HD __forceinline__ void dsincos(double v, double* s, double* c) { sincos(v, s, c); }
-__device__ __forceinline__ void dsincos(float v, float* s, float* c) { __sincosf(v, s, c); }
+__device__ __forceinline__ void dsincos(float v, float* s, float* c) { __sincosf(reduce_2pi(v), s, c); }
 // the library sine/cosine in both precisions (measured faster than the
 // hardware pair inside the quadruped's large kernel)
 CBIC_HD __forceinline__ void dsincos_lib(double v, double* s, double* c) { sincos(v, s, c); }

@@ -1022,8 +1022,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 template <class Sys, class R, int GL, bool BOX>
 __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
                                                    int nslots, const int32_t* __restrict__ slots,
-                                                   SolveParams sp, int iters_this_launch,
-                                                   double* __restrict__ trace) {
+                                                   SolveParams sp, int iters_this_launch, IterTrace tr) {
   using LN = Lane<Sys, R>;
   static_assert(GL >= 1 && GL <= 16 && (GL & (GL - 1)) == 0, "group width must be a power of two <= 16");
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1178,6 +1177,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
       }
       break;
     }
+    if (tr.j && lead) tr.j[size_t(b) * sp.max_iter + iters] = fail ? -1 : acc;
     if (fail) {
       st = fail;
       break;
@@ -1187,7 +1187,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
     const double Jold = J;
     J = Jn;
     ++iters;
-    if (trace && lead) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
+    if (tr.J && lead) tr.J[size_t(b) * (sp.max_iter + 1) + iters] = J;
     if (sp.stop_mode == 1 && (Jold - J) <= sp.rtol * fabs(Jold)) {
       st = ST_CONVERGED;
       break;

@@ -748,7 +748,7 @@ template <class R>
 // hides more of it than the spills cost (measured: FP32 -26 %, FP64 -7 %).
 __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                     const int32_t* __restrict__ slots, SolveParams sp,
-                                                    int iters_this_launch, double* __restrict__ trace,
+                                                    int iters_this_launch, IterTrace tr,
                                                     R* __restrict__ dblk) {
   __shared__ Smem<R> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
@@ -774,6 +774,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
     ++nsweep;
     const uint32_t bad = backward(sm, prm, w, s, T, buf, eps, tid, dblk + size_t(s) * CH * DB);
     if (bad) {
+      if (tr.j && tid == 0) tr.j[size_t(b) * sp.max_iter + iters] = -1;
       st = bad;
       break;
     }
@@ -823,6 +824,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
       if (acc == 0 || (acc < 0 && j0 >= sp.ls_trials)) break;
       if (acc > 0) commit = true;
     }
+    if (tr.j && tid == 0) tr.j[size_t(b) * sp.max_iter + iters] = acc;
     if (acc < 0) {
       st = ST_LS_FAILED;
       break;
@@ -831,7 +833,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
     const double Jold = J;
     J = Jn;
     ++iters;
-    if (trace && tid == 0) trace[size_t(b) * (sp.max_iter + 1) + iters] = J;
+    if (tr.J && tid == 0) tr.J[size_t(b) * (sp.max_iter + 1) + iters] = J;
     if (sp.stop_mode == 1 && (Jold - J) <= sp.rtol * fabs(Jold)) {
       st = ST_CONVERGED;
       break;
@@ -1052,12 +1054,12 @@ struct QuadLaunch {
   }
 
   static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
-                            const int32_t* slots, const SolveParamsH& sp, int G, int, double* trace,
+                            const int32_t* slots, const SolveParamsH& sp, int G, int, const IterTrace& tr,
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     hipLaunchKernelGGL(quad_iterate<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, to_dev(sp), G,
-                       trace, blocks(base, Bcap, Tcap));
+                       tr, blocks(base, Bcap, Tcap));
     return hipGetLastError();
   }
 

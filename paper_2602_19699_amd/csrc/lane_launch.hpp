@@ -82,29 +82,29 @@ struct LaneLaunch {
   // unbounded one keeps its register allocation
   template <int GL>
   static hipError_t iterate_g(const double* prm, const LaneState<R>& w, int nthreads, const int32_t* slots,
-                              const SolveParams& sp, int G, double* trace, hipStream_t st) {
+                              const SolveParams& sp, int G, const IterTrace& tr, hipStream_t st) {
     const long total = long(nthreads) * GL;
     if (__builtin_isfinite(sp.umax))
       hipLaunchKernelGGL((lane_iterate<Sys, R, GL, true>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                         nthreads, slots, sp, G, trace);
+                         nthreads, slots, sp, G, tr);
     else
       hipLaunchKernelGGL((lane_iterate<Sys, R, GL, false>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                         nthreads, slots, sp, G, trace);
+                         nthreads, slots, sp, G, tr);
     return hipGetLastError();
   }
 
   static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
-                            const int32_t* slots, const SolveParamsH& sp, int G, int group, double* trace,
+                            const int32_t* slots, const SolveParamsH& sp, int G, int group, const IterTrace& tr,
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
     const SolveParams d = to_dev(sp);
     switch (group) {
-      case 1: return iterate_g<1>(prm, w, nthreads, slots, d, G, trace, st);
-      case 2: return iterate_g<2>(prm, w, nthreads, slots, d, G, trace, st);
-      case 4: return iterate_g<4>(prm, w, nthreads, slots, d, G, trace, st);
-      case 8: return iterate_g<8>(prm, w, nthreads, slots, d, G, trace, st);
-      case 16: return iterate_g<16>(prm, w, nthreads, slots, d, G, trace, st);
+      case 1: return iterate_g<1>(prm, w, nthreads, slots, d, G, tr, st);
+      case 2: return iterate_g<2>(prm, w, nthreads, slots, d, G, tr, st);
+      case 4: return iterate_g<4>(prm, w, nthreads, slots, d, G, tr, st);
+      case 8: return iterate_g<8>(prm, w, nthreads, slots, d, G, tr, st);
+      case 16: return iterate_g<16>(prm, w, nthreads, slots, d, G, tr, st);
       default: return hipErrorInvalidValue;
     }
   }

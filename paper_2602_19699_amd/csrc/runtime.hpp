@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/cbic.h"
+#include "dev_common.hpp"
 
 namespace cbic {
 
@@ -70,7 +71,7 @@ struct Launcher {
                      int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
                      int max_iter, double* trace, double umax, hipStream_t st);
   hipError_t (*iterate)(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
-                        const SolveParamsH& sp, int G, int group, double* trace, hipStream_t st);
+                        const SolveParamsH& sp, int G, int group, const IterTrace& tr, hipStream_t st);
   hipError_t (*finalize)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
                          const int32_t* slots, int Tmax, int max_iter, int lookahead, const FinalOutH& o,
                          hipStream_t st);

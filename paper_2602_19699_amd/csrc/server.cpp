@@ -263,7 +263,7 @@ bool launch_iterations(cbic_server* srv, Pool* p) {
                   p->opts.psd_eps, p->opts.ls_beta, p->opts.rtol};
   const int group = p->opts.group_lanes > 0 ? p->opts.group_lanes : default_group(p->sys->kind, na, p->precision);
   SRV_TRY(p->L->iterate(p->sys->d_prm, p->ws, p->Bcap, p->Tcap, na, p->d_list, sp,
-                        std::max(1, srv->opts.iters_per_launch), group, nullptr, p->stream));
+                        std::max(1, srv->opts.iters_per_launch), group, IterTrace{nullptr, nullptr}, p->stream));
   const uint32_t* st = reinterpret_cast<const uint32_t*>(static_cast<char*>(p->ws) + p->lay.status);
   SRV_TRY(launch_gather_u32(st, p->d_list, na, p->d_statg, p->stream));
   SRV_TRY(hipMemcpyAsync(p->h_statg, p->d_statg, 4 * na, hipMemcpyDeviceToHost, p->stream));

@@ -7,7 +7,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2602_19699_amd import inputs as I
 
-from gpu_helpers import compare, compare_sensitivity_aware, gpu_solve, oracle_opts, oracle_with_sensitivity, rel
+from gpu_helpers import check_parity, compare, gpu_solve, oracle_ensemble, oracle_opts, rel
 from lq_dense import bounded_qp, dense_qp
 
 pytestmark = pytest.mark.gpu
@@ -34,8 +34,9 @@ def test_bounded_point_mass_fp64(ctx):
     kind, p, x0, T, _ = I.workload("pm64")
     for o in (dict(max_iter=50, u_max=10.0), dict(max_iter=200, stop_mode=1, rtol=1e-10, u_max=10.0)):
         g = gpu_solve(ctx, kind, p, x0, T, trace=True, **o)
-        r, rho = oracle_with_sensitivity(kind, p, x0, T, opts=oracle_opts(**o))
-        compare_sensitivity_aware(g, r, rho, min_well=0.8, label=f"pm64 bounded {o}")
+        oo = oracle_opts(**o)
+        r, rps = oracle_ensemble(kind, p, x0, T, opts=oo)
+        check_parity(g, kind, p, x0, T, None, oo, r, rps, label=f"pm64 bounded {o}")
         _feasible(g, 10.0)
         assert np.mean(np.any(np.abs(g["U"]) == 10.0, axis=(1, 2))) > 0.5  # the bound binds
         for b in range(64):
@@ -48,16 +49,18 @@ def test_bounded_point_mass_ragged_and_mixed(ctx):
     p = I.point_mass_params(1)
     x0 = I.point_mass_x0(B, 77)
     T = I.horizons(B, 1, 100, seed=5)
-    g = gpu_solve(ctx, PM, p, x0, 100, T=T, u_max=8.0)
-    r, rho = oracle_with_sensitivity(PM, p, x0, 100, T=T, opts=oracle_opts(u_max=8.0))
-    compare_sensitivity_aware(g, r, rho, min_well=0.8, label="pm-ragged bounded")
+    g = gpu_solve(ctx, PM, p, x0, 100, T=T, u_max=8.0, trace=True)
+    o = oracle_opts(u_max=8.0)
+    r, rps = oracle_ensemble(PM, p, x0, 100, T=T, opts=o)
+    check_parity(g, PM, p, x0, 100, T, o, r, rps, label="pm-ragged bounded")
     _feasible(g, 8.0)
     for b in range(B):
         assert np.all(g["X"][b, T[b] + 1:] == 0) and np.all(g["U"][b, T[b]:] == 0)
-    gm = gpu_solve(ctx, PM, p, x0, 100, T=T, precision=1, u_max=8.0)
-    e = rel(gm["J"], r.J)
-    print(f"pm-ragged bounded mixed: max rel {e.max():.2e}, within 1e-4: {(e <= 1e-4).mean():.3f}")
-    assert (e <= 1e-4).mean() >= 0.9 and np.all(np.isfinite(gm["J"]))
+    gm = gpu_solve(ctx, PM, p, x0, 100, T=T, precision=1, u_max=8.0, trace=True)
+    r32, rps32 = oracle_ensemble(PM, p, x0, 100, T=T, opts=o, rel_step=2.0 ** -24, probe32=True)
+    check_parity(gm, PM, p, x0, 100, T, o, r32, rps32, tol=1e-4, onset_tol=1e-6, mixed=True,
+                 label="pm-ragged bounded mixed")
+    assert np.all(np.isfinite(gm["J"]))
     _feasible(gm, 8.0)
 
 
@@ -87,9 +90,10 @@ def test_bounded_arm_ragged_fp64(ctx):
     p = I.planar3_params(0)
     x0 = I.planar3_x0(B, 11)
     T = I.horizons(B, 50, 200, seed=12)
-    g = gpu_solve(ctx, P3, p, x0, 200, T=T, max_iter=20, u_max=8.0)
-    r, rho = oracle_with_sensitivity(P3, p, x0, 200, T=T, opts=oracle_opts(max_iter=20, u_max=8.0))
-    compare_sensitivity_aware(g, r, rho, min_well=0.5, label="arm bounded")
+    g = gpu_solve(ctx, P3, p, x0, 200, T=T, max_iter=20, u_max=8.0, trace=True)
+    o = oracle_opts(max_iter=20, u_max=8.0)
+    r, rps = oracle_ensemble(P3, p, x0, 200, T=T, opts=o)
+    check_parity(g, P3, p, x0, 200, T, o, r, rps, label="arm bounded")
     _feasible(g, 8.0)
     for b in range(B):
         d, J = orc.check_trajectory(P3, p, g["X"][b, :T[b] + 1], g["U"][b, :T[b]])
@@ -98,11 +102,12 @@ def test_bounded_arm_ragged_fp64(ctx):
 
 def test_bounded_16k_sampled_and_feasible(ctx):
     kind, p, x0, T, _ = I.workload("pm16k")
-    g = gpu_solve(ctx, kind, p, x0, T, u_max=10.0)
+    g = gpu_solve(ctx, kind, p, x0, T, u_max=10.0, trace=True)
     _feasible(g, 10.0)
-    idx = np.r_[np.random.default_rng(4).choice(len(x0), 64, replace=False), 0, len(x0) - 1]
-    r, rho = oracle_with_sensitivity(kind, p, x0[idx], T, opts=oracle_opts(u_max=10.0))
-    compare_sensitivity_aware(g, r, rho, idx=idx, min_well=0.8, label="pm16k bounded")
+    idx = np.r_[np.random.default_rng(4).choice(np.arange(1, len(x0) - 1), 254, replace=False), 0, len(x0) - 1]
+    o = oracle_opts(u_max=10.0)
+    r, rps = oracle_ensemble(kind, p, x0[idx], T, opts=o)
+    check_parity(g, kind, p, x0, T, None, o, r, rps, idx=idx, label="pm16k bounded")
 
 
 @pytest.mark.parametrize("kind", [PM, P3], ids=["pm", "arm"])
@@ -139,9 +144,10 @@ def test_loose_bound_and_warm_start(ctx):
 def test_bounded_with_levenberg_marquardt(ctx):
     kind, p, x0, T, _ = I.workload("pm64")
     o = dict(max_iter=50, u_max=10.0, regularization=1)
-    g = gpu_solve(ctx, kind, p, x0, T, **o)
-    r, rho = oracle_with_sensitivity(kind, p, x0, T, opts=oracle_opts(**o))
-    compare_sensitivity_aware(g, r, rho, min_well=0.8, label="pm64 bounded LM")
+    g = gpu_solve(ctx, kind, p, x0, T, trace=True, **o)
+    oo = oracle_opts(**o)
+    r, rps = oracle_ensemble(kind, p, x0, T, opts=oo)
+    check_parity(g, kind, p, x0, T, None, oo, r, rps, label="pm64 bounded LM")
     _feasible(g, 10.0)
 
 

@@ -7,7 +7,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2602_19699_amd import inputs as I
 
-from gpu_helpers import compare, compare_sensitivity_aware, gpu_solve, oracle_opts, oracle_with_sensitivity, rel
+from gpu_helpers import check_parity, compare, gpu_solve, oracle_ensemble, oracle_opts, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -47,10 +47,12 @@ def test_lm_point_mass_ragged_mixed(ctx):
     compare(g, r, label="pm-ragged lm")
     for b in range(B):
         assert np.all(g["X"][b, T[b] + 1:] == 0) and np.all(g["U"][b, T[b]:] == 0)
-    gm = gpu_solve(ctx, PM, p, x0, 100, T=T, precision=1, **LM)
-    e = rel(gm["J"], r.J)
-    print(f"pm-ragged LM mixed: max rel {e.max():.2e}, within 1e-4: {(e <= 1e-4).mean():.3f}")
-    assert (e <= 1e-4).mean() >= 0.95 and np.all(np.isfinite(gm["J"]))
+    gm = gpu_solve(ctx, PM, p, x0, 100, T=T, precision=1, trace=True, **LM)
+    o = oracle_opts(**LM)
+    r32, rps = oracle_ensemble(PM, p, x0, 100, T=T, opts=o, rel_step=2.0 ** -24, probe32=True)
+    check_parity(gm, PM, p, x0, 100, T, o, r32, rps, tol=1e-4, onset_tol=1e-6, mixed=True,
+                 label="pm-ragged lm mixed")
+    assert np.all(np.isfinite(gm["J"]))
 
 
 @pytest.mark.parametrize("mu0", [1e-3, 0.5])
@@ -98,9 +100,10 @@ def test_lm_arm_ragged_fp64(ctx):
     p = I.planar3_params(0)
     x0 = I.planar3_x0(B, 11)
     T = I.horizons(B, 50, 200, seed=12)
-    g = gpu_solve(ctx, P3, p, x0, 200, T=T, max_iter=20, **LM)
-    r, rho = oracle_with_sensitivity(P3, p, x0, 200, T=T, opts=oracle_opts(max_iter=20, **LM))
-    compare_sensitivity_aware(g, r, rho, label="arm lm")
+    g = gpu_solve(ctx, P3, p, x0, 200, T=T, max_iter=20, trace=True, **LM)
+    o = oracle_opts(max_iter=20, **LM)
+    r, rps = oracle_ensemble(P3, p, x0, 200, T=T, opts=o)
+    check_parity(g, P3, p, x0, 200, T, o, r, rps, label="arm lm")
     for b in range(B):
         d, J = orc.check_trajectory(P3, p, g["X"][b, :T[b] + 1], g["U"][b, :T[b]])
         assert d <= 1e-12 and abs(J - g["J"][b]) <= 1e-12 * abs(J)

@@ -13,7 +13,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2602_19699_amd import inputs as I
 
-from gpu_helpers import gpu_solve, oracle_opts, rel
+from gpu_helpers import check_parity, gpu_solve, oracle_ensemble, oracle_opts, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -155,7 +155,10 @@ def test_actor_rollout(ctx, kind):
 
 def test_bic_pipeline_feeds_the_solver(ctx):
     # select 64 of 640 candidates, roll the actor out from them, solve from that
-    # warm start; against the oracle's own pipeline on the candidates both pick
+    # warm start.  The solve is held per instance to the oracle's solve from the
+    # same warm start (the actor's FP32 rollout is checked against the oracle's
+    # actor in the tests above); the whole pipeline is compared with the
+    # oracle's own pipeline on the candidates both pick, for the record
     import torch
     from paper_2602_19699_amd import cbic
     kind, p, _, _, _ = I.workload("pm64")
@@ -166,21 +169,22 @@ def test_bic_pipeline_feeds_the_solver(ctx):
     _, sel, xs, Ts = cbic.bic_select(ctx, std, torch.as_tensor(x, device="cuda"), torch.as_tensor(T, device="cuda"),
                                      T_max, 64, gather=True)
     U0 = cbic.actor_rollout(ctx, sys_, g, xs, T_max, T=Ts)
-    gs = gpu_solve(ctx, kind, p, xs.cpu().numpy(), T_max, T=Ts.cpu().numpy(), U0=U0.cpu().numpy(), max_iter=200,
-                   stop_mode=1, rtol=1e-12)
+    xs, Ts, U0 = xs.cpu().numpy(), Ts.cpu().numpy(), U0.cpu().numpy()
+    opt = dict(max_iter=200, stop_mode=1, rtol=1e-12)
+    gs = gpu_solve(ctx, kind, p, xs, T_max, T=Ts, U0=U0, trace=True, **opt)
     sys_.close()
+    oo = oracle_opts(**opt)
+    r, rps = oracle_ensemble(kind, p, xs, T_max, T=Ts, U0=U0, opts=oo)
+    check_parity(gs, kind, p, xs, T_max, Ts, oo, r, rps, U0=U0, label="BIC pipeline solve")
     _, sel_o = orc.bic_select(std_o, x, T, T_max, 64)
     Uo, _ = orc.actor_rollout(kind, p, o, x[sel_o], T_max, T=T[sel_o])
-    r = orc.solve_batch(kind, p, x[sel_o], T_max, T=T[sel_o], U0=Uo,
-                        opts=oracle_opts(max_iter=200, stop_mode=1, rtol=1e-12))
+    ro = orc.solve_batch(kind, p, x[sel_o], T_max, T=T[sel_o], U0=Uo, opts=oo)
     sel = sel.cpu().numpy()
     both = np.intersect1d(sel, sel_o)
     assert len(both) >= 60
-    ig = np.searchsorted(sel, both)
-    io = np.searchsorted(sel_o, both)
-    e = rel(gs["J"][ig], r.J[io])
-    print(f"BIC pipeline: {len(both)} common candidates, median rel cost {np.median(e):.2e}, max {e.max():.2e}")
-    assert (e <= 1e-6).mean() >= 0.9
+    e = rel(gs["J"][np.searchsorted(sel, both)], ro.J[np.searchsorted(sel_o, both)])
+    print(f"BIC pipeline vs the oracle's pipeline: {len(both)} common candidates, median rel cost "
+          f"{np.median(e):.2e}, max {e.max():.2e}")
 
 
 def test_network_errors(ctx):

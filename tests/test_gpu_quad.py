@@ -65,23 +65,23 @@ def test_quad_mixed_precision(ctx):
 def test_quad_1k_sampled(ctx):
     kind, p, x0, T, _ = I.workload("quad1k")
     g = gpu_solve(ctx, kind, p, x0, T)
-    idx = np.r_[np.random.default_rng(2).choice(len(x0), 6, replace=False), 0, len(x0) - 1]
+    idx = np.r_[np.random.default_rng(2).choice(np.arange(1, len(x0) - 1), 126, replace=False), 0, len(x0) - 1]
     r = orc.solve_batch(kind, p, x0[idx], T, opts=oracle_opts())
-    compare(g, r, idx=idx, label="quad1k")
-    _check_targets(g, kind, p, x0, T, idx[:3])
+    worst = compare(g, r, idx=idx, label="quad1k")
+    print(f"quad1k fp64: {len(idx)} instances, max rel cost {worst:.2e}")
+    _check_targets(g, kind, p, x0, T, idx[:16])
     assert np.all(np.isfinite(g["J"]))
 
 
 def test_quad_1k_headline_form(ctx):
     # the timed configuration of the quadruped: 1024 instances, mixed form,
-    # relative-decrease stop at 1e-4; sampled against the FP64 oracle at the
-    # 1e-4 cost bar, every instance ended by its stop rule
+    # relative-decrease stop at 1e-4; every instance against the FP64 oracle
+    # at the 1e-4 cost bar, every instance ended by its stop rule
     kind, p, x0, T, _ = I.workload("quad1k")
     g = gpu_solve(ctx, kind, p, x0, T, precision=1, stop_mode=1, rtol=1e-4)
-    idx = np.r_[np.random.default_rng(5).choice(len(x0), 24, replace=False), 0, len(x0) - 1]
-    r = orc.solve_batch(kind, p, x0[idx], T, opts=oracle_opts())
-    e = rel(g["J"][idx], r.J)
-    print(f"quad1k headline form: max rel {e.max():.2e}")
+    r = orc.solve_batch(kind, p, x0, T, opts=oracle_opts())
+    e = rel(g["J"], r.J)
+    print(f"quad1k headline form: {len(e)} instances, max rel {e.max():.2e}, median {np.median(e):.2e}")
     assert e.max() <= 1e-4
     assert np.all((g["status"] & (orc.ST_NONFINITE | orc.ST_CHOL_FAIL | orc.ST_MAX_ITER)) == 0)
 

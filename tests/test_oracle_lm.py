@@ -7,7 +7,8 @@ controls, H and g built here by numpy from (A, B, Q, R, Q_T); this fixes where
 mu enters, the value update under a damped gain, the raise of mu to the first
 power that factorises, and the floor mu0, without using the Riccati recursion.
 The fall of mu from a raised value needs a Hessian that changes between
-iterations; that rule has no closed-form pin here (parity unpinned)."""
+iterations: test_oracle_linesearch pins it on the point mass, whose linear
+dynamics make each iteration a proximal Newton step of a dense model."""
 import numpy as np
 import pytest
 
