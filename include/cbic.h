@@ -225,6 +225,31 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
                              const int32_t* d_T, const double* d_x0, const double* d_U0,
                              const cbic_solve_opts* opts, const cbic_outputs* out, void* stream);
 
+/* Allocation-free solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, kernels and results as cbic_solve_batch, but
+ * the workspace is not the context's: it is a device array of
+ * CBIC_NOALLOC_SCRATCH_BYTES held by the library on every GPU it runs on from
+ * load until the process ends, so the call allocates nothing (no hipMalloc,
+ * no graph of its own) and only enqueues kernels on `stream`.
+ * Limits and rules:
+ *  - the solve's workspace (cbic_workspace_size) must fit the array, else
+ *    CBIC_E_OOM before anything is launched (64 MiB: e.g. about 7000
+ *    point-mass instances of horizon 100 in the mixed form, 3500 in FP64);
+ *  - opts->flags must not hold CBIC_FLAG_GRAPH or CBIC_FLAG_TIMING, and an LQ
+ *    system must have been built or last solved with the same psd_eps
+ *    (CBIC_E_INVALID otherwise);
+ *  - every call on one GPU uses that GPU's one array, whatever its context or
+ *    stream: calls that overlap in time on a GPU race and give undefined
+ *    results, so the caller orders them (one stream, or events).  No state
+ *    carries over from one call to the next: each call initialises what it
+ *    reads.
+ * Errors: as cbic_solve_batch. */
+#define CBIC_NOALLOC_SCRATCH_BYTES (64u << 20)
+cbic_status cbic_solve_batch_noalloc(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max,
+                                     const int32_t* d_T, const double* d_x0, const double* d_U0,
+                                     const cbic_solve_opts* opts, const cbic_outputs* out, void* stream);
+
 /* Autotune the lane schedule for one problem class: solve the given batch
  * (same arguments as cbic_solve_batch) once per lanes-per-instance width
  * 1, 2, 4, 8, 16, time each on `stream`, and remember the fastest in the

@@ -83,6 +83,8 @@ _SIGS = {
     "cbic_workspace_size": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "cbic_solve_batch": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "cbic_solve_batch_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "cbic_phase_times": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "cbic_autotune": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -281,6 +283,25 @@ def solve_batch(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts
     _check(lib().cbic_solve_batch(ctx.h, sys.h, B, T_max, _dptr(T), x0.data_ptr(), _dptr(U0), C.byref(o),
                                   C.byref(oc), st))
     out._keep = (x0, T, U0)  # keep inputs alive until the caller synchronises
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def solve_batch_noalloc(ctx: Context, sys: System, x0, T_max: int, out: Outputs, T=None, U0=None,
+                        opts: Options | None = None, stream=None) -> Outputs:
+    """Enqueue a solve through the allocation-free entry point: the caller
+    provides every device buffer (inputs as float64 / int32 device tensors,
+    `out` from Outputs.allocate); the library's fixed device scratch is the
+    workspace."""
+    import torch
+    opts = opts or Options()
+    o = opts.c()
+    oc = out.c()
+    st = stream if stream is not None else torch.cuda.current_stream(torch.device("cuda", ctx.device)).cuda_stream
+    _check(lib().cbic_solve_batch_noalloc(ctx.h, sys.h, x0.shape[0], T_max, _dptr(T), x0.data_ptr(), _dptr(U0),
+                                          C.byref(o), C.byref(oc), st))
     return out
 
 

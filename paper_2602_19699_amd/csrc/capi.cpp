@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "runtime.hpp"
@@ -111,6 +113,146 @@ cbic_status ensure_ws(cbic_context* ctx, size_t need) {
   return CBIC_OK;
 }
 
+// Checks shared by both solve entry points (nothing is launched before they
+// pass); *L receives the launcher of the system, precision and schedule.
+cbic_status check_solve(cbic_context* ctx, const cbic_system* sys, int B, int Tmax, const int32_t* d_T,
+                        const double* d_x0, const double* d_U0, const cbic_solve_opts* opts,
+                        const cbic_outputs* out, const Launcher** L) {
+  if (!ctx || !sys) { set_error("ctx and sys are required"); return CBIC_E_INVALID; }
+  if (sys->ctx != ctx || !sys->d_prm) { set_error("sys was not created on this context"); return CBIC_E_INVALID; }
+  if (B < 1 || Tmax < 1) { set_error("B and T_max must be >= 1 (got %d, %d)", B, Tmax); return CBIC_E_INVALID; }
+  if (!d_x0) { set_error("d_x0 is required"); return CBIC_E_INVALID; }
+  if (!out || !out->X || !out->U || !out->J || !out->iters || !out->status) {
+    set_error("outputs X, U, J, iters and status are required");
+    return CBIC_E_INVALID;
+  }
+  const void* ptrs[] = {d_T, d_x0, d_U0, out->X, out->U, out->J, out->iters, out->status,
+                        out->Vbar, out->Vx, out->xK, out->cost_trace, out->work, out->jtrace};
+  for (const void* p : ptrs)
+    if (p && !aligned8(p) && p != d_T && p != out->iters && p != out->status && p != out->work &&
+        p != out->jtrace) {
+      set_error("device pointers must be 8-byte aligned");
+      return CBIC_E_INVALID;
+    }
+  if ((d_T && (reinterpret_cast<uintptr_t>(d_T) & 3u)) || (reinterpret_cast<uintptr_t>(out->iters) & 3u) ||
+      (reinterpret_cast<uintptr_t>(out->status) & 3u) || (out->work && (reinterpret_cast<uintptr_t>(out->work) & 3u)) ||
+      (out->jtrace && (reinterpret_cast<uintptr_t>(out->jtrace) & 3u))) {
+    set_error("int32 device pointers must be 4-byte aligned");
+    return CBIC_E_INVALID;
+  }
+  cbic_status st = check_opts(opts);
+  if (st) return st;
+  *L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, opts->schedule);
+  if (!*L) {
+    set_error("no kernel for system kind %d (n=%d, m=%d), precision %d, schedule %d", sys->kind, sys->n,
+              sys->m, opts->precision, opts->schedule);
+    return CBIC_E_UNSUPPORTED;
+  }
+  if (opts->regularization == CBIC_REG_LM && (*L)->schedule != CBIC_SCHED_LANE) {
+    set_error("the Levenberg-Marquardt variant runs on the lane schedule only");
+    return CBIC_E_UNSUPPORTED;
+  }
+  if (std::isfinite(opts->u_max) && (*L)->schedule != CBIC_SCHED_LANE) {
+    set_error("the control bound runs on the lane schedule only");
+    return CBIC_E_UNSUPPORTED;
+  }
+  return CBIC_OK;
+}
+
+// Enqueue one solve on `stream` with its workspace at `base`: ws_main bytes
+// of the launcher's layout followed by the horizon sort's scratch.  The caller
+// holds ctx->mu with the context's device current.  Allocates nothing itself
+// (a graph launch builds its cached graph on first use).
+cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launcher* L, const SolveParamsH& sp,
+                          int B, int Tmax, const int32_t* d_T, const double* d_x0, const double* d_U0,
+                          const cbic_solve_opts* opts, const cbic_outputs* out, char* base, size_t ws_main,
+                          hipStream_t stream) {
+  int32_t* hist = reinterpret_cast<int32_t*>(base + ws_main);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + ws_main + ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256);
+  if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
+  else perm = nullptr;
+
+  const bool timing = (opts->flags & CBIC_FLAG_TIMING) != 0;
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[0], stream));
+  // iterations that never run keep the marker -2
+  if (out->jtrace && opts->max_iter > 0) HIP_TRY(launch_fill_i32(out->jtrace, size_t(B) * opts->max_iter, -2, stream));
+  const IterTrace tr{out->cost_trace, out->jtrace};
+  HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
+                  out->cost_trace, sp.umax, stream));
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
+  int group = opts->group_lanes;
+  if (group <= 0) {
+    auto it = ctx->tuned.find(tune_key(sys, B, Tmax, opts));
+    group = it != ctx->tuned.end() ? it->second : default_group(sys->kind, B, opts->precision);
+  }
+  if (opts->max_iter > 0) {
+    const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
+    const int chunks = (opts->max_iter + G - 1) / G;
+    const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
+    if (!graph) {
+      for (int c = 0; c < chunks; ++c)
+        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
+    } else {
+      char key[512];
+      std::snprintf(key, sizeof key,
+                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
+                    (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
+                    sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
+                    (void*)out->jtrace, sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
+      auto it = ctx->graphs.find(key);
+      if (it == ctx->graphs.end()) {
+        cbic_context::GraphEntry ge;
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < chunks && e == hipSuccess; ++c)
+          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);
+          set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+          return CBIC_E_HIP;
+        }
+        ge.g = g;
+        HIP_TRY(hipGraphInstantiate(&ge.ge, g, nullptr, nullptr, 0));
+        it = ctx->graphs.emplace(key, ge).first;
+      }
+      HIP_TRY(hipGraphLaunch(it->second.ge, stream));
+    }
+  }
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[2], stream));
+  FinalOutH fo{out->X, out->U, out->J, out->iters, out->status, out->Vbar, out->Vx, out->xK, out->cost_trace,
+               out->work};
+  HIP_TRY(L->finalize(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
+  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[3], stream));
+  ctx->timed = ctx->timed || timing;
+  return CBIC_OK;
+}
+
+// ---------------------------------------------------------------- allocation-free scratch
+// The workspace of cbic_solve_batch_noalloc: a file-scope device array, part
+// of the library's code object, so each GPU the library runs on holds one
+// copy from module load until the process ends.  In host code its name is
+// not a device address; each context takes its device's address from
+// hipGetSymbolAddress at creation (scratch_address) and uses only that.
+constexpr size_t kScratchBytes = size_t(CBIC_NOALLOC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// The array's address on the current device (looked up once per device).
+cbic_status scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    it = addr.emplace(device, p).first;
+  }
+  *out = it->second;
+  return CBIC_OK;
+}
+
 }  // namespace
 
 cbic_status context_aux(cbic_context* ctx, size_t need, void** p) {
@@ -179,6 +321,10 @@ cbic_status cbic_context_create(int hip_device, size_t cap, cbic_context** out) 
   if (!c) { set_error("out of host memory"); return CBIC_E_OOM; }
   c->device = hip_device;
   c->cap = cap;
+  if (scratch_address(hip_device, &c->scratch) != CBIC_OK) {
+    delete c;
+    return CBIC_E_HIP;
+  }
   hipError_t e = hipEventCreateWithFlags(&c->done_ev, hipEventDisableTiming);
   for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&c->phase_ev[i]);
   if (e != hipSuccess) {
@@ -279,44 +425,9 @@ cbic_status cbic_workspace_size(const cbic_system* s, int32_t B, int32_t Tmax, c
 cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t Tmax,
                              const int32_t* d_T, const double* d_x0, const double* d_U0,
                              const cbic_solve_opts* opts, const cbic_outputs* out, void* stream_v) {
-  if (!ctx || !sys) { set_error("ctx and sys are required"); return CBIC_E_INVALID; }
-  if (sys->ctx != ctx || !sys->d_prm) { set_error("sys was not created on this context"); return CBIC_E_INVALID; }
-  if (B < 1 || Tmax < 1) { set_error("B and T_max must be >= 1 (got %d, %d)", B, Tmax); return CBIC_E_INVALID; }
-  if (!d_x0) { set_error("d_x0 is required"); return CBIC_E_INVALID; }
-  if (!out || !out->X || !out->U || !out->J || !out->iters || !out->status) {
-    set_error("outputs X, U, J, iters and status are required");
-    return CBIC_E_INVALID;
-  }
-  const void* ptrs[] = {d_T, d_x0, d_U0, out->X, out->U, out->J, out->iters, out->status,
-                        out->Vbar, out->Vx, out->xK, out->cost_trace, out->work, out->jtrace};
-  for (const void* p : ptrs)
-    if (p && !aligned8(p) && p != d_T && p != out->iters && p != out->status && p != out->work &&
-        p != out->jtrace) {
-      set_error("device pointers must be 8-byte aligned");
-      return CBIC_E_INVALID;
-    }
-  if ((d_T && (reinterpret_cast<uintptr_t>(d_T) & 3u)) || (reinterpret_cast<uintptr_t>(out->iters) & 3u) ||
-      (reinterpret_cast<uintptr_t>(out->status) & 3u) || (out->work && (reinterpret_cast<uintptr_t>(out->work) & 3u)) ||
-      (out->jtrace && (reinterpret_cast<uintptr_t>(out->jtrace) & 3u))) {
-    set_error("int32 device pointers must be 4-byte aligned");
-    return CBIC_E_INVALID;
-  }
-  cbic_status st = check_opts(opts);
+  const Launcher* L = nullptr;
+  cbic_status st = check_solve(ctx, sys, B, Tmax, d_T, d_x0, d_U0, opts, out, &L);
   if (st) return st;
-  const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, opts->schedule);
-  if (!L) {
-    set_error("no kernel for system kind %d (n=%d, m=%d), precision %d, schedule %d", sys->kind, sys->n,
-              sys->m, opts->precision, opts->schedule);
-    return CBIC_E_UNSUPPORTED;
-  }
-  if (opts->regularization == CBIC_REG_LM && L->schedule != CBIC_SCHED_LANE) {
-    set_error("the Levenberg-Marquardt variant runs on the lane schedule only");
-    return CBIC_E_UNSUPPORTED;
-  }
-  if (std::isfinite(opts->u_max) && L->schedule != CBIC_SCHED_LANE) {
-    set_error("the control bound runs on the lane schedule only");
-    return CBIC_E_UNSUPPORTED;
-  }
   const SolveParamsH sp = solve_params(opts);
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
@@ -334,72 +445,46 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
   st = ensure_ws(ctx, ws_main + sort_bytes(B, Tmax));
   if (st) return st;
   if (ctx->have_last && ctx->last_stream != stream) HIP_TRY(hipStreamWaitEvent(stream, ctx->done_ev, 0));
-
-  char* base = static_cast<char*>(ctx->ws);
-  int32_t* hist = reinterpret_cast<int32_t*>(base + ws_main);
-  int32_t* perm = reinterpret_cast<int32_t*>(base + ws_main + ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256);
-  if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
-  else perm = nullptr;
-
-  const bool timing = (opts->flags & CBIC_FLAG_TIMING) != 0;
-  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[0], stream));
-  // iterations that never run keep the marker -2
-  if (out->jtrace && opts->max_iter > 0)
-    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(out->jtrace), -2, size_t(B) * opts->max_iter, stream));
-  const IterTrace tr{out->cost_trace, out->jtrace};
-  HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
-                  out->cost_trace, sp.umax, stream));
-  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
-  int group = opts->group_lanes;
-  if (group <= 0) {
-    auto it = ctx->tuned.find(tune_key(sys, B, Tmax, opts));
-    group = it != ctx->tuned.end() ? it->second : default_group(sys->kind, B, opts->precision);
-  }
-  if (opts->max_iter > 0) {
-    const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
-    const int chunks = (opts->max_iter + G - 1) / G;
-    const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
-    if (!graph) {
-      for (int c = 0; c < chunks; ++c)
-        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
-    } else {
-      char key[512];
-      std::snprintf(key, sizeof key,
-                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
-                    (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
-                    sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
-                    (void*)out->jtrace, sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
-      auto it = ctx->graphs.find(key);
-      if (it == ctx->graphs.end()) {
-        cbic_context::GraphEntry ge;
-        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = hipSuccess;
-        for (int c = 0; c < chunks && e == hipSuccess; ++c)
-          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
-        hipGraph_t g = nullptr;
-        hipError_t e2 = hipStreamEndCapture(stream, &g);
-        if (e != hipSuccess || e2 != hipSuccess) {
-          if (g) (void)hipGraphDestroy(g);
-          set_error("graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
-          return CBIC_E_HIP;
-        }
-        ge.g = g;
-        HIP_TRY(hipGraphInstantiate(&ge.ge, g, nullptr, nullptr, 0));
-        it = ctx->graphs.emplace(key, ge).first;
-      }
-      HIP_TRY(hipGraphLaunch(it->second.ge, stream));
-    }
-  }
-  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[2], stream));
-  FinalOutH fo{out->X, out->U, out->J, out->iters, out->status, out->Vbar, out->Vx, out->xK, out->cost_trace,
-               out->work};
-  HIP_TRY(L->finalize(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
-  if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[3], stream));
-  ctx->timed = ctx->timed || timing;
+  st = enqueue_solve(ctx, sys, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->ws), ws_main,
+                     stream);
+  if (st) return st;
   HIP_TRY(hipEventRecord(ctx->done_ev, stream));
   ctx->last_stream = stream;
   ctx->have_last = true;
   return CBIC_OK;
+}
+
+cbic_status cbic_solve_batch_noalloc(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t Tmax,
+                                     const int32_t* d_T, const double* d_x0, const double* d_U0,
+                                     const cbic_solve_opts* opts, const cbic_outputs* out, void* stream_v) {
+  const Launcher* L = nullptr;
+  cbic_status st = check_solve(ctx, sys, B, Tmax, d_T, d_x0, d_U0, opts, out, &L);
+  if (st) return st;
+  if (opts->flags & (CBIC_FLAG_GRAPH | CBIC_FLAG_TIMING)) {
+    set_error("the allocation-free solve takes neither CBIC_FLAG_GRAPH nor CBIC_FLAG_TIMING");
+    return CBIC_E_INVALID;
+  }
+  const SolveParamsH sp = solve_params(opts);
+  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != sp.eps) {
+    set_error("this LQ system's clipped Hessians were built for psd_eps %g, not %g (a refresh needs a "
+              "synchronous copy; cbic_solve_batch does it)", sys->dev_eps, sp.eps);
+    return CBIC_E_INVALID;
+  }
+  const size_t ws_main = L->ws_bytes(B, Tmax);
+  const size_t need = ws_main + sort_bytes(B, Tmax);
+  if (need > kScratchBytes) {
+    set_error("the solve needs %zu workspace bytes; the allocation-free solve has %zu (CBIC_NOALLOC_SCRATCH_BYTES)",
+              need, kScratchBytes);
+    return CBIC_E_OOM;
+  }
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (!ctx->scratch) {
+    set_error("no device scratch address for device %d", ctx->device);
+    return CBIC_E_HIP;
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  return enqueue_solve(ctx, sys, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->scratch),
+                       ws_main, static_cast<hipStream_t>(stream_v));
 }
 
 cbic_status cbic_phase_times(cbic_context* ctx, double* ms3) {

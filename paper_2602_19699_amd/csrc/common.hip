@@ -55,6 +55,11 @@ __global__ void k_zero_i32(int32_t* __restrict__ p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
 }
 
+__global__ void k_fill_i32(int32_t* __restrict__ p, size_t n, int32_t v) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
 // dst[i] = src[idx[i]]  (status words of a slot list, for the serving loop)
 __global__ void k_gather_u32(const uint32_t* __restrict__ src, const int32_t* __restrict__ idx, int n,
                              uint32_t* __restrict__ dst) {
@@ -77,6 +82,15 @@ hipError_t launch_gather_u32(const uint32_t* src, const int32_t* idx, int n, uin
 hipError_t launch_set_index(const int32_t* slots, int n, int32_t* inst, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_set_index, dim3((n + 255) / 256), dim3(256), 0, st, slots, n, inst);
+  return hipGetLastError();
+}
+
+// p[0..n) = v by a kernel (not a memset node, so that captured graphs of a
+// solve replay it reliably)
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t g = (n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096;
+  hipLaunchKernelGGL(k_fill_i32, dim3(unsigned(g)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -94,6 +94,9 @@ std::string tune_key(const cbic_system* sys, int B, int Tmax, const cbic_solve_o
 // horizon sort (longest first) of B instances -> perm (device)
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st);
 
+// p[0..n) = v on the device, by a kernel
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
+
 }  // namespace cbic
 
 struct cbic_context {
@@ -119,6 +122,8 @@ struct cbic_context {
   // biased initial states), grown on demand
   void* aux = nullptr;
   size_t aux_bytes = 0;
+  // this device's address of the allocation-free solve's scratch array
+  void* scratch = nullptr;
 };
 
 // At least `need` bytes of the context's auxiliary device scratch in *p
