@@ -287,13 +287,22 @@ cbic_status cbic_phase_times(cbic_context* ctx, double* ms3);
 
 /* ---------------------------------------------------------------- serving
  * A continuous-batching request loop.  Requests (one TO instance each, any
- * system created on the server's context, any horizon up to that system
- * class's T_max) are admitted into per-class device slot pools while their
- * device footprint fits under mem_cap_bytes; admitted requests iterate
- * G iterations per launch beside the requests already resident, so work of
- * requests that arrive while others run overlaps on the GPU.  Their iterates
- * stay in device memory until they finish; finished slots are extracted,
- * copied to host and freed for new admissions. */
+ * system created on the server's context, any horizon up to the server's
+ * t_max) are grouped into classes: the system, the precision and the options
+ * that change a result (max_iter, psd_eps, the line search, the stop rule,
+ * lookahead_K, the regularization and its parameters, u_max); requests of
+ * different classes never share a pool, so each gets exactly its own options
+ * (the lanes-per-instance width and launch split come from the class's first
+ * request: they do not change results).  Each class has a device slot pool
+ * with its own stream; admitted requests iterate G iterations per launch beside
+ * the requests already resident, so work of requests that arrive while others
+ * run overlaps on the GPU.  Their iterates stay in device memory until they
+ * finish; finished slots are extracted, copied to host and freed for new
+ * admissions.  Memory: the device memory of all pools together stays within
+ * mem_cap_bytes.  A class's pool gets as many slots (up to slots_per_class)
+ * as fit beside the others; when not even one fits, idle pools (nothing
+ * resident or waiting) are released, and a class that still finds no room
+ * waits until another pool goes idle. */
 typedef struct {
   uint32_t struct_size;
   size_t mem_cap_bytes;    /* device memory for all slot pools; default 32 GiB              */
@@ -319,9 +328,12 @@ typedef struct {
 
 cbic_status cbic_server_opts_default(cbic_server_opts* opts);
 cbic_status cbic_server_create(cbic_context* ctx, const cbic_server_opts* opts, cbic_server** out);
-/* Queue one request.  h_x0 [n]; h_U0 [T][m] or NULL.  The solve options of the
- * request's class are fixed by the first request of that (system, precision).
- * Returns a ticket.  CBIC_E_BUSY if the request can never fit under the cap. */
+/* Queue one request.  h_x0 [n]; h_U0 [T][m] or NULL; opts are checked as
+ * cbic_solve_batch checks them.  Returns a ticket.  Errors: CBIC_E_INVALID (bad
+ * argument or options; an LQ system whose clipped Hessians were built for
+ * another psd_eps), CBIC_E_UNSUPPORTED (the Levenberg-Marquardt variant or a
+ * control bound for a system on the workgroup schedule), CBIC_E_BUSY (a
+ * one-slot pool of the request's class exceeds the cap: it can never run). */
 cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t T, const double* h_x0,
                                const double* h_U0, const cbic_solve_opts* opts, uint64_t* ticket);
 /* CBIC_OK with *out filled once the ticket is done (the ticket is then
@@ -332,9 +344,13 @@ typedef struct {
   uint64_t submitted, completed, rounds;
   size_t inflight_bytes;      /* footprint of the requests resident now          */
   size_t peak_inflight_bytes; /* largest footprint resident at once so far        */
-  size_t pool_bytes;          /* device memory held by the slot pools             */
-  int32_t classes;            /* (system, precision) pools created                */
+  size_t pool_bytes;          /* device memory held by the slot pools now         */
+  int32_t classes;            /* request classes seen (see cbic_server_submit)    */
   int32_t max_resident;       /* most requests resident at once                   */
+  size_t peak_pool_bytes;     /* most device memory the pools held at once (<= cap) */
+  uint64_t evictions;         /* idle pools released to make room for another class */
+  uint64_t launches;          /* iteration launches (G iterations of one class each) */
+  uint64_t launched_slots;    /* resident requests summed over those launches      */
 } cbic_server_stats;
 cbic_status cbic_server_get_stats(cbic_server* srv, cbic_server_stats* out);
 

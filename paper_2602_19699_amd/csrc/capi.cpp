@@ -28,11 +28,9 @@ using namespace cbic;
     }                                                                              \
   } while (0)
 
-namespace {
+namespace cbic {
 
-bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
-
-cbic_status check_opts(const cbic_solve_opts* o) {
+cbic_status check_solve_opts(const cbic_solve_opts* o) {
   if (!o) { set_error("opts is NULL"); return CBIC_E_INVALID; }
   if (o->struct_size != sizeof(cbic_solve_opts)) {
     set_error("opts.struct_size is %u, expected %zu", o->struct_size, sizeof(cbic_solve_opts));
@@ -79,6 +77,12 @@ SolveParamsH solve_params(const cbic_solve_opts* o) {
   sp.umax = o->u_max;
   return sp;
 }
+
+}  // namespace cbic
+
+namespace {
+
+bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
 size_t sort_bytes(int B, int Tmax) {
   return ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256 + (size_t(B) * 4 + 255) / 256 * 256;
@@ -140,7 +144,7 @@ cbic_status check_solve(cbic_context* ctx, const cbic_system* sys, int B, int Tm
     set_error("int32 device pointers must be 4-byte aligned");
     return CBIC_E_INVALID;
   }
-  cbic_status st = check_opts(opts);
+  cbic_status st = check_solve_opts(opts);
   if (st) return st;
   *L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, opts->schedule);
   if (!*L) {
@@ -410,7 +414,7 @@ cbic_status cbic_workspace_size(const cbic_system* s, int32_t B, int32_t Tmax, c
                                 size_t* bytes) {
   if (!s || !bytes) { set_error("NULL argument"); return CBIC_E_INVALID; }
   if (B < 1 || Tmax < 1) { set_error("B and T_max must be >= 1"); return CBIC_E_INVALID; }
-  cbic_status st = check_opts(opts);
+  cbic_status st = check_solve_opts(opts);
   if (st) return st;
   const Launcher* L = find_launcher(s->kind, s->n, s->m, opts->precision, opts->schedule);
   if (!L) {

@@ -83,6 +83,12 @@ struct Launcher {
 
 const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);
 
+// validation of a cbic_solve_opts (CBIC_E_INVALID with the message set)
+cbic_status check_solve_opts(const cbic_solve_opts* o);
+// the kernels' solve parameters for valid options (the Levenberg-Marquardt
+// variant clips nothing: eps is then negative)
+SolveParamsH solve_params(const cbic_solve_opts* o);
+
 // lanes per instance of the lane schedule when the caller leaves it to the
 // library: enough groups to give every SIMD of the chip a wave or two
 int default_group(int kind, int B, int precision);

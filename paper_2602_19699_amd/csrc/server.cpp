@@ -17,6 +17,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -36,9 +38,21 @@ struct Request {
   int T = 0;
   std::vector<double> x0, U0;
   cbic_solve_opts opts{};
+  std::string sig;  // the result-affecting options (the class key with sys and precision)
   double t_submit = 0, t_admit = 0;
   size_t bytes = 0;
 };
+
+// The options that change a solve's result, as a key: requests that differ in
+// them are served by different pools (the lanes-per-instance width, the
+// launch split and the flags do not change results).
+std::string result_signature(const cbic_solve_opts& o) {
+  char b[320];
+  std::snprintf(b, sizeof b, "%d|%.17g|%d|%.17g|%d|%.17g|%d|%d|%.17g|%.17g|%.17g|%.17g", o.max_iter, o.psd_eps,
+                o.ls_max_trials, o.ls_beta, o.stop_mode, o.rtol, o.lookahead_K, o.regularization, o.lm_mu0,
+                o.lm_factor, o.lm_mu_max, o.u_max);
+  return b;
+}
 
 struct Result {
   std::vector<double> X, U, Vbar, Vx;
@@ -77,7 +91,7 @@ struct Pool {
   uint32_t *h_statg = nullptr, *h_stat = nullptr;
   double *h_x0 = nullptr, *h_U0 = nullptr, *h_X = nullptr, *h_U = nullptr, *h_J = nullptr, *h_Vb = nullptr,
          *h_Vx = nullptr;
-  size_t bytes = 0;  // device bytes of this pool
+  size_t bytes = 0;  // device bytes of this pool (0 while it holds none)
   std::vector<int> free_slots;
   std::vector<std::unique_ptr<Request>> slot_req;  // request resident in each slot
   std::vector<int> active;                         // slots in use
@@ -104,10 +118,10 @@ struct cbic_server {
   std::unordered_map<uint64_t, std::unique_ptr<Result>> results;
   uint64_t next_ticket = 1;
   size_t outstanding = 0;  // submitted and not yet done
-  size_t inflight_bytes = 0, pool_bytes = 0, peak_inflight = 0;
-  uint64_t submitted = 0, completed = 0, rounds = 0;
+  size_t inflight_bytes = 0, pool_bytes = 0, peak_inflight = 0, peak_pool = 0;
+  uint64_t submitted = 0, completed = 0, rounds = 0, evictions = 0, launches = 0, launched_slots = 0;
   int max_resident = 0, resident = 0;
-  std::map<std::pair<const cbic_system*, int>, std::unique_ptr<Pool>> pools;
+  std::map<std::tuple<const cbic_system*, int, std::string>, std::unique_ptr<Pool>> pools;
   std::thread worker;
   bool stop = false;
   int fatal = 0;
@@ -143,11 +157,16 @@ size_t staging_bytes(int B, int T, int n, int m) {
          a(8 * size_t(B) * (T + 1) * n) * 2 + a(8 * size_t(B) * T * m) + a(8 * size_t(B)) + a(8 * size_t(B) * (T + 1));
 }
 
+// device bytes of a pool of Bcap slots: the launcher's workspace and staging
+size_t pool_bytes(const Launcher* L, int Bcap, int Tcap, int n, int m) {
+  return L->ws_bytes(Bcap, Tcap) + staging_bytes(Bcap, Tcap, n, m);
+}
+
 bool make_pool(cbic_server* srv, Pool* p) {
   const int elem = p->precision ? 4 : 8;
   p->lay = lane_layout(p->n, p->m, elem, p->Bcap, p->Tcap, p->L->nbuf);
-  SRV_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
-  SRV_TRY(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
+  if (!p->stream) SRV_TRY(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking));
+  if (!p->ev) SRV_TRY(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
   // the launcher's workspace: the lane layout plus whatever it keeps per slot
   const size_t wsb = p->L->ws_bytes(p->Bcap, p->Tcap);
   SRV_TRY(hipMalloc(&p->ws, wsb));
@@ -170,19 +189,49 @@ bool make_pool(cbic_server* srv, Pool* p) {
     (pass ? p->h_J : p->d_J) = carve<double>(q, p->Bcap);
     (pass ? p->h_Vb : p->d_Vb) = carve<double>(q, size_t(p->Bcap) * (p->Tcap + 1));
   }
+  p->slot_req.clear();
   p->slot_req.resize(p->Bcap);
+  p->free_slots.clear();
   p->free_slots.reserve(p->Bcap);
   for (int s = p->Bcap - 1; s >= 0; --s) p->free_slots.push_back(s);
   return true;
 }
 
-void free_pool(Pool* p) {
+// Release a pool's device and pinned memory (its stream and event too when
+// `all`); an idle pool released this way is rebuilt when requests return.
+void free_pool(Pool* p, bool all = true) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   if (p->ws) (void)hipFree(p->ws);
   if (p->dbuf) (void)hipFree(p->dbuf);
   if (p->hbuf) (void)hipHostFree(p->hbuf);
-  if (p->ev) (void)hipEventDestroy(p->ev);
-  if (p->stream) (void)hipStreamDestroy(p->stream);
+  p->ws = nullptr;
+  p->dbuf = nullptr;
+  p->hbuf = nullptr;
+  p->bytes = 0;
+  p->free_slots.clear();
+  p->slot_req.clear();
+  p->list_dirty = true;
+  if (all) {
+    if (p->ev) (void)hipEventDestroy(p->ev);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    p->ev = nullptr;
+    p->stream = nullptr;
+  }
+}
+
+// Largest slot count (<= want) whose pool fits beside the memory the other
+// pools hold, 0 if not even one slot fits.
+int fit_slots(const cbic_server* srv, const Pool* p, int want) {
+  const size_t cap = srv->opts.mem_cap_bytes;
+  auto fits = [&](int b) { return srv->pool_bytes + pool_bytes(p->L, b, p->Tcap, p->n, p->m) <= cap; };
+  if (!fits(1)) return 0;
+  int lo = 1, hi = want;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    if (fits(mid)) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 void collect_inbox(cbic_server* srv) {
@@ -190,7 +239,7 @@ void collect_inbox(cbic_server* srv) {
   while (!srv->inbox.empty()) {
     std::unique_ptr<Request> r = std::move(srv->inbox.front());
     srv->inbox.pop_front();
-    auto key = std::make_pair(r->sys, r->opts.precision);
+    auto key = std::make_tuple(r->sys, int(r->opts.precision), r->sig);
     auto it = srv->pools.find(key);
     if (it == srv->pools.end()) {
       auto p = std::make_unique<Pool>();
@@ -200,7 +249,7 @@ void collect_inbox(cbic_server* srv) {
       p->opts = r->opts;
       p->n = r->sys->n;
       p->m = r->sys->m;
-      p->Bcap = srv->opts.slots_per_class;
+      p->Bcap = 0;
       p->Tcap = srv->opts.t_max;
       it = srv->pools.emplace(key, std::move(p)).first;
     }
@@ -208,18 +257,40 @@ void collect_inbox(cbic_server* srv) {
   }
 }
 
-// Admit pending requests of class p (FIFO) while a slot is free and the
-// in-flight footprint stays under the cap; stage their inputs and run init.
+// Give a class with waiting requests its pool: as many slots (up to
+// slots_per_class) as fit beside the memory the other pools hold, releasing
+// idle pools (nothing resident, nothing waiting) when not even one slot fits.
+// The device memory of all pools together never exceeds the cap; a class
+// that finds no room keeps waiting until another pool goes idle.
+bool ensure_pool(cbic_server* srv, Pool* p) {
+  if (p->ws || p->pending.empty()) return true;
+  int b = fit_slots(srv, p, srv->opts.slots_per_class);
+  if (b == 0)
+    for (auto& kv : srv->pools) {
+      Pool* q = kv.second.get();
+      if (q == p || !q->ws || !q->active.empty() || !q->pending.empty() || q->phase != 0) continue;
+      srv->pool_bytes -= q->bytes;
+      free_pool(q, false);
+      ++srv->evictions;
+      if ((b = fit_slots(srv, p, srv->opts.slots_per_class)) > 0) break;
+    }
+  if (b == 0) return true;
+  p->Bcap = b;
+  if (!make_pool(srv, p)) return false;
+  srv->pool_bytes += p->bytes;
+  srv->peak_pool = std::max(srv->peak_pool, srv->pool_bytes);
+  return true;
+}
+
+// Admit pending requests of class p (FIFO) while a slot of its pool is free;
+// stage their inputs and run init.
 bool admit(cbic_server* srv, Pool* p) {
-  if (!p->ws && !p->pending.empty()) {
-    if (!make_pool(srv, p)) return false;
-    srv->pool_bytes += p->bytes;
-  }
+  if (!ensure_pool(srv, p)) return false;
+  if (!p->ws) return true;
   const double tnow = srv->now();
   int nadm = 0;
   while (!p->pending.empty() && !p->free_slots.empty()) {
     Request* r = p->pending.front().get();
-    if (srv->inflight_bytes + r->bytes > srv->opts.mem_cap_bytes) break;
     const int s = p->free_slots.back();
     p->free_slots.pop_back();
     srv->inflight_bytes += r->bytes;
@@ -246,7 +317,7 @@ bool admit(cbic_server* srv, Pool* p) {
   SRV_TRY(hipMemcpyAsync(p->d_T, p->h_T, 4 * nadm, hipMemcpyHostToDevice, p->stream));
   SRV_TRY(hipMemcpyAsync(p->d_adm, p->h_adm, 4 * nadm, hipMemcpyHostToDevice, p->stream));
   SRV_TRY(p->L->init(p->sys->d_prm, p->ws, p->Bcap, p->Tcap, nadm, p->d_adm, p->Tcap, p->d_T, nullptr, p->d_x0,
-                     p->d_U0, p->opts.max_iter, nullptr, __builtin_inf(), p->stream));
+                     p->d_U0, p->opts.max_iter, nullptr, p->opts.u_max, p->stream));
   return true;
 }
 
@@ -259,8 +330,9 @@ bool launch_iterations(cbic_server* srv, Pool* p) {
     SRV_TRY(hipMemcpyAsync(p->d_list, p->h_list, 4 * na, hipMemcpyHostToDevice, p->stream));
     p->list_dirty = false;
   }
-  SolveParamsH sp{p->opts.max_iter, p->opts.ls_max_trials, p->opts.stop_mode, p->opts.lookahead_K,
-                  p->opts.psd_eps, p->opts.ls_beta, p->opts.rtol};
+  const SolveParamsH sp = solve_params(&p->opts);
+  ++srv->launches;
+  srv->launched_slots += uint64_t(na);
   const int group = p->opts.group_lanes > 0 ? p->opts.group_lanes : default_group(p->sys->kind, na, p->precision);
   SRV_TRY(p->L->iterate(p->sys->d_prm, p->ws, p->Bcap, p->Tcap, na, p->d_list, sp,
                         std::max(1, srv->opts.iters_per_launch), group, IterTrace{nullptr, nullptr}, p->stream));
@@ -442,22 +514,22 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
                                const double* h_U0, const cbic_solve_opts* opts, uint64_t* ticket) {
   if (!srv || !sys || !h_x0 || !opts || !ticket) { set_error("NULL argument"); return CBIC_E_INVALID; }
   if (sys->ctx != srv->ctx || !sys->d_prm) { set_error("sys was not created on the server's context"); return CBIC_E_INVALID; }
-  if (opts->struct_size != sizeof(cbic_solve_opts)) { set_error("opts.struct_size mismatch"); return CBIC_E_INVALID; }
+  const cbic_status cs = check_solve_opts(opts);
+  if (cs) return cs;
   if (T < 1 || T > srv->opts.t_max) { set_error("T must be in 1..%d", srv->opts.t_max); return CBIC_E_INVALID; }
-  if (opts->precision != CBIC_FP64 && opts->precision != CBIC_MIXED) { set_error("bad precision"); return CBIC_E_INVALID; }
-  if (opts->regularization != CBIC_REG_CLIP) {
-    set_error("the server runs the clipped regularization only");
-    return CBIC_E_UNSUPPORTED;
-  }
-  if (!(opts->u_max > 0.0)) { set_error("u_max must be > 0"); return CBIC_E_INVALID; }
-  if (std::isfinite(opts->u_max)) {
-    set_error("the server runs unbounded controls only");
-    return CBIC_E_UNSUPPORTED;
-  }
   const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, 0);
   if (!L) {
     set_error("no kernel for this system and precision");
     return CBIC_E_UNSUPPORTED;
+  }
+  if (L->schedule != CBIC_SCHED_LANE && (opts->regularization != CBIC_REG_CLIP || std::isfinite(opts->u_max))) {
+    set_error("the Levenberg-Marquardt variant and the control bound run on the lane schedule only");
+    return CBIC_E_UNSUPPORTED;
+  }
+  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != solve_params(opts).eps) {
+    set_error("this LQ system's clipped Hessians were built for psd_eps %g (a served request cannot rebuild "
+              "them under running solves)", sys->dev_eps);
+    return CBIC_E_INVALID;
   }
   if (srv->fatal) { set_error("server stopped: %s", srv->fatal_msg); return CBIC_E_HIP; }
   auto r = std::make_unique<Request>();
@@ -466,12 +538,12 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
   r->x0.assign(h_x0, h_x0 + sys->n);
   if (h_U0) r->U0.assign(h_U0, h_U0 + size_t(T) * sys->m);
   r->opts = *opts;
+  r->sig = result_signature(*opts);
   r->bytes = footprint(sys->n, sys->m, opts->precision ? 4 : 8, T, L->nbuf) + L->slot_extra;
-  // a request that can never fit: its own footprint plus its class pool over the cap
-  const size_t pool = L->ws_bytes(srv->opts.slots_per_class, srv->opts.t_max) +
-                      staging_bytes(srv->opts.slots_per_class, srv->opts.t_max, sys->n, sys->m);
-  if (r->bytes > srv->opts.mem_cap_bytes || pool > srv->opts.mem_cap_bytes) {
-    set_error("request footprint %zu B (pool %zu B) exceeds the memory cap %zu B", r->bytes, pool,
+  // a request that can never fit: a one-slot pool of its class over the cap
+  const size_t one = pool_bytes(L, 1, srv->opts.t_max, sys->n, sys->m);
+  if (one > srv->opts.mem_cap_bytes) {
+    set_error("a one-slot pool of this class needs %zu B, over the memory cap of %zu B", one,
               srv->opts.mem_cap_bytes);
     return CBIC_E_BUSY;
   }
@@ -528,6 +600,10 @@ cbic_status cbic_server_get_stats(cbic_server* srv, cbic_server_stats* out) {
   out->pool_bytes = srv->pool_bytes;
   out->classes = int32_t(srv->pools.size());
   out->max_resident = srv->max_resident;
+  out->peak_pool_bytes = srv->peak_pool;
+  out->evictions = srv->evictions;
+  out->launches = srv->launches;
+  out->launched_slots = srv->launched_slots;
   return CBIC_OK;
 }
 

@@ -162,10 +162,12 @@ def test_bound_rejected_where_unsupported(ctx):
         with pytest.raises(cbic.CbicError) as e:
             gpu_solve(ctx, kind, p, x0[:2], T, u_max=bad)
         assert e.value.code == cbic.E_INVALID
+    # the server serves bounded requests of the lane systems (its class test
+    # checks them against the batched solver) and refuses them for the quadruped
     srv = cbic.Server(ctx, slots_per_class=4, t_max=200)
-    sys_ = cbic.System(ctx, PM, p)
+    q = cbic.System(ctx, QUAD, I.quad_params(0))
     with pytest.raises(cbic.CbicError) as e:
-        srv.submit(sys_, x0[0], 50, opts=cbic.Options(u_max=5.0))
+        srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=7)[0], 50, opts=cbic.Options(u_max=5.0))
     assert e.value.code == cbic.E_UNSUPPORTED
     srv.close()
-    sys_.close()
+    q.close()

@@ -140,12 +140,13 @@ def test_lm_rejected_where_unsupported(ctx):
         with pytest.raises(cbic.CbicError) as e:
             gpu_solve(ctx, kind, p, x0[:2], T, **{**LM, **bad})
         assert e.value.code == cbic.E_INVALID
-    # the serving runtime takes clip-regularised requests only
+    # the serving runtime takes the LM variant for lane systems (its class
+    # test checks them against the batched solver), not for the quadruped
     srv = cbic.Server(ctx, slots_per_class=4, t_max=200)
-    sys_ = cbic.System(ctx, PM, p)
+    q = cbic.System(ctx, QUAD, I.quad_params(0))
     with pytest.raises(cbic.CbicError) as e:
-        srv.submit(sys_, x0[0], 50, opts=cbic.Options(regularization=1))
+        srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=7)[0], 50, opts=cbic.Options(regularization=1))
     assert e.value.code == cbic.E_UNSUPPORTED
     srv.close()
-    sys_.close()
+    q.close()
     torch.cuda.synchronize()

@@ -60,28 +60,105 @@ def test_alone_equals_mix_and_matches_batch_and_oracle(ctx):
 
 
 def test_admission_respects_the_memory_cap(ctx):
+    # the device memory of all pools together stays within the cap: with a
+    # generous cap every class gets its pool; with a cap below two one-slot
+    # pools one class runs at a time, and idle pools are released for the
+    # classes waiting (evictions); every request completes either way, with
+    # the batched solver's result
     from paper_2602_19699_amd import cbic, loadgen
     mix = loadgen.Mix(ctx)
     reqs = mix.requests(40, seed=5, t_range=(20, 40))
-    # pools are sized for a few slots; the cap admits only a handful of requests at once
-    quad_fp = 8 * (2 * 41 * 37 + 2 * 40 * 12 + 40 * 12 * 37 + 40 * 12) + 40
-    cap = 48 << 20
-    srv = cbic.Server(ctx, mem_cap=cap, slots_per_class=16, t_max=40, iters_per_launch=2)
-    tickets = [srv.submit(mix.systems[k], x0, T, opts=mix.opts) for k, T, x0 in reqs]
-    srv.drain()
-    res = [srv.poll(t, targets=False) for t in tickets]
-    st = srv.stats()
-    assert st["peak_inflight_bytes"] <= cap and st["completed"] == 40
-    assert all(np.isfinite(r["J"]) for r in res)
-    assert quad_fp < cap
-    srv.close()
+    one = max(mix.systems[k].workspace_size(1, 40) for k in mix.kinds)
+    for cap, expect_evictions in ((48 << 20, False), (int(1.2 * one), True)):
+        srv = cbic.Server(ctx, mem_cap=cap, slots_per_class=16, t_max=40, iters_per_launch=2)
+        tickets = [srv.submit(mix.systems[k], x0, T, opts=mix.opts) for k, T, x0 in reqs]
+        srv.drain()
+        res = [srv.poll(t, targets=False) for t in tickets]
+        st = srv.stats()
+        print(f"cap {cap} B: {st}")
+        assert st["completed"] == 40 and st["peak_pool_bytes"] <= cap
+        assert st["inflight_bytes"] == 0 and st["peak_inflight_bytes"] <= st["peak_pool_bytes"]
+        assert (st["evictions"] > 0) == expect_evictions
+        for kind in mix.kinds:
+            idx = [i for i, (k, _, _) in enumerate(reqs) if k == kind]
+            x0 = np.stack([reqs[i][2] for i in idx])
+            T = np.array([reqs[i][1] for i in idx], np.int32)
+            g = gpu_solve(ctx, kind, mix.params[kind], x0, 40, T=T, stop_mode=1, rtol=1e-10)
+            for j, i in enumerate(idx):
+                assert g["J"][j] == res[i]["J"]
+        srv.close()
     # a request that can never fit is refused
     tiny = cbic.Server(ctx, mem_cap=4096, slots_per_class=4, t_max=200)
-    k, T, x0 = mix.requests(1, seed=1)[0]
     with pytest.raises(cbic.CbicError) as e:
         tiny.submit(mix.systems[I.SYS_QUAD_SYNTH], mix.x0(I.SYS_QUAD_SYNTH, 1, 1)[0], 200, opts=mix.opts)
     assert e.value.code == cbic.E_BUSY
     tiny.close()
+
+
+def test_requests_are_served_with_their_own_options(ctx):
+    # requests of one system and precision with different result-affecting
+    # options (budget, stop rule, control bound, Levenberg-Marquardt) form
+    # classes of their own: each result is the batched solver's under that
+    # request's options, bit for bit
+    from paper_2602_19699_amd import cbic
+    p = I.point_mass_params(0)
+    pa = I.planar3_params(0)
+    sp, sa = cbic.System(ctx, I.SYS_POINT_MASS, p), cbic.System(ctx, I.SYS_PLANAR3, pa)
+    x0, xa = I.point_mass_x0(12, 4), I.planar3_x0(12, 5)
+    variants = [dict(max_iter=7), dict(max_iter=30, stop_mode=1, rtol=1e-9), dict(max_iter=20, u_max=6.0),
+                dict(max_iter=20, regularization=1), dict(max_iter=15, precision=1, u_max=6.0)]
+    srv = cbic.Server(ctx, slots_per_class=32, t_max=80, iters_per_launch=3)
+    jobs = []
+    for vi, v in enumerate(variants):
+        for sysm, kind, xs, T in ((sp, I.SYS_POINT_MASS, x0, 60), (sa, I.SYS_PLANAR3, xa, 70)):
+            for b in range(0, 12, 3):
+                jobs.append((vi, kind, b, T, srv.submit(sysm, xs[b], T, opts=cbic.Options(**v))))
+    srv.drain()
+    st = srv.stats()
+    assert st["classes"] == 2 * len(variants)
+    for vi, v in enumerate(variants):
+        for kind, xs, T, prm in ((I.SYS_POINT_MASS, x0, 60, p), (I.SYS_PLANAR3, xa, 70, pa)):
+            g = gpu_solve(ctx, kind, prm, xs, T, **v)
+            for vj, k, b, T2, t in jobs:
+                if vj == vi and k == kind:
+                    r = srv.poll(t)
+                    assert r["J"] == g["J"][b] and r["status"] == g["status"][b], (v, kind, b)
+                    np.testing.assert_array_equal(r["U"], g["U"][b, :T2])
+    srv.close()
+    sp.close()
+    sa.close()
+
+
+def test_invalid_requests_are_refused_and_the_server_keeps_serving(ctx):
+    from paper_2602_19699_amd import cbic
+    p = I.point_mass_params(0)
+    sysm = cbic.System(ctx, I.SYS_POINT_MASS, p)
+    x0 = I.point_mass_x0(2, 6)
+    srv = cbic.Server(ctx, slots_per_class=8, t_max=50)
+    for bad in (dict(group_lanes=3), dict(ls_beta=1.5), dict(psd_eps=float("nan")), dict(max_iter=-1),
+                dict(schedule=7), dict(u_max=0.0)):
+        with pytest.raises(cbic.CbicError) as e:
+            srv.submit(sysm, x0[0], 30, opts=cbic.Options(**bad))
+        assert e.value.code == cbic.E_INVALID, bad
+    # the workgroup-schedule system takes neither the bound nor the LM variant
+    q = cbic.System(ctx, I.SYS_QUAD_SYNTH, I.quad_params(0))
+    for v in (dict(u_max=5.0), dict(regularization=1)):
+        with pytest.raises(cbic.CbicError) as e:
+            srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=2)[0], 20, opts=cbic.Options(**v))
+        assert e.value.code == cbic.E_UNSUPPORTED
+    # an LQ system built for another clipping floor
+    lq = cbic.System(ctx, I.SYS_LQ, I.lq_random(2, 1, seed=1))
+    with pytest.raises(cbic.CbicError) as e:
+        srv.submit(lq, np.ones(2), 10, opts=cbic.Options(psd_eps=1e-3))
+    assert e.value.code == cbic.E_INVALID
+    t = srv.submit(sysm, x0[1], 30, opts=cbic.Options(max_iter=10))
+    srv.drain()
+    r = srv.poll(t)
+    g = gpu_solve(ctx, I.SYS_POINT_MASS, p, x0[1:], 30, max_iter=10)
+    assert r["J"] == g["J"][0]
+    srv.close()
+    for s_ in (sysm, q, lq):
+        s_.close()
 
 
 def test_poisson_run_reports_latency(ctx):
