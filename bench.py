@@ -38,6 +38,7 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 METRIC = "converged TO solves/sec at 1e-4 rel cost vs FP64 plain; p50/p99 latency"
+SERVING_RATES = (1000, 2000, 5000, 10000, 20000, 50000)
 
 
 # HBM traffic of the dominant kernels from rocprofv3 counter runs (FETCH_SIZE,
@@ -74,11 +75,36 @@ def sources_sha(files):
     return h.hexdigest()
 
 
-def traffic_for(name, form, kernel):
+def _counters(name, form, kernel):
     e = COUNTERS.get((name, form, kernel))
     if e is None or e["sha256"] != sources_sha(e["sources"]):
         return None
+    return e
+
+
+def traffic_for(name, form, kernel):
+    e = _counters(name, form, kernel)
+    if e is None:
+        return None
     return round((e["fetch_kib"] * FETCH_SCALE + e["write_kib"] * WRITE_SCALE) * 1024.0)
+
+
+# VALU issue capacity: a wave64 VALU instruction occupies its SIMD's 16 lanes
+# for 4 cycles (FP32 without packing, and FP64), so the chip issues at most
+# 1024 SIMDs x 2.4e9 / 4 wave instructions per second.  SQ_ACTIVE_INST_VALU
+# counts the issued wave instructions in those 4-cycle units (it agrees with
+# SQ_INSTS_VALU within 5 %).
+N_SIMD, CLOCK_HZ, VALU_CYCLES = 1024, 2.4e9, 4
+
+
+def valu_issue_frac(name, form, kernel, iterate_ms):
+    """Fraction of the chip's VALU issue capacity the kernel used, from the
+    SQ_ACTIVE_INST_VALU count per launch of a counter run of the same sources
+    and the kernel's duration measured live."""
+    e = _counters(name, form, kernel)
+    if e is None or "sq_active_inst_valu" not in e:
+        return None
+    return e["sq_active_inst_valu"] * VALU_CYCLES / (N_SIMD * CLOCK_HZ * iterate_ms * 1e-3)
 
 
 def riccati_flops(n, m):
@@ -266,10 +292,13 @@ def roofline_for(name, form, res, form_opts):
     sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
     bounded = "true" if np.isfinite(form_opts.u_max) else "false"
     kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']},{bounded}>"
+    vf = valu_issue_frac(name, form, kernel, res["iterate_ms"])
     return {"bound": "hbm", "achieved": round(res["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": traffic_for(name, form, kernel),
             "kernel": kernel, "alg_bytes_per_launch": res["iterate_alg_bytes"],
-            "iterate_ms": round(res["iterate_ms"], 4)}
+            "iterate_ms": round(res["iterate_ms"], 4),
+            # the binding resource: the share of the chip's VALU issue slots the kernel used
+            "valu_issue_frac": None if vf is None else round(vf, 4)}
 
 
 def bic_pipeline(ctx, steps, warmup):
@@ -333,22 +362,47 @@ def bic_pipeline(ctx, steps, warmup):
             "steps": steps}
 
 
-def serving(ctx, rates, seconds):
+SERVING_FORMS = {
+    # name: (precision, relative-decrease stop)
+    "fp64_tol1e-10": (0, 1e-10),
+    "mixed_tol1e-7": (1, 1e-7),
+}
+
+
+def serving(ctx, rates, min_requests=20000, min_seconds=0.4, batched=None):
     """Open-loop Poisson serving: requests drawn 50/30/20 from the point mass,
-    the arm and the quadruped, horizons uniform on 20..200, FP64 with the
-    relative-decrease stop, 32 GiB admission cap, 4 iterations per launch."""
+    the arm and the quadruped, horizons uniform on 20..200, 32 GiB memory cap,
+    4 iterations per launch; for each form (FP64 and the mixed form, each with
+    its relative-decrease stop) and each offered rate, max(min_requests,
+    rate * min_seconds) arrivals.  Beside p50/p99 per class, the server's own
+    counters over each rate: iteration launches, resident requests per launch,
+    and the share of wall time its worker thread was busy (the host side's
+    load).  `batched` (optional) maps a form to the batched solver's per-batch
+    p99 of each class, for comparison."""
     from paper_2602_19699_amd import cbic, loadgen
-    mix = loadgen.Mix(ctx, precision=cbic.FP64, stop_mode=1, rtol=1e-10)
-    srv = cbic.Server(ctx, mem_cap=32 << 30, slots_per_class=4096, t_max=200, iters_per_launch=4)
-    loadgen.run_poisson(srv, mix, rate=1000.0, n=200, seed=1)  # warm-up: pools, code objects
-    out = {"workload": "Poisson arrivals, mix 50/30/20 point mass / arm / quadruped, T~U{20..200}, FP64 "
-                       "tolerance stop 1e-10, cap 32 GiB, 4 iterations per launch", "rates": []}
-    for i, rate in enumerate(rates):
-        n = int(rate * seconds)
-        st, _, _ = loadgen.run_poisson(srv, mix, rate=float(rate), n=n, seed=100 + i)
-        out["rates"].append({k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()})
-    out["server_stats"] = srv.stats()
-    srv.close()
+    out = {"workload": "Poisson arrivals, mix 50/30/20 point mass / arm / quadruped, T~U{20..200}, cap 32 GiB, "
+                       "4 iterations per launch", "forms": {}}
+    for fi, (fname, (prec, rtol)) in enumerate(SERVING_FORMS.items()):
+        mix = loadgen.Mix(ctx, precision=prec, stop_mode=1, rtol=rtol)
+        srv = cbic.Server(ctx, mem_cap=32 << 30, slots_per_class=4096, t_max=200, iters_per_launch=4)
+        loadgen.run_poisson(srv, mix, rate=1000.0, n=300, seed=1)  # warm-up: pools, code objects
+        rows = []
+        for i, rate in enumerate(rates):
+            n = int(max(min_requests, rate * min_seconds))
+            s0 = srv.stats()
+            t0 = time.perf_counter()
+            st, _, _ = loadgen.run_poisson(srv, mix, rate=float(rate), n=n, seed=100 + 10 * fi + i)
+            wall = time.perf_counter() - t0
+            s1 = srv.stats()
+            launches = s1["launches"] - s0["launches"]
+            st["launches"] = launches
+            st["slots_per_launch"] = (s1["launched_slots"] - s0["launched_slots"]) / max(launches, 1)
+            st["host_busy_frac"] = (s1["host_busy_s"] - s0["host_busy_s"]) / wall
+            rows.append({k: (float(f"{v:.4g}") if isinstance(v, float) else v) for k, v in st.items()})
+            print(f"serving {fname} {rate}/s: {rows[-1]}", file=sys.stderr, flush=True)
+        out["forms"][fname] = {"rates": rows, "server_stats": srv.stats(),
+                               "batched_p99_ms": None if batched is None else batched.get(fname)}
+        srv.close()
     return out
 
 
@@ -391,7 +445,7 @@ def main():
 
     ctx = cbic.Context(0)
     if args.serving_sweep:
-        print(json.dumps(serving(ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=2.0)))
+        print(json.dumps(serving(ctx, rates=SERVING_RATES)))
         return
     if args.bic:
         print(json.dumps(bic_pipeline(ctx, steps=args.steps, warmup=args.warmup)))
@@ -441,8 +495,14 @@ def main():
           "pm64": "point-mass OCP (n=4, m=2), B=64, T=100",
           "arm4k": "planar 3-link arm (n=6, m=3), B=4096, T uniform 50..200",
           "quad1k": "quadruped-sized system (n=37, m=12), B=1024, T=100"}[nme]
-    serve = None if (args.quick or args.only or args.workload) else serving(
-        ctx, rates=(1000, 2000, 5000, 10000, 20000, 50000), seconds=1.5)
+    # the batched solver's per-batch p99 of each class in the serving forms
+    allforms = {nme: res, **{k: v["forms"] for k, v in other.items()}}
+    batched = {fname: {cls: round(allforms[w][fname]["p99_ms"], 4)
+                       for cls, w in (("pm", "pm16k"), ("arm", "arm4k"), ("quad", "quad1k"))
+                       if fname in allforms.get(w, {})}
+               for fname in SERVING_FORMS}
+    serve = None if (args.quick or args.only or args.workload) else serving(ctx, rates=SERVING_RATES,
+                                                                            batched=batched)
     bic = None if (args.quick or args.only or args.workload) else bic_pipeline(ctx, steps=10, warmup=2)
     line = {
         "metric": METRIC,

@@ -351,6 +351,9 @@ typedef struct {
   uint64_t evictions;         /* idle pools released to make room for another class */
   uint64_t launches;          /* iteration launches (G iterations of one class each) */
   uint64_t launched_slots;    /* resident requests summed over those launches      */
+  double host_busy_s;         /* seconds the server's worker thread spent working (not
+                                 sleeping): its share of wall time shows whether the host
+                                 side limits the request rate                        */
 } cbic_server_stats;
 cbic_status cbic_server_get_stats(cbic_server* srv, cbic_server_stats* out);
 

@@ -61,7 +61,8 @@ class _ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("rounds", C.c_uint64),
                 ("inflight_bytes", C.c_size_t), ("peak_inflight_bytes", C.c_size_t), ("pool_bytes", C.c_size_t),
                 ("classes", C.c_int32), ("max_resident", C.c_int32), ("peak_pool_bytes", C.c_size_t),
-                ("evictions", C.c_uint64), ("launches", C.c_uint64), ("launched_slots", C.c_uint64)]
+                ("evictions", C.c_uint64), ("launches", C.c_uint64), ("launched_slots", C.c_uint64),
+                ("host_busy_s", C.c_double)]
 
 
 class _Mlp(C.Structure):

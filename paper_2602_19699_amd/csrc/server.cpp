@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdio>
@@ -120,6 +121,8 @@ struct cbic_server {
   size_t outstanding = 0;  // submitted and not yet done
   size_t inflight_bytes = 0, pool_bytes = 0, peak_inflight = 0, peak_pool = 0;
   uint64_t submitted = 0, completed = 0, rounds = 0, evictions = 0, launches = 0, launched_slots = 0;
+  // worker time spent in its rounds (host bookkeeping, staging, launches)
+  std::atomic<uint64_t> host_busy_ns{0};
   int max_resident = 0, resident = 0;
   std::map<std::tuple<const cbic_system*, int, std::string>, std::unique_ptr<Pool>> pools;
   std::thread worker;
@@ -468,7 +471,11 @@ void worker_main(cbic_server* srv) {
       }
     }
     bool progressed = false;
-    if (!round(srv, progressed)) {
+    const auto t_round = std::chrono::steady_clock::now();
+    const bool ok = round(srv, progressed);
+    srv->host_busy_ns += uint64_t(
+        std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t_round).count());
+    if (!ok) {
       std::lock_guard<std::mutex> lk(srv->mu);
       srv->done_cv.notify_all();
       break;
@@ -604,6 +611,7 @@ cbic_status cbic_server_get_stats(cbic_server* srv, cbic_server_stats* out) {
   out->evictions = srv->evictions;
   out->launches = srv->launches;
   out->launched_slots = srv->launched_slots;
+  out->host_busy_s = 1e-9 * double(srv->host_busy_ns.load());
   return CBIC_OK;
 }
 
