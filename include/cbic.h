@@ -136,8 +136,9 @@ typedef struct {
  *                or the line search fails the instance multiplies mu by
  *                lm_factor and retries its backward sweep (frozen with the
  *                failure's status once mu would exceed lm_mu_max), after an
- *                accepted step it divides mu by lm_factor (not below lm_mu0).
- *                Lane schedule only (not the quadruped kernel, not the server). */
+ *                accepted step it divides mu by lm_factor (not below lm_mu0);
+ *                mu carries over between the launches of one solve.  Every
+ *                system and schedule, and served requests. */
 #define CBIC_REG_CLIP 0
 #define CBIC_REG_LM 1
 
@@ -146,8 +147,10 @@ typedef struct {
  * of the backward sweep minimises the local model over the box (a bounded
  * quadratic program in the control step, solved exactly by an active-set
  * method in FP64), the feedback rows of the components held at a bound are
- * zero, and the line-search rollouts clamp their controls.  Lane schedule only
- * (not the quadruped kernel, not the server): CBIC_E_UNSUPPORTED there. */
+ * zero, and the line-search rollouts clamp their controls.  Every system and
+ * schedule (the workgroup schedule solves the box QP with one wave, a lane
+ * per control component), and served requests.  A bound that never binds
+ * changes no bit of a result. */
 
 /* schedule ids */
 #define CBIC_SCHED_LANE 1  /* one lane per instance, registers + step-major HBM          */

@@ -152,14 +152,6 @@ cbic_status check_solve(cbic_context* ctx, const cbic_system* sys, int B, int Tm
               sys->m, opts->precision, opts->schedule);
     return CBIC_E_UNSUPPORTED;
   }
-  if (opts->regularization == CBIC_REG_LM && (*L)->schedule != CBIC_SCHED_LANE) {
-    set_error("the Levenberg-Marquardt variant runs on the lane schedule only");
-    return CBIC_E_UNSUPPORTED;
-  }
-  if (std::isfinite(opts->u_max) && (*L)->schedule != CBIC_SCHED_LANE) {
-    set_error("the control bound runs on the lane schedule only");
-    return CBIC_E_UNSUPPORTED;
-  }
   return CBIC_OK;
 }
 

@@ -58,7 +58,9 @@ struct Smem {
   R A[N][LD];   // f_x
   R PA[N][LD];  // P f_x; right-hand sides of the Jacobian solves; scratch
   R Bm[N][LDB]; // f_u
-  R PB[N][LDB]; // P f_u
+  // P f_u; once Q_uu is formed, the bounded step's copy of Q_uu and the
+  // reciprocal pivots of its face factors live here (box_step)
+  alignas(8) R PB[N][LDB];
   R Kg[M][LD];  // feedback gain (m x n)
   R Qux[M][LD];
   R p[LD], Qx[LD];
@@ -69,6 +71,7 @@ struct Smem {
   double wJ[NW];
   int wok[NW];
   int flag;
+  unsigned Hq_held;  // components held at a bound by the bounded step
   WaveScratch<R> wv[NW];
 };
 
@@ -471,6 +474,215 @@ __device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
   return sm.flag == 0;
 }
 
+// ------------------------------------------------------------------ bounded control step (eq. 1)
+// FP64 storage of the bounded step inside PB (free once Q_uu is formed):
+// H = Q_uu [M][M + 1], then the reciprocal pivots of a face factor [M].
+template <class R>
+__device__ __forceinline__ double* box_H(Smem<R>& sm) {
+  return reinterpret_cast<double*>(&sm.PB[0][0]);
+}
+static_assert(sizeof(double) * (M * (M + 1) + M) <= sizeof(float) * N * LDB, "box step storage fits PB");
+
+// Wave-parallel Cholesky (rows on lanes, the pivot column broadcast from its
+// lane) of the face of H with the components in W held: their rows and
+// columns become identity.  Lane i < M keeps row i of the factor in f and
+// stores it to Lf[i]; the reciprocal pivots go to Li (lane 0 writes).  False
+// when a pivot is not positive or not finite.
+__device__ __forceinline__ bool face_factor(const double* H, unsigned W, int lane, double (&f)[M],
+                                            double (*Lf)[M + 1], double* Li) {
+  const bool row = lane < M;
+  const int ri = row ? lane : 0;
+  const bool hr = (W >> ri) & 1u;
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+    f[j] = !row ? 0.0 : (hr || ((W >> j) & 1u)) ? (ri == j ? 1.0 : 0.0) : H[min(ri, j) * (M + 1) + max(ri, j)];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double piv = bcast(f[j], j);
+    ok = ok && (piv > 0.0) && isfinite(piv);
+    const double inv = rsqrt_nr(piv);
+    if (lane == 0) Li[j] = inv;
+    const double lij = (lane == j) ? piv * inv : (lane > j && row ? f[j] * inv : 0.0);
+    f[j] = lij;
+#pragma unroll
+    for (int k = j + 1; k < M; ++k) f[k] -= lij * bcast(lij, k);
+  }
+  if (row)
+#pragma unroll
+    for (int j = 0; j < M; ++j) Lf[ri][j] = f[j];
+  wave_sync();
+  return ok;
+}
+
+// (L L^T) y = b for the factor (rows on lanes in f, all rows in Lf) and its
+// reciprocal pivots Li; lane i < M holds b_i on entry and y_i on return.
+__device__ __forceinline__ double face_solve(const double (&f)[M], const double (*Lf)[M + 1], const double* Li,
+                                             double y, int lane) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const double yj = bcast(y, j) * Li[j];
+    if (lane == j) y = yj;
+    else if (lane > j && lane < M) y -= f[j] * yj;
+  }
+  const int ri = lane < M ? lane : 0;
+#pragma unroll
+  for (int j = M - 1; j >= 0; --j) {
+    const double zj = bcast(y, j) * Li[j];
+    if (lane == j) y = zj;
+    else if (lane < j) y -= Lf[j][ri] * zj;
+  }
+  return y;
+}
+
+// The control step under the bound (paper eq. 1) once gains() has formed the
+// unconstrained gains: when the step k_k lies in the box [-umax - u_k,
+// umax - u_k] it stands (so a bound that never binds changes nothing).
+// Otherwise wave 0 minimises 0.5 d'Hd + Q_u'd over the box exactly in FP64 by
+// the primal active-set method of the lane kernels (box_qp in dev_common.hpp):
+// start from the clamped unconstrained minimiser, holding the clamped
+// components; move towards the current face's minimiser until a free
+// component meets a bound (smallest step, lowest index on ties), or at the
+// face's minimiser release the held component with the most negative
+// multiplier (lowest index on ties); at most 4 M + 4 steps.  The feedback rows
+// of the held components are zero and the free ones come from the final
+// face's factor: K = -[face factor]^-1 Q_ux with the held rows of Q_ux zeroed.
+// Returns 0 or the status bit that freezes the instance.
+template <class R>
+__device__ uint32_t box_step(Smem<R>& sm, const WaveScratch<R>& w0, double umax, int tid) {
+  double* H = box_H(sm);
+  double* Li = H + M * (M + 1);
+  if (tid < 64) {
+    const int lane = tid;
+    const bool row = lane < M;
+    const int ri = row ? lane : 0;
+    const double u = double(w0.u[ri]);
+    const double lo = -umax - u, hi = umax - u;
+    const double kk = double(sm.kk[ri]);
+    const bool inside = !row || (kk >= lo && kk <= hi);
+    unsigned W = 0, up = 0;
+    bool ok = true;
+    if (__ballot(!inside)) {
+      constexpr unsigned ALL = (1u << M) - 1u;
+      const double g = double(sm.Qu[ri]);
+      // the unconstrained minimiser -H^-1 g in FP64 from the factor of H
+      double f[M];
+      ok = face_factor(H, 0u, lane, f, sm.Lq, Li);
+      double d = face_solve(f, sm.Lq, Li, row ? -g : 0.0, lane);
+      const bool dl = row && d < lo, dh = row && d > hi;
+      d = dl ? lo : (dh ? hi : d);
+      W = unsigned(__ballot(dl || dh)) & ALL;
+      up = unsigned(__ballot(dh)) & ALL;
+      bool at_min = false;
+      for (int it = 0; it < 4 * M + 4 && ok; ++it) {
+        if (!at_min) {
+          if (W == ALL) {
+            at_min = true;
+            continue;
+          }
+          ok = face_factor(H, W, lane, f, sm.Lq, Li);
+          if (!ok) break;
+          const bool held = (W >> ri) & 1u;
+          double v = g;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const double dj = bcast(d, j);
+            if ((W >> j) & 1u) v += H[min(ri, j) * (M + 1) + max(ri, j)] * dj;
+          }
+          const double y = face_solve(f, sm.Lq, Li, (row && !held) ? -v : 0.0, lane);
+          // ratio test over the free components
+          const double pdir = y - d;
+          double t = __builtin_inf();
+          if (row && !held) {
+            if (pdir < 0.0) t = (lo - d) / pdir;
+            else if (pdir > 0.0) t = (hi - d) / pdir;
+          }
+          double alpha = 1.0;
+          int blk = -1;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const double tj = bcast(t, j);
+            if (tj < alpha) {
+              alpha = tj;
+              blk = j;
+            }
+          }
+          if (blk < 0) {
+            if (row && !held) d = y;
+            at_min = true;
+          } else {
+            const bool bup = bcast(pdir, blk) > 0.0;
+            if (row && !held)
+              d = lane == blk ? (bup ? hi : lo) : clamp_nan2(d + alpha * (y - d), lo, hi);
+            W |= 1u << blk;
+            up = bup ? (up | (1u << blk)) : (up & ~(1u << blk));
+          }
+        } else {
+          double gr = g;
+#pragma unroll
+          for (int j = 0; j < M; ++j) gr += H[min(ri, j) * (M + 1) + max(ri, j)] * bcast(d, j);
+          const double lam = ((up >> ri) & 1u) ? -gr : gr;
+          double lmin = 0.0;
+          int rel = -1;
+#pragma unroll
+          for (int j = 0; j < M; ++j) {
+            const double lj = bcast(lam, j);
+            if (((W >> j) & 1u) && lj < lmin) {
+              lmin = lj;
+              rel = j;
+            }
+          }
+          if (rel < 0) break;
+          W &= ~(1u << rel);
+          at_min = false;
+        }
+      }
+      // the final face's factor (to Lq, Lqi) and the step
+      if (ok) ok = face_factor(H, W, lane, f, sm.Lq, Li);
+      if (row) sm.kk[ri] = R(d);
+      if (lane < M) sm.Lqi[lane] = Li[lane];
+      if (lane == 0) sm.flag = ok ? 3 : 1;  // 3: the feedback rows are recomputed below
+    } else if (lane == 0) {
+      sm.flag = 0;
+    }
+    if (lane == 0) sm.Hq_held = W;
+  }
+  __syncthreads();
+  if (sm.flag == 1) return ST_CHOL_FAIL;
+  if (sm.flag == 0) return 0u;
+  // feedback rows from the face factor (FP64), the held rows zero
+  if (tid < N) {
+    const unsigned W = sm.Hq_held;
+    double y[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) y[i] = ((W >> i) & 1u) ? 0.0 : double(sm.Qux[i][tid]);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      double v = y[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) v -= sm.Lq[i][k] * y[k];
+      y[i] = v * sm.Lqi[i];
+    }
+#pragma unroll
+    for (int i = M - 1; i >= 0; --i) {
+      double v = y[i];
+#pragma unroll
+      for (int k = i + 1; k < M; ++k) v -= sm.Lq[k][i] * y[k];
+      y[i] = v * sm.Lqi[i];
+    }
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      sm.Kg[i][tid] = R(-y[i]);
+      fin = fin && isfinite(sm.Kg[i][tid]);
+    }
+    if (tid < M) fin = fin && isfinite(sm.kk[tid]);
+    if (!fin) sm.flag = 2;
+  }
+  __syncthreads();
+  return sm.flag == 2 ? ST_NONFINITE : 0u;
+}
+
 template <class R>
 struct QW {  // workspace accessors (the lane schedule's slot-major layout)
   static __device__ __forceinline__ R* xp(const LaneState<R>& w, int buf, int k, int s) {
@@ -488,9 +700,11 @@ struct QW {  // workspace accessors (the lane schedule's slot-major layout)
 };
 
 // ------------------------------------------------------------------ backward sweep
-template <class R>
+// BOX: the bounded control step of eq. 1 (umax); mu: the Levenberg-Marquardt
+// shift of Q_uu (zero for the clipped form)
+template <class R, bool BOX>
 __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
-                             int buf, R eps, int tid, R* __restrict__ blk) {
+                             int buf, R eps, int tid, R* __restrict__ blk, double mu, double umax) {
   using Q = QW<R>;
   const R dt = R(prm[O_DT]);
   const R wq = R(prm[O_WQ]), wv = R(prm[O_WV]), wu = R(prm[O_WU]), wT = R(prm[O_WT]);
@@ -578,10 +792,21 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       R v = R(0);
       for (int t = 0; t < N; ++t) v += sm.Bm[t][i] * sm.PB[t][j];
       sm.Quu[i][j] = double(v) + (i == j ? double(dmax(R(2) * wu, eps)) : 0.0);
+      // the Levenberg-Marquardt shift (zero otherwise: adding it changes no bit)
+      if (i == j) sm.Quu[i][j] += mu;
     }
     __syncthreads();
     if (tid < N) sm.P[tid][tid] += dmax(R(2) * (tid < NQ ? wq : wv), eps);
+    if constexpr (BOX) {
+      // Q_uu for the bounded step (gains() reuses its storage in the mixed form)
+      if (tid < M * M) box_H(sm)[(tid / M) * (M + 1) + tid % M] = sm.Quu[tid / M][tid % M];
+      __syncthreads();
+    }
     if (!gains(sm, tid)) return sm.flag == 1 ? ST_CHOL_FAIL : ST_NONFINITE;
+    if constexpr (BOX) {
+      const uint32_t b = box_step(sm, w0, umax, tid);
+      if (b) return b;
+    }
     // store the gains
     {
       R* dK = Q::Kp(w, k, s);
@@ -611,9 +836,10 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
 // ------------------------------------------------------------------ line-search trial (one wave)
 // Closed-loop rollout of wave `wid` with step alpha; writes the trajectory
 // when `write`; early stop once the partial cost reaches Jcur (costs >= 0).
-template <class R>
+// With BOX the trial's controls are clamped into [-umax, umax] (eq. 1).
+template <class R, bool BOX>
 __device__ __forceinline__ double wave_trial(Smem<R>& sm, const double* __restrict__ prm, const LaneState<R>& w, int s, int T,
-                             int buf, R alpha, double Jcur, bool write, int lane, int wid, int& steps) {
+                             int buf, R alpha, double Jcur, bool write, int lane, int wid, int& steps, R umax) {
   using Q = QW<R>;
   WaveScratch<R>& ws = sm.wv[wid];
   const R dt = R(prm[O_DT]);
@@ -657,7 +883,10 @@ __device__ __forceinline__ double wave_trial(Smem<R>& sm, const double* __restri
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
-      if (c < M && part == 0) ws.u[c] = uk + alpha * kk + acc;
+      if (c < M && part == 0) {
+        const R v = uk + alpha * kk + acc;
+        ws.u[c] = BOX ? clamp_nan(v, umax) : v;
+      }
     }
     wave_sync();
     Jh += double(wave_cost(sm, ws.x, ws.u, prm, lane, false));
@@ -684,7 +913,7 @@ __global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, 
                                                  const int32_t* __restrict__ slots, int Tmax,
                                                  const int32_t* __restrict__ Tin, const int32_t* __restrict__ perm,
                                                  const double* __restrict__ x0, const double* __restrict__ U0,
-                                                 int max_iter, double* __restrict__ trace) {
+                                                 int max_iter, double* __restrict__ trace, double umax) {
   using Q = QW<R>;
   __shared__ WaveSmem<R, 1> sm;
   const int g = blockIdx.x, tid = threadIdx.x;
@@ -709,7 +938,8 @@ __global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, 
   double J = 0.0;
   for (int k = 0; k < T; ++k) {
     if (lane < M) {
-      const R v = U0 ? R(U0[(size_t(b) * Tmax + k) * M + lane]) : R(0);
+      // the warm start is clamped into the box of eq. 1 (umax infinite: none)
+      const R v = clamp_nan(U0 ? R(U0[(size_t(b) * Tmax + k) * M + lane]) : R(0), R(umax));
       ws.u[lane] = v;
       Q::up(w, 0, k, s)[lane] = v;
     }
@@ -742,10 +972,14 @@ __global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, 
   }
 }
 
-template <class R>
+template <class R, bool BOX, bool LM>
 // Two workgroups per CU (registers capped for two, some values spill): the
 // per-step chain is latency-bound, and a second resident instance per CU
 // hides more of it than the spills cost (measured: FP32 -26 %, FP64 -7 %).
+// BOX: the variant with the control bound of eq. 1 (sp.umax finite).  LM: the
+// Levenberg-Marquardt variant (sp.reg = 1), in which a failed Cholesky or line search
+// multiplies mu by mu_fac and retries the sweep while mu stays within mu_max;
+// an accepted step divides it (not below mu0); mu carries over between launches.
 __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                     const int32_t* __restrict__ slots, SolveParams sp,
                                                     int iters_this_launch, IterTrace tr,
@@ -766,69 +1000,88 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
   int buf = w.cur[s];
   int nsweep = w.work[4 * s], npass = w.work[4 * s + 1], nread = w.work[4 * s + 2], nwrite = w.work[4 * s + 3];
   const R eps = R(sp.eps);
+  constexpr bool lm = LM;
+  double mu = lm ? (nsweep == 0 ? sp.mu0 : w.mu[s]) : 0.0;
   for (int it = 0; it < iters_this_launch && st == 0; ++it) {
     if (iters >= sp.max_iter) {
       st = ST_MAX_ITER;
       break;
     }
-    ++nsweep;
-    const uint32_t bad = backward(sm, prm, w, s, T, buf, eps, tid, dblk + size_t(s) * CH * DB);
-    if (bad) {
-      if (tr.j && tid == 0) tr.j[size_t(b) * sp.max_iter + iters] = -1;
-      st = bad;
-      break;
-    }
-    // line search: rounds of NW parallel trials, then (if the accepted step
-    // is not alpha = 1, which wave 0 wrote while trying it) one commit rollout;
-    // a single call site keeps the kernel's register footprint down
     int acc = -1;
     double Jn = J;
-    bool commit = false;
-    for (int j0 = 0;;) {
-      const int j = commit ? acc : j0 + wid;
-      const bool run = commit ? (wid == 0) : (j < sp.ls_trials);
-      double Jh = __builtin_nan("");
-      int steps = 0;
-      if (run) {
-        double alpha = 1.0;
-        for (int q = 0; q < j; ++q) alpha *= sp.beta;
-        Jh = wave_trial(sm, prm, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, commit || j == 0, lane,
-                        wid, steps);
-      }
-      if (lane == 0) {
-        sm.wJ[wid] = Jh;
-        sm.wok[wid] = steps;
-      }
-      __syncthreads();
-      ++npass;
-      if (commit) {
-        Jn = sm.wJ[0];
-        nread += T;
-        nwrite += T;
-        __syncthreads();
+    uint32_t fail = 0;
+    for (;;) {
+      ++nsweep;
+      const uint32_t bad = backward<R, BOX>(sm, prm, w, s, T, buf, eps, tid, dblk + size_t(s) * CH * DB, mu, sp.umax);
+      if (bad) {
+        if (lm && bad == ST_CHOL_FAIL && mu * sp.mu_fac <= sp.mu_max) {
+          mu *= sp.mu_fac;
+          continue;
+        }
+        fail = bad;
         break;
       }
-      int longest = 0;
-      for (int q = 0; q < NW; ++q) {
-        longest = max(longest, sm.wok[q]);
-        const double v = sm.wJ[q];
-        if (acc < 0 && j0 + q < sp.ls_trials && isfinite(v) && v < J) {
-          acc = j0 + q;
-          Jn = v;
+      // line search: rounds of NW parallel trials, then (if the accepted step
+      // is not alpha = 1, which wave 0 wrote while trying it) one commit
+      // rollout; a single call site keeps the kernel's register footprint down
+      acc = -1;
+      Jn = J;
+      bool commit = false;
+      for (int j0 = 0;;) {
+        const int j = commit ? acc : j0 + wid;
+        const bool run = commit ? (wid == 0) : (j < sp.ls_trials);
+        double Jh = __builtin_nan("");
+        int steps = 0;
+        if (run) {
+          double alpha = 1.0;
+          for (int q = 0; q < j; ++q) alpha *= sp.beta;
+          Jh = wave_trial<R, BOX>(sm, prm, w, s, T, buf, R(alpha), commit ? __builtin_inf() : J, commit || j == 0,
+                                  lane, wid, steps, R(sp.umax));
         }
+        if (lane == 0) {
+          sm.wJ[wid] = Jh;
+          sm.wok[wid] = steps;
+        }
+        __syncthreads();
+        ++npass;
+        if (commit) {
+          Jn = sm.wJ[0];
+          nread += T;
+          nwrite += T;
+          __syncthreads();
+          break;
+        }
+        int longest = 0;
+        for (int q = 0; q < NW; ++q) {
+          longest = max(longest, sm.wok[q]);
+          const double v = sm.wJ[q];
+          if (acc < 0 && j0 + q < sp.ls_trials && isfinite(v) && v < J) {
+            acc = j0 + q;
+            Jn = v;
+          }
+        }
+        if (j0 == 0) nwrite += sm.wok[0];
+        nread += longest;
+        __syncthreads();
+        j0 += NW;
+        if (acc == 0 || (acc < 0 && j0 >= sp.ls_trials)) break;
+        if (acc > 0) commit = true;
       }
-      if (j0 == 0) nwrite += sm.wok[0];
-      nread += longest;
-      __syncthreads();
-      j0 += NW;
-      if (acc == 0 || (acc < 0 && j0 >= sp.ls_trials)) break;
-      if (acc > 0) commit = true;
-    }
-    if (tr.j && tid == 0) tr.j[size_t(b) * sp.max_iter + iters] = acc;
-    if (acc < 0) {
-      st = ST_LS_FAILED;
+      if (acc < 0) {
+        if (lm && mu * sp.mu_fac <= sp.mu_max) {
+          mu *= sp.mu_fac;
+          continue;
+        }
+        fail = ST_LS_FAILED;
+      }
       break;
     }
+    if (tr.j && tid == 0) tr.j[size_t(b) * sp.max_iter + iters] = fail ? -1 : acc;
+    if (fail) {
+      st = fail;
+      break;
+    }
+    if (lm) mu = fmax(mu / sp.mu_fac, sp.mu0);
     buf ^= 1;
     const double Jold = J;
     J = Jn;
@@ -849,6 +1102,7 @@ __global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__
     w.work[4 * s + 1] = npass;
     w.work[4 * s + 2] = nread;
     w.work[4 * s + 3] = nwrite;
+    if (lm) w.mu[s] = mu;
   }
 }
 
@@ -1043,13 +1297,12 @@ struct QuadLaunch {
 
   static hipError_t init(const double* prm, void* base, int Bcap, int Tcap, int nthreads, const int32_t* slots,
                          int Tmax, const int32_t* Tin, const int32_t* perm, const double* x0, const double* U0,
-                         int max_iter, double* trace, double /*umax: the bound is not offered here*/,
-                         hipStream_t st) {
+                         int max_iter, double* trace, double umax, hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
     // one wave per instance (quad_init is built for 64-thread workgroups)
     hipLaunchKernelGGL(quad_init<R>, dim3(nthreads), dim3(64), 0, st, prm, w, nthreads, slots, Tmax, Tin, perm,
-                       x0, U0, max_iter, trace);
+                       x0, U0, max_iter, trace, umax);
     return hipGetLastError();
   }
 
@@ -1058,8 +1311,23 @@ struct QuadLaunch {
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
-    hipLaunchKernelGGL(quad_iterate<R>, dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, to_dev(sp), G,
-                       tr, blocks(base, Bcap, Tcap));
+    // the bounded variant is a kernel of its own, so that the unbounded one
+    // keeps its register allocation and shared-memory footprint
+    const SolveParams d = to_dev(sp);
+    R* blk = blocks(base, Bcap, Tcap);
+    const bool box = __builtin_isfinite(sp.umax), lm = sp.reg == 1;
+    if (box && lm)
+      hipLaunchKernelGGL((quad_iterate<R, true, true>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, d,
+                         G, tr, blk);
+    else if (box)
+      hipLaunchKernelGGL((quad_iterate<R, true, false>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
+                         d, G, tr, blk);
+    else if (lm)
+      hipLaunchKernelGGL((quad_iterate<R, false, true>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
+                         d, G, tr, blk);
+    else
+      hipLaunchKernelGGL((quad_iterate<R, false, false>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
+                         d, G, tr, blk);
     return hipGetLastError();
   }
 

@@ -529,10 +529,6 @@ cbic_status cbic_server_submit(cbic_server* srv, const cbic_system* sys, int32_t
     set_error("no kernel for this system and precision");
     return CBIC_E_UNSUPPORTED;
   }
-  if (L->schedule != CBIC_SCHED_LANE && (opts->regularization != CBIC_REG_CLIP || std::isfinite(opts->u_max))) {
-    set_error("the Levenberg-Marquardt variant and the control bound run on the lane schedule only");
-    return CBIC_E_UNSUPPORTED;
-  }
   if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != solve_params(opts).eps) {
     set_error("this LQ system's clipped Hessians were built for psd_eps %g (a served request cannot rebuild "
               "them under running solves)", sys->dev_eps);

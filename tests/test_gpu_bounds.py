@@ -151,23 +151,56 @@ def test_bounded_with_levenberg_marquardt(ctx):
     _feasible(g, 10.0)
 
 
-def test_bound_rejected_where_unsupported(ctx):
+def test_invalid_bounds_rejected(ctx):
     from paper_2602_19699_amd import cbic
-    p = I.quad_params(0)
-    with pytest.raises(cbic.CbicError) as e:
-        gpu_solve(ctx, QUAD, p, I.quad_x0(2, p, seed=7), 10, u_max=5.0)
-    assert e.value.code == cbic.E_UNSUPPORTED
     kind, p, x0, T, _ = I.workload("pm64")
     for bad in (0.0, -1.0, float("nan")):
         with pytest.raises(cbic.CbicError) as e:
             gpu_solve(ctx, kind, p, x0[:2], T, u_max=bad)
         assert e.value.code == cbic.E_INVALID
-    # the server serves bounded requests of the lane systems (its class test
-    # checks them against the batched solver) and refuses them for the quadruped
-    srv = cbic.Server(ctx, slots_per_class=4, t_max=200)
-    q = cbic.System(ctx, QUAD, I.quad_params(0))
-    with pytest.raises(cbic.CbicError) as e:
-        srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=7)[0], 50, opts=cbic.Options(u_max=5.0))
-    assert e.value.code == cbic.E_UNSUPPORTED
-    srv.close()
-    q.close()
+
+
+def _quad_case():
+    p = I.quad_params(0)
+    return p, I.quad_x0(8, p, seed=7), np.array([40, 12, 33, 40, 5, 27, 40, 18], np.int32)
+
+
+def test_bounded_quadruped(ctx):
+    # the workgroup kernel's bounded step (the FP64 box QP on wave 0, the
+    # feedback rows of the free components from the face factor) and clamped
+    # rollouts, against the oracle in both forms
+    p, x0, T = _quad_case()
+    for um in (5.0, 2.0):
+        o = dict(max_iter=12, u_max=um)
+        g = gpu_solve(ctx, QUAD, p, x0, 40, T=T, trace=True, **o)
+        oo = oracle_opts(**o)
+        r, rps = oracle_ensemble(QUAD, p, x0, 40, T=T, opts=oo)
+        check_parity(g, QUAD, p, x0, 40, T, oo, r, rps, label=f"quad bounded {um}")
+        _feasible(g, um)
+        assert np.mean(np.abs(g["U"]) == um) > 0.05  # the bound binds
+    o = dict(max_iter=12, u_max=5.0)
+    gm = gpu_solve(ctx, QUAD, p, x0, 40, T=T, trace=True, precision=1, **o)
+    oo = oracle_opts(**o)
+    r32, rps32 = oracle_ensemble(QUAD, p, x0, 40, T=T, opts=oo, rel_step=2.0 ** -24, probe32=True)
+    check_parity(gm, QUAD, p, x0, 40, T, oo, r32, rps32, tol=1e-4, onset_tol=1e-6, mixed=True,
+                 label="quad bounded mixed")
+    _feasible(gm, 5.0)
+
+
+def test_bounded_quadruped_loose_bound_warm_start_and_launch_splits(ctx):
+    p, x0, T = _quad_case()
+    for prec in (0, 1):
+        a = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=8, precision=prec)
+        b = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=8, precision=prec, u_max=1e30)
+        for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"precision {prec} field {k}")
+        c = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=8, precision=prec, u_max=4.0)
+        d = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=8, precision=prec, u_max=4.0, iters_per_launch=3)
+        for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"):
+            np.testing.assert_array_equal(c[k], d[k], err_msg=f"launch split, precision {prec} field {k}")
+    U0 = np.random.default_rng(2).normal(size=(8, 40, 12)) * 10.0
+    g = gpu_solve(ctx, QUAD, p, x0, 40, T=T, U0=U0, max_iter=0, u_max=5.0)
+    r = orc.solve_batch(QUAD, p, x0, 40, T=T, U0=U0, opts=oracle_opts(max_iter=0, u_max=5.0))
+    for b in range(8):
+        np.testing.assert_array_equal(g["U"][b, :T[b]], np.clip(U0[b, :T[b]], -5.0, 5.0))
+    assert np.all(rel(g["J"], r.J) <= 1e-13)

@@ -126,27 +126,36 @@ def test_lm_group_widths_and_launch_splits_identical(ctx, kind):
             np.testing.assert_array_equal(ref[k], g[k], err_msg=f"{o} field {k}")
 
 
-def test_lm_rejected_where_unsupported(ctx):
-    import torch
-    from paper_2602_19699_amd import cbic
-    # the workgroup-per-instance schedule has no LM variant
+def test_lm_quadruped(ctx):
+    # the workgroup kernel's Levenberg-Marquardt variant against the oracle:
+    # Q_uu + mu I, no clip (the quadruped's cost Hessians are diagonal and
+    # non-negative), retries after failed line searches with mu raised, mu
+    # carried across launches
     p = I.quad_params(0)
-    with pytest.raises(cbic.CbicError) as e:
-        gpu_solve(ctx, QUAD, p, I.quad_x0(2, p, seed=7), 10, **LM)
-    assert e.value.code == cbic.E_UNSUPPORTED
+    x0 = I.quad_x0(8, p, seed=7)
+    T = np.array([40, 12, 33, 40, 5, 27, 40, 18], np.int32)
+    o = dict(max_iter=12, **LM)
+    g = gpu_solve(ctx, QUAD, p, x0, 40, T=T, trace=True, **o)
+    oo = oracle_opts(**o)
+    r, rps = oracle_ensemble(QUAD, p, x0, 40, T=T, opts=oo)
+    check_parity(g, QUAD, p, x0, 40, T, oo, r, rps, label="quad lm")
+    assert np.all(g["work"][:, 0] >= g["iters"])  # sweeps, retries included
+    gm = gpu_solve(ctx, QUAD, p, x0, 40, T=T, trace=True, precision=1, **o)
+    r32, rps32 = oracle_ensemble(QUAD, p, x0, 40, T=T, opts=oo, rel_step=2.0 ** -24, probe32=True)
+    check_parity(gm, QUAD, p, x0, 40, T, oo, r32, rps32, tol=1e-4, onset_tol=1e-6, mixed=True, label="quad lm mixed")
+    # mu carries over between launches: split launches give the same bits
+    for prec in (0, 1):
+        a = gpu_solve(ctx, QUAD, p, x0, 40, T=T, precision=prec, **o)
+        b = gpu_solve(ctx, QUAD, p, x0, 40, T=T, precision=prec, iters_per_launch=2, **o)
+        for k in ("X", "U", "J", "iters", "status", "work"):
+            np.testing.assert_array_equal(a[k], b[k], err_msg=f"precision {prec} field {k}")
+
+
+def test_lm_invalid_parameters(ctx):
+    from paper_2602_19699_amd import cbic
     # invalid LM parameters
     kind, p, x0, T, _ = I.workload("pm64")
     for bad in (dict(lm_mu0=0.0), dict(lm_factor=1.0), dict(lm_mu_max=1e-9), dict(regularization=2)):
         with pytest.raises(cbic.CbicError) as e:
             gpu_solve(ctx, kind, p, x0[:2], T, **{**LM, **bad})
         assert e.value.code == cbic.E_INVALID
-    # the serving runtime takes the LM variant for lane systems (its class
-    # test checks them against the batched solver), not for the quadruped
-    srv = cbic.Server(ctx, slots_per_class=4, t_max=200)
-    q = cbic.System(ctx, QUAD, I.quad_params(0))
-    with pytest.raises(cbic.CbicError) as e:
-        srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=7)[0], 50, opts=cbic.Options(regularization=1))
-    assert e.value.code == cbic.E_UNSUPPORTED
-    srv.close()
-    q.close()
-    torch.cuda.synchronize()

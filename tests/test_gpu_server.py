@@ -97,27 +97,32 @@ def test_admission_respects_the_memory_cap(ctx):
 
 def test_requests_are_served_with_their_own_options(ctx):
     # requests of one system and precision with different result-affecting
-    # options (budget, stop rule, control bound, Levenberg-Marquardt) form
+    # options (budget, stop rule, control bound, Levenberg-Marquardt; lane and
+    # workgroup schedules) form
     # classes of their own: each result is the batched solver's under that
     # request's options, bit for bit
     from paper_2602_19699_amd import cbic
     p = I.point_mass_params(0)
     pa = I.planar3_params(0)
+    pq = I.quad_params(0)
     sp, sa = cbic.System(ctx, I.SYS_POINT_MASS, p), cbic.System(ctx, I.SYS_PLANAR3, pa)
-    x0, xa = I.point_mass_x0(12, 4), I.planar3_x0(12, 5)
+    sq = cbic.System(ctx, I.SYS_QUAD_SYNTH, pq)
+    x0, xa, xq = I.point_mass_x0(12, 4), I.planar3_x0(12, 5), I.quad_x0(12, pq, seed=6)
     variants = [dict(max_iter=7), dict(max_iter=30, stop_mode=1, rtol=1e-9), dict(max_iter=20, u_max=6.0),
                 dict(max_iter=20, regularization=1), dict(max_iter=15, precision=1, u_max=6.0)]
     srv = cbic.Server(ctx, slots_per_class=32, t_max=80, iters_per_launch=3)
     jobs = []
     for vi, v in enumerate(variants):
-        for sysm, kind, xs, T in ((sp, I.SYS_POINT_MASS, x0, 60), (sa, I.SYS_PLANAR3, xa, 70)):
+        for sysm, kind, xs, T in ((sp, I.SYS_POINT_MASS, x0, 60), (sa, I.SYS_PLANAR3, xa, 70),
+                                  (sq, I.SYS_QUAD_SYNTH, xq, 30)):
             for b in range(0, 12, 3):
                 jobs.append((vi, kind, b, T, srv.submit(sysm, xs[b], T, opts=cbic.Options(**v))))
     srv.drain()
     st = srv.stats()
-    assert st["classes"] == 2 * len(variants)
+    assert st["classes"] == 3 * len(variants)
     for vi, v in enumerate(variants):
-        for kind, xs, T, prm in ((I.SYS_POINT_MASS, x0, 60, p), (I.SYS_PLANAR3, xa, 70, pa)):
+        for kind, xs, T, prm in ((I.SYS_POINT_MASS, x0, 60, p), (I.SYS_PLANAR3, xa, 70, pa),
+                                 (I.SYS_QUAD_SYNTH, xq, 30, pq)):
             g = gpu_solve(ctx, kind, prm, xs, T, **v)
             for vj, k, b, T2, t in jobs:
                 if vj == vi and k == kind:
@@ -127,6 +132,7 @@ def test_requests_are_served_with_their_own_options(ctx):
     srv.close()
     sp.close()
     sa.close()
+    sq.close()
 
 
 def test_invalid_requests_are_refused_and_the_server_keeps_serving(ctx):
@@ -140,12 +146,6 @@ def test_invalid_requests_are_refused_and_the_server_keeps_serving(ctx):
         with pytest.raises(cbic.CbicError) as e:
             srv.submit(sysm, x0[0], 30, opts=cbic.Options(**bad))
         assert e.value.code == cbic.E_INVALID, bad
-    # the workgroup-schedule system takes neither the bound nor the LM variant
-    q = cbic.System(ctx, I.SYS_QUAD_SYNTH, I.quad_params(0))
-    for v in (dict(u_max=5.0), dict(regularization=1)):
-        with pytest.raises(cbic.CbicError) as e:
-            srv.submit(q, I.quad_x0(1, I.quad_params(0), seed=2)[0], 20, opts=cbic.Options(**v))
-        assert e.value.code == cbic.E_UNSUPPORTED
     # an LQ system built for another clipping floor
     lq = cbic.System(ctx, I.SYS_LQ, I.lq_random(2, 1, seed=1))
     with pytest.raises(cbic.CbicError) as e:
@@ -157,7 +157,7 @@ def test_invalid_requests_are_refused_and_the_server_keeps_serving(ctx):
     g = gpu_solve(ctx, I.SYS_POINT_MASS, p, x0[1:], 30, max_iter=10)
     assert r["J"] == g["J"][0]
     srv.close()
-    for s_ in (sysm, q, lq):
+    for s_ in (sysm, lq):
         s_.close()
 
 
