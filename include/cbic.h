@@ -240,7 +240,8 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
  *    CBIC_E_OOM before anything is launched (64 MiB: e.g. about 7000
  *    point-mass instances of horizon 100 in the mixed form, 3500 in FP64);
  *  - opts->flags must not hold CBIC_FLAG_GRAPH or CBIC_FLAG_TIMING, and an LQ
- *    system must have been built or last solved with the same psd_eps
+ *    system must already hold a parameter block for the solve's psd_eps (the
+ *    one it was created with, 1e-6, or one an earlier cbic_solve_batch built)
  *    (CBIC_E_INVALID otherwise);
  *  - every call on one GPU uses that GPU's one array, whatever its context or
  *    stream: calls that overlap in time on a GPU race and give undefined

@@ -14,6 +14,7 @@
 namespace cbic {
 const char* last_error();
 bool make_device_block(cbic_system* s, double eps);
+bool build_device_block(const cbic_system* s, double eps, std::vector<double>& d);
 bool validate_params(int kind, const double* p, size_t np, int* n, int* m);
 }  // namespace cbic
 
@@ -155,14 +156,53 @@ cbic_status check_solve(cbic_context* ctx, const cbic_system* sys, int B, int Tm
   return CBIC_OK;
 }
 
+// The device parameter block of a solve with clip floor eps: the system's own
+// block, or for an LQ system whose clipped constant Hessians were built for
+// another eps, the block for that eps (built, uploaded on the solve's stream
+// and kept on first use when may_build; CBIC_E_INVALID otherwise).  No device
+// synchronisation: solves with other floors on other streams keep their blocks.
+cbic_status param_block(cbic_system* s, double eps, hipStream_t stream, bool may_build, const double** out) {
+  if (s->kind != CBIC_SYS_LQ || s->dev_eps == eps) {
+    *out = s->d_prm;
+    return CBIC_OK;
+  }
+  auto it = s->lq_blocks.find(eps);
+  if (it == s->lq_blocks.end()) {
+    if (!may_build) {
+      set_error("no parameter block of this LQ system for psd_eps %g yet (cbic_solve_batch builds it)", eps);
+      return CBIC_E_INVALID;
+    }
+    std::vector<double> h;
+    if (!build_device_block(s, eps, h)) {
+      set_error("cannot build the LQ parameter block");
+      return CBIC_E_INVALID;
+    }
+    double* d = nullptr;
+    hipError_t e = hipMalloc(&d, h.size() * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc of the LQ parameter block failed: %s", hipGetErrorString(e));
+      return CBIC_E_OOM;
+    }
+    it = s->lq_blocks.emplace(eps, std::make_pair(std::move(h), d)).first;
+    HIP_TRY(hipMemcpyAsync(d, it->second.first.data(), it->second.first.size() * sizeof(double),
+                           hipMemcpyHostToDevice, stream));
+  }
+  *out = it->second.second;
+  return CBIC_OK;
+}
+
 // Enqueue one solve on `stream` with its workspace at `base`: ws_main bytes
 // of the launcher's layout followed by the horizon sort's scratch.  The caller
 // holds ctx->mu with the context's device current.  Allocates nothing itself
 // (a graph launch builds its cached graph on first use).
-cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launcher* L, const SolveParamsH& sp,
-                          int B, int Tmax, const int32_t* d_T, const double* d_x0, const double* d_U0,
-                          const cbic_solve_opts* opts, const cbic_outputs* out, char* base, size_t ws_main,
-                          hipStream_t stream) {
+cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const double* prm, const Launcher* L,
+                          const SolveParamsH& sp, int B, int Tmax, const int32_t* d_T, const double* d_x0,
+                          const double* d_U0, const cbic_solve_opts* opts, const cbic_outputs* out, char* base,
+                          size_t ws_main, hipStream_t stream) {
+  // the launches below report through hipGetLastError: drop an error another
+  // call on this thread left behind
+  (void)hipGetLastError();
   int32_t* hist = reinterpret_cast<int32_t*>(base + ws_main);
   int32_t* perm = reinterpret_cast<int32_t*>(base + ws_main + ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256);
   if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
@@ -173,7 +213,7 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launc
   // iterations that never run keep the marker -2
   if (out->jtrace && opts->max_iter > 0) HIP_TRY(launch_fill_i32(out->jtrace, size_t(B) * opts->max_iter, -2, stream));
   const IterTrace tr{out->cost_trace, out->jtrace};
-  HIP_TRY(L->init(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
+  HIP_TRY(L->init(prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, sp.umax, stream));
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
   int group = opts->group_lanes;
@@ -187,12 +227,12 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launc
     const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
     if (!graph) {
       for (int c = 0; c < chunks; ++c)
-        HIP_TRY(L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
+        HIP_TRY(L->iterate(prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
     } else {
       char key[512];
       std::snprintf(key, sizeof key,
                     "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
-                    (const void*)L, (const void*)sys->d_prm, (const void*)base, B, Tmax, G, chunks, group,
+                    (const void*)L, (const void*)prm, (const void*)base, B, Tmax, G, chunks, group,
                     sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
                     (void*)out->jtrace, sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
       auto it = ctx->graphs.find(key);
@@ -201,7 +241,7 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launc
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int c = 0; c < chunks && e == hipSuccess; ++c)
-          e = L->iterate(sys->d_prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
+          e = L->iterate(prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -219,7 +259,7 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const Launc
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[2], stream));
   FinalOutH fo{out->X, out->U, out->J, out->iters, out->status, out->Vbar, out->Vx, out->xK, out->cost_trace,
                out->work};
-  HIP_TRY(L->finalize(sys->d_prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
+  HIP_TRY(L->finalize(prm, base, B, Tmax, B, nullptr, Tmax, opts->max_iter, opts->lookahead_K, fo, stream));
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[3], stream));
   ctx->timed = ctx->timed || timing;
   return CBIC_OK;
@@ -369,6 +409,7 @@ cbic_status cbic_system_create(cbic_context* ctx, cbic_system_kind kind, const d
   }
   s->dev_eps = 1e-6;
   if (ctx) {
+    s->device = ctx->device;
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess) e = hipMalloc(&s->d_prm, s->dev.size() * sizeof(double));
     if (e == hipSuccess)
@@ -394,9 +435,10 @@ cbic_status cbic_system_dims(const cbic_system* s, int32_t* n, int32_t* m) {
 cbic_status cbic_system_destroy(cbic_system* s) {
   if (!s) { set_error("sys is NULL"); return CBIC_E_INVALID; }
   if (s->d_prm) {
-    (void)hipSetDevice(s->ctx->device);
+    (void)hipSetDevice(s->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(s->d_prm);
+    for (auto& kv : s->lq_blocks) (void)hipFree(kv.second.second);
   }
   delete s;
   return CBIC_OK;
@@ -428,21 +470,17 @@ cbic_status cbic_solve_batch(cbic_context* ctx, const cbic_system* sys, int32_t 
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t stream = static_cast<hipStream_t>(stream_v);
   HIP_TRY(hipSetDevice(ctx->device));
-  cbic_system* ms = const_cast<cbic_system*>(sys);
-  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != sp.eps) {
-    // the LQ Hessians are constant; their clip is refreshed for a new eps
-    // (none for the Levenberg-Marquardt variant)
-    HIP_TRY(hipDeviceSynchronize());
-    make_device_block(ms, sp.eps);
-    HIP_TRY(hipMemcpy(ms->d_prm, ms->dev.data(), ms->dev.size() * sizeof(double), hipMemcpyHostToDevice));
-    ms->dev_eps = sp.eps;
-  }
+  // the LQ Hessians are constant; a solve with another clip floor (or the
+  // Levenberg-Marquardt variant, which clips nothing) uses a block of its own
+  const double* prm = nullptr;
+  st = param_block(const_cast<cbic_system*>(sys), sp.eps, stream, true, &prm);
+  if (st) return st;
   const size_t ws_main = L->ws_bytes(B, Tmax);
   st = ensure_ws(ctx, ws_main + sort_bytes(B, Tmax));
   if (st) return st;
   if (ctx->have_last && ctx->last_stream != stream) HIP_TRY(hipStreamWaitEvent(stream, ctx->done_ev, 0));
-  st = enqueue_solve(ctx, sys, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->ws), ws_main,
-                     stream);
+  st = enqueue_solve(ctx, sys, prm, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->ws),
+                     ws_main, stream);
   if (st) return st;
   HIP_TRY(hipEventRecord(ctx->done_ev, stream));
   ctx->last_stream = stream;
@@ -461,11 +499,6 @@ cbic_status cbic_solve_batch_noalloc(cbic_context* ctx, const cbic_system* sys, 
     return CBIC_E_INVALID;
   }
   const SolveParamsH sp = solve_params(opts);
-  if (sys->kind == CBIC_SYS_LQ && sys->dev_eps != sp.eps) {
-    set_error("this LQ system's clipped Hessians were built for psd_eps %g, not %g (a refresh needs a "
-              "synchronous copy; cbic_solve_batch does it)", sys->dev_eps, sp.eps);
-    return CBIC_E_INVALID;
-  }
   const size_t ws_main = L->ws_bytes(B, Tmax);
   const size_t need = ws_main + sort_bytes(B, Tmax);
   if (need > kScratchBytes) {
@@ -479,7 +512,10 @@ cbic_status cbic_solve_batch_noalloc(cbic_context* ctx, const cbic_system* sys, 
     return CBIC_E_HIP;
   }
   HIP_TRY(hipSetDevice(ctx->device));
-  return enqueue_solve(ctx, sys, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->scratch),
+  const double* prm = nullptr;
+  st = param_block(const_cast<cbic_system*>(sys), sp.eps, static_cast<hipStream_t>(stream_v), false, &prm);
+  if (st) return st;
+  return enqueue_solve(ctx, sys, prm, L, sp, B, Tmax, d_T, d_x0, d_U0, opts, out, static_cast<char*>(ctx->scratch),
                        ws_main, static_cast<hipStream_t>(stream_v));
 }
 

@@ -432,6 +432,7 @@ cbic_status cbic_mlp_forward(cbic_context* ctx, const cbic_mlp* net, int32_t B, 
   }
   if (B == 0) return CBIC_OK;
   HIP_TRY(hipSetDevice(ctx->device));
+  (void)hipGetLastError();  // launch errors below are this call's, not a stale one
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*net);
   const MlpLds L = mlp_lds(net->in_dim, net->width, net->depth, net->out_dim);
@@ -471,6 +472,7 @@ cbic_status cbic_bic_select(cbic_context* ctx, const cbic_mlp* net, int32_t Bc, 
     return CBIC_E_INVALID;
   }
   HIP_TRY(hipSetDevice(ctx->device));
+  (void)hipGetLastError();  // launch errors below are this call's, not a stale one
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*net);
   const MlpLds L = mlp_lds(net->in_dim, net->width, net->depth, net->out_dim);
@@ -531,6 +533,7 @@ cbic_status cbic_actor_rollout(cbic_context* ctx, const cbic_system* sys, const 
     return CBIC_E_INVALID;
   }
   HIP_TRY(hipSetDevice(ctx->device));
+  (void)hipGetLastError();  // launch errors below are this call's, not a stale one
   hipStream_t st = static_cast<hipStream_t>(stream);
   const MlpDev d = dev_mlp(*actor);
   const MlpLds w = mlp_lds(actor->in_dim, actor->width, actor->depth, actor->out_dim);

@@ -127,9 +127,8 @@ static bool all_finite(const double* p, size_t n) {
   return true;
 }
 
-bool make_device_block(cbic_system* s, double eps) {
+bool build_device_block(const cbic_system* s, double eps, std::vector<double>& d) {
   const std::vector<double>& p = s->params;
-  std::vector<double>& d = s->dev;
   d.clear();
   switch (s->kind) {
     case CBIC_SYS_POINT_MASS: {
@@ -201,6 +200,8 @@ bool make_device_block(cbic_system* s, double eps) {
       return false;
   }
 }
+
+bool make_device_block(cbic_system* s, double eps) { return build_device_block(s, eps, s->dev); }
 
 bool validate_params(int kind, const double* p, size_t np, int* n, int* m) {
   if (!p) {

@@ -144,5 +144,10 @@ struct cbic_system {
   std::vector<double> dev;     // derived device block
   double dev_eps = 1e-6;       // eps the LQ block was clipped with
   cbic_context* ctx = nullptr;
+  int device = -1;             // the context's device (the system may outlive its context)
   double* d_prm = nullptr;     // device copy of `dev`
+  // LQ systems: the blocks for other clip floors solved with (their clipped
+  // constant Hessians depend on it), keyed by psd_eps; each host copy lives as
+  // long as the system, since an asynchronous upload reads it
+  std::map<double, std::pair<std::vector<double>, double*>> lq_blocks;
 };

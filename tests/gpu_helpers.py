@@ -16,17 +16,19 @@ def gpu_solve(ctx, kind, params, x0, T_max, T=None, U0=None, trace=False, **opt)
     import torch
     from paper_2602_19699_amd import cbic
     sys_ = cbic.System(ctx, kind, params)
-    o = cbic.Options(**opt)
-    dev = torch.device("cuda", ctx.device)
-    Tt = None if T is None else torch.as_tensor(np.asarray(T, np.int32), device=dev)
-    U0t = None if U0 is None else torch.as_tensor(np.asarray(U0, np.float64), device=dev)
-    out = cbic.solve_batch(ctx, sys_, torch.as_tensor(np.asarray(x0, np.float64), device=dev), T_max, T=Tt,
-                           U0=U0t, opts=o, trace=trace)
-    torch.cuda.synchronize(dev)
-    res = {k: (None if getattr(out, k) is None else getattr(out, k).cpu().numpy())
-           for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx", "xK", "cost_trace", "work", "jtrace")}
-    res["status"] = res["status"].astype(np.uint32)
-    sys_.close()
+    try:
+        o = cbic.Options(**opt)
+        dev = torch.device("cuda", ctx.device)
+        Tt = None if T is None else torch.as_tensor(np.asarray(T, np.int32), device=dev)
+        U0t = None if U0 is None else torch.as_tensor(np.asarray(U0, np.float64), device=dev)
+        out = cbic.solve_batch(ctx, sys_, torch.as_tensor(np.asarray(x0, np.float64), device=dev), T_max, T=Tt,
+                               U0=U0t, opts=o, trace=trace)
+        torch.cuda.synchronize(dev)
+        res = {k: (None if getattr(out, k) is None else getattr(out, k).cpu().numpy())
+               for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx", "xK", "cost_trace", "work", "jtrace")}
+        res["status"] = res["status"].astype(np.uint32)
+    finally:
+        sys_.close()
     return res
 
 

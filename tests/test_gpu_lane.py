@@ -141,6 +141,23 @@ def test_lq_one_iteration_optimum(ctx, n, m):
     np.testing.assert_allclose(g["U"], r.U, atol=1e-9)
 
 
+def test_lq_clip_floors_alternate(ctx):
+    # an LQ system's clipped constant Hessians depend on psd_eps: solves with
+    # different floors, in any order, each match the oracle under their own
+    # floor, and repeating a floor repeats its bits
+    q = I.lq_random(4, 2, seed=5, ref=True)
+    x0 = I.lq_x0(20, 4, seed=3)
+    runs = {}
+    for eps in (1e-6, 0.7, 1e-6, 0.7, 0.0):
+        g = gpu_solve(ctx, LQ, q, x0, 30, max_iter=3, psd_eps=eps)
+        r = orc.solve_batch(LQ, q, x0, 30, opts=oracle_opts(max_iter=3, psd_eps=eps))
+        compare(g, r, tol_J=1e-11, label=f"lq eps={eps}")
+        if eps in runs:
+            np.testing.assert_array_equal(runs[eps]["U"], g["U"])
+        runs[eps] = g
+    assert not np.array_equal(runs[1e-6]["U"], runs[0.7]["U"])
+
+
 def test_arm_ragged_fp64(ctx):
     # per instance: equal to the oracle to 1e-9, or a near-tie line-search
     # decision replayed, or rounding-sensitive (its own cost moves under a
