@@ -284,11 +284,15 @@ def roofline_for(name, form, res, form_opts):
     if name == "quad1k":
         # the Riccati products run as MFMA tiles: the dense matrix-core peak of the form's precision
         peak = FP64_PEAK_TFLOPS if form_opts.precision == 0 else FP32_PEAK_TFLOPS
-        kernel = f"quad_iterate<{prec}>"
+        box = "true" if np.isfinite(form_opts.u_max) else "false"
+        lm = "true" if form_opts.regularization == 1 else "false"
+        kernel = f"quad_iterate<{prec},{box},{lm}>"
+        vf = valu_issue_frac(name, form, kernel, res["iterate_ms"])
         return {"bound": "mfma", "achieved": round(res["iterate_TFLOPs"], 4), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(res["iterate_TFLOPs"] / peak, 5), "traffic": traffic_for(name, form, kernel),
                 "kernel": kernel, "alg_flops_per_launch": res["iterate_alg_flops"],
-                "iterate_ms": round(res["iterate_ms"], 4)}
+                "iterate_ms": round(res["iterate_ms"], 4),
+                "valu_issue_frac": None if vf is None else round(vf, 4)}
     sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
     bounded = "true" if np.isfinite(form_opts.u_max) else "false"
     kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']},{bounded}>"
@@ -466,7 +470,9 @@ def main():
                   "mixed_tol1e-7_umax8": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=8.0)},
         "quad1k": {"fp64_fixed50": F(max_iter=50), "fp64_tol1e-10": F(stop_mode=1, rtol=1e-10),
                    "mixed_tol1e-7": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7),
-                   "mixed_tol1e-4": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-4)},
+                   "mixed_tol1e-4": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-4),
+                   "fp64_tol1e-10_lm": F(stop_mode=1, rtol=1e-10, regularization=cbic.REG_LM),
+                   "mixed_tol1e-7_umax5": F(precision=cbic.MIXED, stop_mode=1, rtol=1e-7, u_max=5.0)},
     }
     cpu_cfg = {"pm16k": (16384, "fp64_fixed50"), "pm64": (64, "fp64_fixed50"), "arm4k": (512, "fp64_fixed50"),
                "quad1k": (64, "fp64_tol1e-10")}

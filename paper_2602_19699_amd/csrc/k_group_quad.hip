@@ -356,9 +356,11 @@ __device__ __forceinline__ void wave_jac(const Smem<R>& sm, const WaveScratch<R>
 }
 
 // ------------------------------------------------------------------ FP64 Cholesky of Q_uu and the gains
-// Wave 0 factors Quu (rows on lanes); threads 0..37 solve for [K k].
-template <class R>
-__device__ __forceinline__ bool gains(Smem<R>& sm, int tid) {
+// Wave 0 factors Quu (rows on lanes); threads 0..37 solve for [K k].  The
+// other waves run `side` meanwhile (work that needs none of the step's gains).
+template <class R, class Side>
+__device__ __forceinline__ bool gains(Smem<R>& sm, int tid, Side&& side) {
+  if (tid >= 64) side();
   if (tid < 64) {
     const int lane = tid;
     const bool row = lane < M;
@@ -708,7 +710,6 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
   using Q = QW<R>;
   const R dt = R(prm[O_DT]);
   const R wq = R(prm[O_WQ]), wv = R(prm[O_WV]), wu = R(prm[O_WU]), wT = R(prm[O_WT]);
-  WaveScratch<R>& w0 = sm.wv[0];
   // terminal: P = clip(l_T,xx) (diagonal), p = l_T,x
   for (int i = tid; i < N * LD; i += NT) (&sm.P[0][0])[i] = R(0);
   __syncthreads();
@@ -720,8 +721,29 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
   }
   __syncthreads();
   const int wid = tid >> 6, lane = tid & 63;
+  // Step kk's (x, u) go to the scratch of wave 2 + (kk & 1) (free between the
+  // derivative pre-passes) and its derivative block to A, Bm, by the threads
+  // from `first` on.  The first step of a chunk is staged by all threads after
+  // the pre-pass; every other step by waves 1..3 while wave 0 factors the
+  // previous step's Q_uu (A and Bm are not read again in a step once Q_uu is
+  // formed).
+  auto stage = [&](int kk, int first) {
+    const int t = tid - first, nt = NT - first;
+    if (t < 0) return;
+    WaveScratch<R>& sx = sm.wv[2 + (kk & 1)];
+    if (t < N) sx.x[t] = Q::xp(w, buf, kk, s)[t];
+    if (t < M) sx.u[t] = Q::up(w, buf, kk, s)[t];
+    const R* src = blk + ((T - 1 - kk) % CH) * DB;
+    for (int i = t; i < DB; i += nt) {
+      const int r = i / (N + M), c = i - r * (N + M);
+      const R v = src[i];
+      if (c < N) sm.A[r][c] = v;
+      else sm.Bm[r][c - N] = v;
+    }
+  };
   for (int k = T - 1; k >= 0; --k) {
     const int q = (T - 1 - k) % CH;
+    WaveScratch<R>& sx = sm.wv[2 + (k & 1)];
     if (q == 0) {
       // derivative blocks of the next CH steps, wave wid taking every fourth
       // step (they do not depend on P)
@@ -735,19 +757,9 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
         wave_sync();
       }
       __syncthreads();
+      stage(k, 0);
+      __syncthreads();
     }
-    if (tid < N) w0.x[tid] = Q::xp(w, buf, k, s)[tid];
-    if (tid < M) w0.u[tid] = Q::up(w, buf, k, s)[tid];
-    {
-      const R* src = blk + q * DB;
-      for (int i = tid; i < DB; i += NT) {
-        const int r = i / (N + M), c = i - r * (N + M);
-        const R v = src[i];
-        if (c < N) sm.A[r][c] = v;
-        else sm.Bm[r][c - N] = v;
-      }
-    }
-    __syncthreads();
     // PA = P A, PB = P B
     // nine 16 x 16 tiles of P A and three of P B over the four waves
     for (int t = tid >> 6; t < 12; t += NW) {
@@ -766,11 +778,11 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       if (r >= 0 && r < N + M) {
         R v;
         if (r < N) {
-          v = R(2) * (r < NQ ? wq : wv) * (w0.x[r] - sm.xnom[r]);
+          v = R(2) * (r < NQ ? wq : wv) * (sx.x[r] - sm.xnom[r]);
           for (int t = 0; t < N; ++t) v += sm.A[t][r] * sm.p[t];
         } else {
           const int c = r - N;
-          v = R(2) * wu * w0.u[c];
+          v = R(2) * wu * sx.u[c];
           for (int t = 0; t < N; ++t) v += sm.Bm[t][c] * sm.p[t];
         }
         if (r < N) sm.Qx[r] = v;
@@ -802,9 +814,12 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       if (tid < M * M) box_H(sm)[(tid / M) * (M + 1) + tid % M] = sm.Quu[tid / M][tid % M];
       __syncthreads();
     }
-    if (!gains(sm, tid)) return sm.flag == 1 ? ST_CHOL_FAIL : ST_NONFINITE;
+    if (!gains(sm, tid, [&] {
+          if (k >= 1 && q + 1 < CH) stage(k - 1, 64);
+        }))
+      return sm.flag == 1 ? ST_CHOL_FAIL : ST_NONFINITE;
     if constexpr (BOX) {
-      const uint32_t b = box_step(sm, w0, umax, tid);
+      const uint32_t b = box_step(sm, sx, umax, tid);
       if (b) return b;
     }
     // store the gains
