@@ -290,6 +290,31 @@ __device__ __forceinline__ void mfma_tile(R* C, int ldc, const R* A, int lda, co
   }
 }
 
+// The same tile product handing each result to out(i, j, value) instead of
+// storing it (no input accumulator).
+template <int Kd, bool TA, bool TB, class R, class Out>
+__device__ __forceinline__ void mfma_tile_out(Out&& out, const R* A, int lda, const R* Bp, int ldb, int Mr, int Nc,
+                                              int i0, int j0, int lane) {
+  using V = typename MfAcc<R>::type;
+  const int li = lane & 15, lk = lane >> 4;
+  V acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = R(0);
+  const int ia = i0 + li, jb = j0 + li;
+#pragma unroll
+  for (int k0 = 0; k0 < Kd; k0 += 4) {
+    const int k = k0 + lk;
+    const R a = (ia < Mr && k < Kd) ? (TA ? A[k * lda + ia] : A[ia * lda + k]) : R(0);
+    const R b = (k < Kd && jb < Nc) ? (TB ? Bp[jb * ldb + k] : Bp[k * ldb + jb]) : R(0);
+    acc = mfma16(a, b, acc);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + MfAcc<R>::row(lk, r), j = j0 + li;
+    if (i < Mr && j < Nc) out(i, j, acc[r]);
+  }
+}
+
 // ------------------------------------------------------------------ wave Jacobians
 // [f_x | f_u] at (ws.x, ws.u) by one wave, after wave_dyn on that point (L, its
 // reciprocal diagonal, a, sin/cos and W2 cos q in ws), written row-major
@@ -760,52 +785,44 @@ __device__ __forceinline__ uint32_t backward(Smem<R>& sm, const double* __restri
       stage(k, 0);
       __syncthreads();
     }
-    // PA = P A, PB = P B
-    // nine 16 x 16 tiles of P A and three of P B over the four waves
-    for (int t = tid >> 6; t < 12; t += NW) {
+    // PA = P A, PB = P B: nine 16 x 16 tiles of P A and three of P B; in the
+    // same phase Q_x = l_x + A^T p and Q_u = l_u + B^T p (p is replaced only
+    // after the gains) as four one-column tiles, the cost gradients (diagonal
+    // Hessians) added to their results: sixteen tiles, four per wave
+    for (int t = tid >> 6; t < 16; t += NW) {
       if (t < 9)
         mfma_tile<N, false, false>(&sm.PA[0][0], LD, &sm.P[0][0], LD, &sm.A[0][0], LD, (const R*)nullptr, 0, N, N,
                                    (t / 3) * 16, (t % 3) * 16, tid & 63);
-      else
+      else if (t < 12)
         mfma_tile<N, false, false>(&sm.PB[0][0], LDB, &sm.P[0][0], LD, &sm.Bm[0][0], LDB, (const R*)nullptr, 0, N, M,
                                    (t - 9) * 16, 0, tid & 63);
-    }
-    // in the same phase, on the last wave: Q_x = l_x + A^T p, Q_u = l_u + B^T p
-    // (p is replaced only after the gains), with the cost gradients (diagonal
-    // Hessians) formed in registers
-    {
-      const int r = tid - (NW - 1) * 64;
-      if (r >= 0 && r < N + M) {
-        R v;
-        if (r < N) {
-          v = R(2) * (r < NQ ? wq : wv) * (sx.x[r] - sm.xnom[r]);
-          for (int t = 0; t < N; ++t) v += sm.A[t][r] * sm.p[t];
-        } else {
-          const int c = r - N;
-          v = R(2) * wu * sx.u[c];
-          for (int t = 0; t < N; ++t) v += sm.Bm[t][c] * sm.p[t];
-        }
-        if (r < N) sm.Qx[r] = v;
-        else sm.Qu[r - N] = v;
-      }
+      else if (t < 15)
+        mfma_tile_out<N, true, false>(
+            [&](int i, int, R v) { sm.Qx[i] = R(2) * (i < NQ ? wq : wv) * (sx.x[i] - sm.xnom[i]) + v; },
+            &sm.A[0][0], LD, &sm.p[0], 1, N, 1, (t - 12) * 16, 0, tid & 63);
+      else
+        mfma_tile_out<N, true, false>([&](int i, int, R v) { sm.Qu[i] = R(2) * wu * sx.u[i] + v; }, &sm.Bm[0][0],
+                                      LDB, &sm.p[0], 1, M, 1, 0, 0, tid & 63);
     }
     __syncthreads();
-    // Q_xx = clip(l_xx) + A^T (P A) into P; Q_uu = clip(l_uu) + B^T (P B); Q_ux = B^T (P A)
-    for (int t = tid >> 6; t < 12; t += NW) {
+    // Q_xx = clip(l_xx) + A^T (P A) into P, Q_ux = B^T (P A): twelve tiles; Q_uu =
+    // clip(l_uu) + B^T (P B) (+ mu I, the Levenberg-Marquardt shift, zero
+    // otherwise: adding it changes no bit) in FP64 from a thirteenth
+    for (int t = tid >> 6; t < 13; t += NW) {
       if (t < 9)
         mfma_tile<N, true, false>(&sm.P[0][0], LD, &sm.A[0][0], LD, &sm.PA[0][0], LD, (const R*)nullptr, 0, N, N,
                                   (t / 3) * 16, (t % 3) * 16, tid & 63);
-      else
+      else if (t < 12)
         mfma_tile<N, true, false>(&sm.Qux[0][0], LD, &sm.Bm[0][0], LDB, &sm.PA[0][0], LD, (const R*)nullptr, 0, M, N,
                                   0, (t - 9) * 16, tid & 63);
-    }
-    if (tid < M * M) {
-      const int i = tid / M, j = tid % M;
-      R v = R(0);
-      for (int t = 0; t < N; ++t) v += sm.Bm[t][i] * sm.PB[t][j];
-      sm.Quu[i][j] = double(v) + (i == j ? double(dmax(R(2) * wu, eps)) : 0.0);
-      // the Levenberg-Marquardt shift (zero otherwise: adding it changes no bit)
-      if (i == j) sm.Quu[i][j] += mu;
+      else
+        mfma_tile_out<N, true, false>(
+            [&](int i, int j, R v) {
+              double q = double(v) + (i == j ? double(dmax(R(2) * wu, eps)) : 0.0);
+              if (i == j) q += mu;
+              sm.Quu[i][j] = q;
+            },
+            &sm.Bm[0][0], LDB, &sm.PB[0][0], LDB, M, M, 0, 0, tid & 63);
     }
     __syncthreads();
     if (tid < N) sm.P[tid][tid] += dmax(R(2) * (tid < NQ ? wq : wv), eps);
