@@ -160,6 +160,12 @@ typedef struct {
 #define CBIC_FLAG_GRAPH 1u  /* launch the iteration chain through a captured HIP graph      */
 #define CBIC_FLAG_TIMING 2u /* record HIP events around init / iterations / finalisation on
                                the solve's stream; read them with cbic_phase_times          */
+#define CBIC_FLAG_INPUT_ORDER 4u /* iterate the instances in the horizon sort's order.  By
+                               default the iteration launches take them longest horizon
+                               first and, within a horizon, highest initial cost J^0 first
+                               (quarter-octave levels), so that instances of similar
+                               expected work share a wave; a scheduling choice only: no
+                               result depends on it                                          */
 
 /* Output buffers: caller-owned DEVICE pointers, AoS per instance, padded to
  * T_max; entries past an instance's horizon are written as zero.
@@ -283,8 +289,9 @@ cbic_status cbic_calibrate_max_iter(cbic_context* ctx, const cbic_system* sys, i
                                     int32_t cap, void* stream, int32_t* p99, int32_t* p50, int64_t* hist);
 
 /* Milliseconds spent by the last solve on this context that was launched with
- * CBIC_FLAG_TIMING in its three phases: ms[0] warm start and initial rollout,
- * ms[1] the iteration kernels (backward sweeps and line searches), ms[2]
+ * CBIC_FLAG_TIMING in its three phases: ms[0] warm start and initial rollout
+ * (with the iteration order of CBIC_FLAG_INPUT_ORDER's default), ms[1] the
+ * iteration kernels (backward sweeps and line searches), ms[2]
  * finalisation (status, critic targets, outputs).  Waits for that solve's
  * stream work to finish.  CBIC_E_INVALID if no timed solve was launched. */
 cbic_status cbic_phase_times(cbic_context* ctx, double* ms3);

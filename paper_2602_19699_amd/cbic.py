@@ -24,6 +24,7 @@ SCHED_AUTO, SCHED_LANE, SCHED_GROUP = 0, 1, 2
 REG_CLIP, REG_LM = 0, 1
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
+FLAG_INPUT_ORDER = 4
 
 
 class CbicError(RuntimeError):

@@ -85,8 +85,12 @@ namespace {
 
 bool aligned8(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
+size_t a256(size_t b) { return (b + 255) / 256 * 256; }
+
+// scratch behind the solver's workspace: the horizon sort's histogram and
+// permutation, then the iteration order's slot list
 size_t sort_bytes(int B, int Tmax) {
-  return ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256 + (size_t(B) * 4 + 255) / 256 * 256;
+  return a256((size_t(Tmax) + 1) * 4) + a256(size_t(B) * 4) + a256(size_t(B) * 4);
 }
 
 cbic_status ensure_ws(cbic_context* ctx, size_t need) {
@@ -203,8 +207,12 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
   // the launches below report through hipGetLastError: drop an error another
   // call on this thread left behind
   (void)hipGetLastError();
-  int32_t* hist = reinterpret_cast<int32_t*>(base + ws_main);
-  int32_t* perm = reinterpret_cast<int32_t*>(base + ws_main + ((size_t(Tmax) + 1) * 4 + 255) / 256 * 256);
+  char* sb = base + ws_main;
+  int32_t* hist = reinterpret_cast<int32_t*>(sb);
+  sb += a256((size_t(Tmax) + 1) * 4);
+  int32_t* perm = reinterpret_cast<int32_t*>(sb);
+  sb += a256(size_t(B) * 4);
+  int32_t* order = reinterpret_cast<int32_t*>(sb);
   if (d_T) HIP_TRY(launch_horizon_sort(d_T, B, Tmax, hist, perm, stream));
   else perm = nullptr;
 
@@ -215,6 +223,17 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
   const IterTrace tr{out->cost_trace, out->jtrace};
   HIP_TRY(L->init(prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, sp.umax, stream));
+  // the iteration launches take the slots in the order of expected work
+  // (longest horizon, then highest initial cost first) unless the caller
+  // asks for the horizon sort's order; results are the same either way
+  if ((opts->flags & CBIC_FLAG_INPUT_ORDER) || opts->max_iter <= 0 || !cost_order_supported(d_T != nullptr, Tmax)) {
+    order = nullptr;
+  } else {
+    const LaneLayout lay = lane_layout(L->N, L->M, L->elem, B, Tmax, L->nbuf);
+    HIP_TRY(launch_cost_order(reinterpret_cast<const int32_t*>(base + lay.T),
+                              reinterpret_cast<const double*>(base + lay.J), B, Tmax, d_T != nullptr, order,
+                              stream));
+  }
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
   int group = opts->group_lanes;
   if (group <= 0) {
@@ -227,12 +246,12 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
     const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
     if (!graph) {
       for (int c = 0; c < chunks; ++c)
-        HIP_TRY(L->iterate(prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream));
+        HIP_TRY(L->iterate(prm, base, B, Tmax, B, order, sp, G, group, tr, stream));
     } else {
       char key[512];
       std::snprintf(key, sizeof key,
-                    "%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
-                    (const void*)L, (const void*)prm, (const void*)base, B, Tmax, G, chunks, group,
+                    "%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%p|%p|%d|%.17g|%.17g|%.17g|%.17g",
+                    (const void*)L, (const void*)prm, (const void*)base, (const void*)order, B, Tmax, G, chunks, group,
                     sp.max_iter, sp.ls_trials, sp.stop_mode, sp.eps, sp.beta, sp.rtol, (void*)out->cost_trace,
                     (void*)out->jtrace, sp.reg, sp.mu0, sp.mu_fac, sp.mu_max, sp.umax);
       auto it = ctx->graphs.find(key);
@@ -241,7 +260,7 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
         HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipSuccess;
         for (int c = 0; c < chunks && e == hipSuccess; ++c)
-          e = L->iterate(prm, base, B, Tmax, B, nullptr, sp, G, group, tr, stream);
+          e = L->iterate(prm, base, B, Tmax, B, order, sp, G, group, tr, stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {

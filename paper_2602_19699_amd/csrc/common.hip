@@ -94,6 +94,111 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- iteration order
+// A scheduling heuristic, not part of the method: an instance whose initial
+// cost J^0 is higher tends to need more iterations, and a wave (or a
+// workgroup) lasts as long as its slowest instance.  The iteration launches
+// take the slots grouped by horizon (longest first, the order the horizon
+// sort already gave the slots) and, within a horizon, by J^0 (highest first)
+// in coarse levels below the batch's largest J^0, so that instances of
+// similar expected work share waves.  No result depends on the order: every
+// instance's arithmetic is its own.
+//
+// One workgroup does it all in shared memory: the largest J^0, a histogram of
+// the (horizon, level) buckets, its scan and the scatter (shared-memory
+// atomics; the order within a bucket is arbitrary).
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBuckets = 16384;  // shared-memory histogram (64 KB)
+
+// levels of J^0 per horizon: quarter octaves below the largest J^0 for a
+// batch of one horizon, whole octaves otherwise, fewer if the horizons need
+// more buckets than the histogram holds
+__host__ __device__ inline int order_levels(bool ragged, int Tmax) {
+  if (!ragged) return 64;
+  const int per = kOrderBuckets / (Tmax + 1);
+  return per < 16 ? per : 16;
+}
+
+__device__ __forceinline__ int order_bucket(int t, double J, int Tmax, bool ragged, int nlev, uint32_t ref) {
+  int lvl = nlev - 1;  // J^0 <= 0 or NaN: last within its horizon
+  if (J > 0.0) {
+    // quarter-octave (or octave) index of float(J^0) from its exponent and
+    // leading mantissa bits, counted down from the largest
+    const int sh = ragged ? 23 : 21;
+    const int d = int(ref >> sh) - int(__float_as_uint(float(J)) >> sh);
+    lvl = d < 0 ? 0 : (d > nlev - 1 ? nlev - 1 : d);
+  }
+  if (!ragged) return lvl;
+  t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
+  return (Tmax - t) * nlev + lvl;
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __restrict__ T,
+                                                               const double* __restrict__ J, int B, int Tmax,
+                                                               int ragged_i, int32_t* __restrict__ order) {
+  __shared__ int32_t hist[kOrderBuckets];
+  __shared__ uint32_t wmax[kOrderThreads / 64];
+  __shared__ int32_t part[kOrderThreads];
+  const int t = threadIdx.x;
+  const bool ragged = ragged_i != 0;
+  const int nlev = order_levels(ragged, Tmax);
+  const int nb = ragged ? (Tmax + 1) * nlev : nlev;
+  for (int i = t; i < nb; i += kOrderThreads) hist[i] = 0;
+  // the largest positive J^0 (as float bits, which order like the values)
+  uint32_t m = 0;
+  for (int s = t; s < B; s += kOrderThreads) {
+    const double j = J[s];
+    if (j > 0.0) {
+      const uint32_t b = __float_as_uint(float(j));
+      m = b > m ? b : m;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t v = uint32_t(__shfl_xor(int(m), o, 64));
+    m = v > m ? v : m;
+  }
+  if ((t & 63) == 0) wmax[t >> 6] = m;
+  __syncthreads();
+  uint32_t ref = 0;
+#pragma unroll
+  for (int w = 0; w < kOrderThreads / 64; ++w) ref = wmax[w] > ref ? wmax[w] : ref;
+  for (int s = t; s < B; s += kOrderThreads) atomicAdd(&hist[order_bucket(T[s], J[s], Tmax, ragged, nlev, ref)], 1);
+  __syncthreads();
+  // exclusive scan of hist[0..nb): a serial run per thread, then across threads
+  const int per = (nb + kOrderThreads - 1) / kOrderThreads;
+  const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
+  int32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += hist[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kOrderThreads; off <<= 1) {
+    const int32_t v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = part[t] - sum;
+  for (int i = lo; i < hi; ++i) {
+    const int32_t c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+  __syncthreads();
+  for (int s = t; s < B; s += kOrderThreads)
+    order[atomicAdd(&hist[order_bucket(T[s], J[s], Tmax, ragged, nlev, ref)], 1)] = s;
+}
+
+hipError_t launch_cost_order(const int32_t* T, const double* J, int B, int Tmax, bool ragged, int32_t* order,
+                             hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (ragged && order_levels(true, Tmax) < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(kOrderThreads), 0, st, T, J, B, Tmax, ragged ? 1 : 0, order);
+  return hipGetLastError();
+}
+
+bool cost_order_supported(bool ragged, int Tmax) { return !ragged || order_levels(true, Tmax) >= 1; }
+
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st) {
   const int nb = Tmax + 1;
   const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;

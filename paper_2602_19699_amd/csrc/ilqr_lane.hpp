@@ -830,9 +830,13 @@ struct Lane {
 
   // Closed-loop rollout with step alpha from the iterate in `buf`; returns
   // J_hat in FP64 (NaN-propagating).  With `write` the trial trajectory goes to
-  // buffer `nb`.  With non-negative costs a trial stops as soon as its
-  // partial sum reaches J: its total could only be larger, so the
-  // accept/reject decision is unchanged.
+  // buffer `nb`.  With non-negative costs a trial stops at the end of the
+  // chunk in which its partial sum reaches J: its total could only be
+  // larger, so the accept/reject decision is unchanged; `steps` is the
+  // number of steps up to that first failing one.  A stopped trial's J_hat
+  // is then not its total (it is rejected either way), and a writing trial
+  // may have written a few steps past it into a buffer that does not become
+  // the iterate.
   //
   // The iterate's step records stream through the group's LDS ring `ring`
   // ([2][CT][SWP]) in chunks of CT = GL * PT steps: lane r loads steps
@@ -875,6 +879,11 @@ struct Lane {
       }
       if (live) {
         const int cn = T - kc < CT ? T - kc : CT;
+        // the stop test is taken at the end of the chunk, so that no step
+        // waits on the branch of the one before (steps past the first
+        // failing one change neither the decision nor the counts)
+        bool failed = false;
+#pragma unroll 2
         for (int q = 0; q < cn; ++q) {
           const R* v = cur + q * SWP;
           const int k = kc + q;
@@ -898,12 +907,13 @@ struct Lane {
             st(up(w, nb, k, s), uh);
             st(xp(w, nb, k + 1, s), xh);
           }
-          if (Sys::kNonNegCost && !(Jh < Jcur)) {
-            steps = k + 1;
-            live = false;
-            break;
+          if constexpr (Sys::kNonNegCost) {
+            const bool f = !(Jh < Jcur);
+            steps = (f && !failed) ? k + 1 : steps;
+            failed = failed || f;
           }
         }
+        if (failed) live = false;
       }
       const unsigned long long any = (__ballot(live) >> gbase) & gmask;
       if (!any || !more) break;
