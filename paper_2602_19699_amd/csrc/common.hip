@@ -108,7 +108,8 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
 // the (horizon, level) buckets, its scan and the scatter (shared-memory
 // atomics; the order within a bucket is arbitrary).
 constexpr int kOrderThreads = 1024;
-constexpr int kOrderBuckets = 16384;  // shared-memory histogram (64 KB)
+constexpr int kOrderBuckets = 8192;  // shared-memory histogram (32 KB)
+constexpr int kOrderKeys = 16384;    // slots whose keys stay in shared memory (64 KB)
 
 // levels of J^0 per horizon: quarter octaves below the largest J^0 for a
 // batch of one horizon, whole octaves otherwise, fewer if the horizons need
@@ -119,39 +120,59 @@ __host__ __device__ inline int order_levels(bool ragged, int Tmax) {
   return per < 16 ? per : 16;
 }
 
-__device__ __forceinline__ int order_bucket(int t, double J, int Tmax, bool ragged, int nlev, uint32_t ref) {
-  int lvl = nlev - 1;  // J^0 <= 0 or NaN: last within its horizon
-  if (J > 0.0) {
-    // quarter-octave (or octave) index of float(J^0) from its exponent and
-    // leading mantissa bits, counted down from the largest
-    const int sh = ragged ? 23 : 21;
-    const int d = int(ref >> sh) - int(__float_as_uint(float(J)) >> sh);
+// a slot's key: its horizon (clamped into [1, Tmax]) and the quarter-octave
+// (or octave) index of float(J^0) from the exponent and leading mantissa
+// bits; 0 for J^0 <= 0 or NaN (float(J^0) beyond the float range is infinity
+// and takes the top index)
+__device__ __forceinline__ uint32_t order_key(int t, double J, int Tmax, int sh) {
+  t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
+  const uint32_t a = J > 0.0 ? (__float_as_uint(float(J)) >> sh) + 1u : 0u;
+  return (uint32_t(t) << 11) | a;  // a < 2^(32 - sh) + 1 <= 2^11
+}
+
+// bucket of a key: horizon (longest first), then the level below the largest
+// index `ref` (highest J^0 first); the last level takes J^0 <= 0
+__device__ __forceinline__ int order_bucket(uint32_t key, int Tmax, bool ragged, int nlev, uint32_t ref) {
+  const uint32_t a = key & 2047u;
+  int lvl = nlev - 1;
+  if (a) {
+    const int d = int(ref) - int(a);
     lvl = d < 0 ? 0 : (d > nlev - 1 ? nlev - 1 : d);
   }
   if (!ragged) return lvl;
-  t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
-  return (Tmax - t) * nlev + lvl;
+  return (Tmax - int(key >> 11)) * nlev + lvl;
 }
 
+// horizons must fit the key's 20 bits, and ragged ones a level each in the histogram
+bool cost_order_supported(bool ragged, int Tmax) {
+  return Tmax < (1 << 20) && (!ragged || order_levels(true, Tmax) >= 1);
+}
+
+template <bool RAGGED, bool CACHED>
 __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __restrict__ T,
                                                                const double* __restrict__ J, int B, int Tmax,
-                                                               int ragged_i, int32_t* __restrict__ order) {
+                                                               int32_t* __restrict__ order) {
   __shared__ int32_t hist[kOrderBuckets];
+  __shared__ uint32_t keys[CACHED ? kOrderKeys : 1];
   __shared__ uint32_t wmax[kOrderThreads / 64];
-  __shared__ int32_t part[kOrderThreads];
+  __shared__ int32_t part[kOrderThreads / 64];
   const int t = threadIdx.x;
-  const bool ragged = ragged_i != 0;
-  const int nlev = order_levels(ragged, Tmax);
-  const int nb = ragged ? (Tmax + 1) * nlev : nlev;
+  constexpr int sh = RAGGED ? 23 : 21;
+  const int nlev = order_levels(RAGGED, Tmax);
+  const int nb = RAGGED ? (Tmax + 1) * nlev : nlev;
+  auto key_at = [&](int s) -> uint32_t { return order_key(RAGGED ? T[s] : Tmax, J[s], Tmax, sh); };
+  auto key_of = [&](int s) -> uint32_t {
+    if constexpr (CACHED) return keys[s];
+    else return key_at(s);
+  };
   for (int i = t; i < nb; i += kOrderThreads) hist[i] = 0;
-  // the largest positive J^0 (as float bits, which order like the values)
+  // keys (kept in shared memory when they fit) and the largest J^0 index
   uint32_t m = 0;
+#pragma unroll 8
   for (int s = t; s < B; s += kOrderThreads) {
-    const double j = J[s];
-    if (j > 0.0) {
-      const uint32_t b = __float_as_uint(float(j));
-      m = b > m ? b : m;
-    }
+    const uint32_t k = key_at(s);
+    if constexpr (CACHED) keys[s] = k;
+    m = (k & 2047u) > m ? (k & 2047u) : m;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -163,41 +184,50 @@ __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __r
   uint32_t ref = 0;
 #pragma unroll
   for (int w = 0; w < kOrderThreads / 64; ++w) ref = wmax[w] > ref ? wmax[w] : ref;
-  for (int s = t; s < B; s += kOrderThreads) atomicAdd(&hist[order_bucket(T[s], J[s], Tmax, ragged, nlev, ref)], 1);
+#pragma unroll 4
+  for (int s = t; s < B; s += kOrderThreads) atomicAdd(&hist[order_bucket(key_of(s), Tmax, RAGGED, nlev, ref)], 1);
   __syncthreads();
   // exclusive scan of hist[0..nb): a serial run per thread, then across threads
   const int per = (nb + kOrderThreads - 1) / kOrderThreads;
   const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
   int32_t sum = 0;
   for (int i = lo; i < hi; ++i) sum += hist[i];
-  part[t] = sum;
-  __syncthreads();
-  for (int off = 1; off < kOrderThreads; off <<= 1) {
-    const int32_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  // inclusive scan of the threads' sums within each wave, then of the wave totals
+  int32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t v = __shfl_up(inc, o, 64);
+    if ((t & 63) >= o) inc += v;
   }
-  int32_t run = part[t] - sum;
+  if ((t & 63) == 63) part[t >> 6] = inc;
+  __syncthreads();
+  int32_t wbase = 0;
+  for (int w = 0; w < (t >> 6); ++w) wbase += part[w];
+  int32_t run = wbase + inc - sum;
   for (int i = lo; i < hi; ++i) {
     const int32_t c = hist[i];
     hist[i] = run;
     run += c;
   }
   __syncthreads();
+#pragma unroll 4
   for (int s = t; s < B; s += kOrderThreads)
-    order[atomicAdd(&hist[order_bucket(T[s], J[s], Tmax, ragged, nlev, ref)], 1)] = s;
+    order[atomicAdd(&hist[order_bucket(key_of(s), Tmax, RAGGED, nlev, ref)], 1)] = s;
 }
 
 hipError_t launch_cost_order(const int32_t* T, const double* J, int B, int Tmax, bool ragged, int32_t* order,
                              hipStream_t st) {
   if (B <= 0) return hipSuccess;
-  if (ragged && order_levels(true, Tmax) < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cost_order, dim3(1), dim3(kOrderThreads), 0, st, T, J, B, Tmax, ragged ? 1 : 0, order);
+  if (!cost_order_supported(ragged, Tmax)) return hipErrorInvalidValue;
+  const dim3 g(1), b(kOrderThreads);
+  const bool cached = B <= kOrderKeys;
+  if (ragged && cached) hipLaunchKernelGGL((k_cost_order<true, true>), g, b, 0, st, T, J, B, Tmax, order);
+  else if (ragged) hipLaunchKernelGGL((k_cost_order<true, false>), g, b, 0, st, T, J, B, Tmax, order);
+  else if (cached) hipLaunchKernelGGL((k_cost_order<false, true>), g, b, 0, st, T, J, B, Tmax, order);
+  else hipLaunchKernelGGL((k_cost_order<false, false>), g, b, 0, st, T, J, B, Tmax, order);
   return hipGetLastError();
 }
 
-bool cost_order_supported(bool ragged, int Tmax) { return !ragged || order_levels(true, Tmax) >= 1; }
 
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st) {
   const int nb = Tmax + 1;
