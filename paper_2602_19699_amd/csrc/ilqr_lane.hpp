@@ -845,7 +845,9 @@ struct Lane {
   // group keeps streaming while any of its lanes is still rolling out.
   //
   // With BOX the trial's controls are clamped into [-umax, umax] (eq. 1).
-  template <int GL, bool BOX>
+  // REPLAY rolls out a step whose cost is already known only to write it:
+  // the same controls and states, no costs (returns 0).
+  template <int GL, bool BOX, bool REPLAY = false>
   __device__ static double trial(const Model& mdl, const LaneState<R>& w, int s, int T, int buf, int nb,
                                  R alpha, double Jcur, bool write, int& steps, R* ring, int r, int gbase,
                                  R umax) {
@@ -898,7 +900,7 @@ struct Lane {
             if constexpr (BOX) u = clamp_nan(u, umax);
             uh[i] = u;
           }
-          Jh += double(mdl.cost(xh, uh));
+          if constexpr (!REPLAY) Jh += double(mdl.cost(xh, uh));
           R xn[N];
           mdl.dyn(xh, uh, xn);
 #pragma unroll
@@ -907,7 +909,7 @@ struct Lane {
             st(up(w, nb, k, s), uh);
             st(xp(w, nb, k + 1, s), xh);
           }
-          if constexpr (Sys::kNonNegCost) {
+          if constexpr (Sys::kNonNegCost && !REPLAY) {
             const bool f = !(Jh < Jcur);
             steps = (f && !failed) ? k + 1 : steps;
             failed = failed || f;
@@ -924,7 +926,8 @@ struct Lane {
       }
       stage_sync();
     }
-    if (live) Jh += double(mdl.term(xh));
+    if constexpr (!REPLAY)
+      if (live) Jh += double(mdl.term(xh));
     return Jh;
   }
 };
@@ -1133,29 +1136,22 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
         }
       } else {
         // rounds of GL parallel trials, then (if the accepted step is not alpha = 1,
-        // whose lane wrote while trying it) one commit rollout that writes it; one
-        // call site of the rollout keeps the register footprint down
-        bool commit = false;
+        // whose lane wrote while trying it) one replay of the accepted step
+        // that writes it: the same controls and states, without the costs
+        // (its J_hat is known from the round)
         for (int j0 = 0;;) {
-          const int j = commit ? acc : j0 + r;
+          const int j = j0 + r;
           double Jh = __builtin_nan("");
           int steps = 0;
-          if (commit || j < sp.ls_trials) {
+          if (j < sp.ls_trials) {
             double alpha = 1.0;
             for (int q = 0; q < j; ++q) alpha *= sp.beta;
-            // alpha = 1 (j == 0) is written while it runs, as is every trial of a
-            // one-lane group; the commit is written by the group's lead lane
-            const bool wr = commit ? lead : (j == 0 || GL == 1);
-            Jh = LN::template trial<GL, BOX>(mdl, w, s, T, buf, buf ^ 1, R(alpha), commit ? __builtin_inf() : J, wr,
-                                             steps, stage, r, gbase, R(sp.umax));
+            // alpha = 1 (j == 0) is written while it runs, as is every trial
+            // of a one-lane group
+            Jh = LN::template trial<GL, BOX>(mdl, w, s, T, buf, buf ^ 1, R(alpha), J, j == 0 || GL == 1, steps,
+                                             stage, r, gbase, R(sp.umax));
           }
           ++npass;
-          if (commit) {
-            Jn = Jh;
-            nread += steps;
-            nwrite += steps;
-            break;
-          }
           // the lanes of a group read the same data: a round moves as many steps
           // as its longest trial; only the alpha = 1 trial (or every trial of a
           // one-lane group) writes
@@ -1174,7 +1170,18 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
           }
           j0 += GL;
           if (acc == 0 || (acc > 0 && GL == 1) || (acc < 0 && j0 >= sp.ls_trials)) break;
-          if (acc > 0) commit = true;
+          if (acc > 0) {
+            // the group's lead lane writes the replay
+            double alpha = 1.0;
+            for (int q = 0; q < acc; ++q) alpha *= sp.beta;
+            int rs = 0;
+            LN::template trial<GL, BOX, true>(mdl, w, s, T, buf, buf ^ 1, R(alpha), __builtin_inf(), lead, rs,
+                                              stage, r, gbase, R(sp.umax));
+            ++npass;
+            nread += rs;
+            nwrite += rs;
+            break;
+          }
         }
         nbuf_acc = buf ^ 1;
       }
