@@ -49,27 +49,30 @@ SERVING_RATES = (1000, 2000, 5000, 10000, 20000, 50000)
 # sha256 is recorded); otherwise traffic is reported as null.
 FETCH_SCALE = 524288.0 / 262159.0
 WRITE_SCALE = 524288.0 / 524288.0
-LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.hpp")
-QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.hpp", "k_group_quad.hip")
+# (the kernels' sources, and the host code that orders the slots they iterate)
+LANE_SOURCES = ("dev_common.hpp", "dev_systems.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.hpp",
+                "common.hip", "capi.cpp")
+QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.hpp", "k_group_quad.hip",
+                "common.hip", "capi.cpp")
 # per launch, from the counter runs listed in each profile (sq_active_inst_valu:
 # SQ_ACTIVE_INST_VALU, in 4-cycle units)
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "454ec0693a2b7e3f04095a9b6e6b90ab439e9edc7d236833c20bf2aabbd1ac63",
-        "fetch_kib": 222952.4, "write_kib": 312919.1, "sq_active_inst_valu": 230263734.0,
+        "sha256": "b23289b00dd79b44c42c5abae425b1dddea985aa09f1f5285a1b137c570ac987",
+        "fetch_kib": 230394.6, "write_kib": 315795.2, "sq_active_inst_valu": 194877498.6,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "a5fddf8080bc73b6e662fcf7aad5fabf147ec7c3e30e7f3f84b5cc33408bbe85",
-        "fetch_kib": 1478655.1, "write_kib": 12107545.8, "sq_active_inst_valu": 6013768104.0,
+        "sha256": "8502533a3df8796d79a04bab3481c83dba1ef8a1b7a2139547effdde452febcb",
+        "fetch_kib": 1479800.0, "write_kib": 12126325.2, "sq_active_inst_valu": 5718231209.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "a9cfbea2f7c65512b50785a9c89d71b0c4db216ef56f557d9f92fcd5409915cf",
-        "fetch_kib": 1965510.4, "write_kib": 2118691.4, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "66f5e02809d62a08dfdffd4df3090e3a89b9ffcc5f4a35f8a990df9e4a204fa0",
+        "fetch_kib": 1955228.4, "write_kib": 2119695.3, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
