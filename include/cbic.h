@@ -277,7 +277,7 @@ cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, int32_t B, 
  * stop (opts->rtol) and at most `cap` iterations (1..100000; the paper uses
  * 1000), then returns the nearest-rank 99th (*p99) and 50th (*p50) percentiles
  * of the per-instance accepted-iteration counts: the budget for batches
- * warm-started naively and from a trained actor, respectively.  An instance
+ * warm-started with zero controls and from a trained actor, respectively.  An instance
  * stopped by the cap counts as `cap`; instances with an invalid horizon are
  * left out.  opts supplies precision, eps and the line search; its stop_mode
  * and max_iter are replaced.  hist (optional, host, cap + 1 entries) receives

@@ -2,7 +2,7 @@
 // instance for the same number of iterations, so the budget is read off the
 // distribution of the iterations the instances need: solve a large batch with
 // the relative-decrease stop under a high cap and take the 99th percentile
-// (for the naive warm start) and the median (for warm starts from a trained
+// (for the zero-control warm start) and the median (for warm starts from a trained
 // actor) of the per-instance iteration counts.
 #include <algorithm>
 #include <vector>
