@@ -252,6 +252,271 @@ struct Lane {
     return gains_update<BOX>(w, s, k, Qx, Qu, Qxx, Quu, Qux, P, p, store, mu, u, umax);
   }
 
+  // riccati_step_si split over a lane pair (lanes 2j, 2j + 1 of a group; h =
+  // r & 1) for the 6-state, 3-control system: each lane forms the columns
+  // J_h of P A, C^T P A, Q_xx, Q_ux, K and of the updated P (J_0 = {0, 2, 5},
+  // J_1 = {1, 3, 4}: 10 and 11 entries of the upper triangle), the pair swaps
+  // Q_ux and the new P (DPP), and the shared small terms (P C, P B, Q_uu, the
+  // Cholesky, k, p) are formed by both.  Every entry comes from the same
+  // formula as in riccati_step_si, so the results agree bit for bit with a
+  // one-lane group.
+  __device__ static __forceinline__ R psel(int h, R a, R b) { return h ? b : a; }
+  template <bool BOX>
+  __device__ static __forceinline__ uint32_t riccati_step_si_pair(const LaneState<R>& w, int s, int k, R dt,
+                                                                  const R (&V)[N / 2][N], const R (&W)[N / 2][M],
+                                                                  const R (&lx)[N], const R (&lu)[M],
+                                                                  const R (&Qc)[N][N], const R (&Rc)[M][M],
+                                                                  R (&P)[N][N], R (&p)[N], double mu,
+                                                                  const R (&u)[M], double umax, int h) {
+    static_assert(N == 6 && M == 3, "the column split is laid out for 6 states and 3 controls");
+    constexpr int NQ = N / 2;
+    constexpr int J0[3] = {0, 2, 5}, J1[3] = {1, 3, 4};
+    constexpr int JN = 3;
+    R PC[N][NQ];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) PC[i][c] = dt * P[i][c] + P[i][NQ + c];
+    // own columns of V
+    R Vo[NQ][JN];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c)
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) Vo[c][jj] = psel(h, V[c][J0[jj]], V[c][J1[jj]]);
+    R PAo[N][JN], PB[N][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) {
+        R v = psel(h, J0[jj] < NQ ? P[i][J0[jj]] : R(0), J1[jj] < NQ ? P[i][J1[jj]] : R(0));
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) v += PC[i][c] * Vo[c][jj];
+        PAo[i][jj] = v;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        R v = R(0);
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) v += PC[i][c] * W[c][m];
+        PB[i][m] = v;
+      }
+    }
+    R CPAo[NQ][JN], CPB[NQ][M], Cp[NQ];
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) CPAo[c][jj] = dt * PAo[c][jj] + PAo[NQ + c][jj];
+#pragma unroll
+      for (int m = 0; m < M; ++m) CPB[c][m] = dt * PB[c][m] + PB[NQ + c][m];
+      Cp[c] = dt * p[c] + p[NQ + c];
+    }
+    R Qx[N], Qu[M];
+    double Quu[M][M];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R v = lx[i] + (i < NQ ? p[i] : R(0));
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) v += V[c][i] * Cp[c];
+      Qx[i] = v;
+    }
+    // Q_xx on the own columns, rows i <= j (slot (i, jj) is used where i <= J_h[jj])
+    R Qxxo[N][JN];
+#pragma unroll
+    for (int jj = 0; jj < JN; ++jj) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i > (J0[jj] > J1[jj] ? J0[jj] : J1[jj])) continue;
+        R q = psel(h, Qc[i][J0[jj]], Qc[i][J1[jj]]) + (i < NQ ? PAo[i][jj] : R(0));
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += V[c][i] * CPAo[c][jj];
+        Qxxo[i][jj] = q;
+      }
+    }
+    R Quxo[M][JN];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      R v = lu[m];
+#pragma unroll
+      for (int c = 0; c < NQ; ++c) v += W[c][m] * Cp[c];
+      Qu[m] = v;
+#pragma unroll
+      for (int n = m; n < M; ++n) {
+        R q = Rc[m][n];
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += W[c][m] * CPB[c][n];
+        Quu[m][n] = double(q);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) {
+        R q = R(0);
+#pragma unroll
+        for (int c = 0; c < NQ; ++c) q += W[c][m] * CPAo[c][jj];
+        Quxo[m][jj] = q;
+      }
+    }
+    // ---- gains (as gains_update, on the own columns)
+    if (mu != 0.0)
+#pragma unroll
+      for (int i = 0; i < M; ++i) Quu[i][i] += mu;
+    constexpr int NR = sizeof(R) == 4 ? 1 : 2;
+    double Lc[M][M], invd[M];
+    uint32_t bad = chol_fp64<M, NR>(Quu, Lc, invd) ? 0u : ST_CHOL_FAIL;
+    R Ko[M][JN], kk[M];
+    bool fin = true;
+    bool solved = false;
+    if constexpr (sizeof(R) == 4) {
+      float lf[M][M], ivf[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        ivf[i] = float(invd[i]);
+#pragma unroll
+        for (int j = 0; j < M; ++j) lf[i][j] = float(Lc[i][j]);
+      }
+      auto solve = [&](float (&b)[M]) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = 0; k2 < i; ++k2) v -= lf[i][k2] * b[k2];
+          b[i] = v * ivf[i];
+        }
+#pragma unroll
+        for (int i = M - 1; i >= 0; --i) {
+          float v = b[i];
+#pragma unroll
+          for (int k2 = i + 1; k2 < M; ++k2) v += lf[k2][i] * b[k2];
+          b[i] = v * -ivf[i];
+        }
+      };
+      float col[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) col[i] = Qu[i];
+      solve(col);
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        kk[i] = col[i];
+        fin = fin && dfinite(kk[i]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) col[i] = Quxo[i][jj];
+        solve(col);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          Ko[i][jj] = col[i];
+          fin = fin && dfinite(Ko[i][jj]);
+        }
+      }
+      solved = true;
+      if constexpr (BOX) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          const double d = double(kk[i]);
+          solved = solved && d >= -umax - double(u[i]) && d <= umax - double(u[i]);
+        }
+        if (!solved) fin = true;
+      }
+    }
+    if (!solved) {
+      double col[M];
+#pragma unroll
+      for (int i = 0; i < M; ++i) col[i] = double(Qu[i]);
+      chol_solve_neg_fp64<M>(Lc, invd, col);
+      unsigned held = 0;
+      if constexpr (BOX) {
+        double g[M], lo[M], hi[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          g[i] = double(Qu[i]);
+          lo[i] = -umax - double(u[i]);
+          hi[i] = umax - double(u[i]);
+        }
+        if (!box_qp<M, NR>(Quu, g, lo, hi, col, held, Lc, invd) && !bad) bad = ST_CHOL_FAIL;
+      }
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        kk[i] = R(col[i]);
+        fin = fin && dfinite(kk[i]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) col[i] = ((held >> i) & 1u) ? 0.0 : double(Quxo[i][jj]);
+        chol_solve_neg_fp64<M>(Lc, invd, col);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          Ko[i][jj] = R(col[i]);
+          fin = fin && dfinite(Ko[i][jj]);
+        }
+      }
+    }
+    // the pair's verdict on its gains (the partner checked its own columns)
+    fin = fin && (__builtin_amdgcn_mov_dpp(int(fin), 0xB1, 0xF, 0xF, true) != 0);
+    if (!fin && !bad) bad = ST_NONFINITE;
+    {
+      // every lane stores its own columns of K and k
+      R* dK = Kp(w, k, s);
+#pragma unroll
+      for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int jj = 0; jj < JN; ++jj) dK[i * N + (h ? J1[jj] : J0[jj])] = Ko[i][jj];
+      st(kp(w, k, s), kk);
+    }
+    // Q_ux on all columns: own and the partner's
+    R Quxp[M][JN];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) Quxp[m][jj] = pair_swap(Quxo[m][jj]);
+    R Qux[M][N];
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int jj = 0; jj < JN; ++jj) {
+        Qux[m][J0[jj]] = psel(h, Quxo[m][jj], Quxp[m][jj]);
+        Qux[m][J1[jj]] = psel(h, Quxp[m][jj], Quxo[m][jj]);
+      }
+    // P = sym(Q_xx + Q_ux^T K) on the own columns, p = Q_x + Q_ux^T k
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R v = Qx[i];
+#pragma unroll
+      for (int t = 0; t < M; ++t) v += Qux[t][i] * kk[t];
+      p[i] = v;
+    }
+    R Po[N][JN];
+#pragma unroll
+    for (int jj = 0; jj < JN; ++jj)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i > (J0[jj] > J1[jj] ? J0[jj] : J1[jj])) continue;
+        R q = Qxxo[i][jj];
+#pragma unroll
+        for (int t = 0; t < M; ++t) q += Qux[t][i] * Ko[t][jj];
+        Po[i][jj] = q;
+      }
+    // the partner's columns, then the full symmetric P
+#pragma unroll
+    for (int jj = 0; jj < JN; ++jj)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        if (i > (J0[jj] > J1[jj] ? J0[jj] : J1[jj])) continue;
+        const R mine = Po[i][jj], other = pair_swap(Po[i][jj]);
+        if (i <= J0[jj]) {
+          const R v = psel(h, mine, other);
+          P[i][J0[jj]] = v;
+          P[J0[jj]][i] = v;
+        }
+        if (i <= J1[jj]) {
+          const R v = psel(h, other, mine);
+          P[i][J1[jj]] = v;
+          P[J1[jj]][i] = v;
+        }
+      }
+    return bad;
+  }
+
   // The control step and the (P, p) update from the step's Q blocks (Q_xx
   // and Q_uu upper triangles): Cholesky of Q_uu (+ mu I in the
   // Levenberg-Marquardt variant) in FP64 (one Newton step on the reciprocal
@@ -754,8 +1019,11 @@ struct Lane {
             // every lane stores the gains (the group's lanes hold the same
             // values): no branch per step; a failure ends the sweep at the
             // end of the chunk
-            const uint32_t b =
-                riccati_step_si<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, true, mu, uq, umax);
+            uint32_t b;
+            if constexpr (GL >= 2 && N == 6 && M == 3)
+              b = riccati_step_si_pair<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, mu, uq, umax, r & 1);
+            else
+              b = riccati_step_si<BOX>(w, s, kc - q, dt, V, W, lx, lu, Qc, Rc, P, p, true, mu, uq, umax);
             if (!chunk_bad) chunk_bad = b;
           } else {
             R A[N][N], B[N][M], lx[N], lu[M], Qc[N][N], Rc[M][M];
