@@ -59,20 +59,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "b23289b00dd79b44c42c5abae425b1dddea985aa09f1f5285a1b137c570ac987",
-        "fetch_kib": 230394.6, "write_kib": 315795.2, "sq_active_inst_valu": 194877498.6,
+        "sha256": "7e0a576435e27f949cd29f4619f18a65a0703ef8c8e60f91445bf3e41d7440fb",
+        "fetch_kib": 230426.5, "write_kib": 315775.8, "sq_active_inst_valu": 194756093.4,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "8502533a3df8796d79a04bab3481c83dba1ef8a1b7a2139547effdde452febcb",
-        "fetch_kib": 1479800.0, "write_kib": 12126325.2, "sq_active_inst_valu": 5718231209.2,
+        "sha256": "da2eefe3472131d3892539a71644ccfac4abd18110c7a55105787ba8d1ec746c",
+        "fetch_kib": 1476300.2, "write_kib": 12142607.1, "sq_active_inst_valu": 5071045455.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "66f5e02809d62a08dfdffd4df3090e3a89b9ffcc5f4a35f8a990df9e4a204fa0",
-        "fetch_kib": 1955228.4, "write_kib": 2119695.3, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "542bd11feb41125f7980971bd5abbfdf0bd0eb9c290f9f34d2b464a973add7ef",
+        "fetch_kib": 1963528.5, "write_kib": 2121470.1, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
