@@ -57,22 +57,22 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 # per launch, from the counter runs listed in each profile (sq_active_inst_valu:
 # SQ_ACTIVE_INST_VALU, in 4-cycle units)
 COUNTERS = {
-    ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false>"): {
+    ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "7e0a576435e27f949cd29f4619f18a65a0703ef8c8e60f91445bf3e41d7440fb",
-        "fetch_kib": 230426.5, "write_kib": 315775.8, "sq_active_inst_valu": 194756093.4,
+        "sha256": "0b77e85fb0f61c5e960872de9f6ad3c29d1f6b1f5e2b8d0932ec5f8d80749609",
+        "fetch_kib": 260797.3, "write_kib": 474394.8, "sq_active_inst_valu": 200984205.3,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
-    ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false>"): {
+    ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "da2eefe3472131d3892539a71644ccfac4abd18110c7a55105787ba8d1ec746c",
-        "fetch_kib": 1476300.2, "write_kib": 12142607.1, "sq_active_inst_valu": 5071045455.2,
+        "sha256": "78ad9e59a525f6c0169055b079d539114b4fa0c1e9463bc0a162d0c3a2d5a2c2",
+        "fetch_kib": 1490459.9, "write_kib": 12258811.6, "sq_active_inst_valu": 5086073361.8,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "542bd11feb41125f7980971bd5abbfdf0bd0eb9c290f9f34d2b464a973add7ef",
-        "fetch_kib": 1963528.5, "write_kib": 2121470.1, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "87a9f3e02cb7594f2e7fb7b5bee8664ec218d695ee8a7d7603ec0255827ca5ec",
+        "fetch_kib": 1957350.1, "write_kib": 2120878.6, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
@@ -134,6 +134,19 @@ def alg_bytes(work, Tb, n, m, elem):
     per_step = n + m + m * n + m
     words = sweeps * (Tb * per_step + n) + reads * per_step + writes * (n + m)
     return float(words.sum() * elem)
+
+
+def final_bytes(Tb, Tmax, n, m, elem, targets=True):
+    """Algorithmic HBM bytes of the finalisation, which a solve in one launch
+    runs inside the iteration kernel: it reads each instance's final
+    trajectory (x_0..x_T, u_0..u_{T-1}) and writes the FP64 outputs padded to
+    T_max (X, U and, with the critic targets, V-bar, V_x and x_{k+K}) and the
+    per-instance scalars (J, iterations, status, the four work counters)."""
+    Tb = np.asarray(Tb, np.float64)
+    reads = ((Tb + 1) * n + Tb * m).sum() * elem
+    rows = (Tmax + 1) * n + Tmax * m + ((Tmax + 1) * (1 + 2 * n) if targets else 0)
+    writes = len(Tb) * (rows * 8 + 32)
+    return float(reads + writes)
 
 
 def alg_flops(work, Tb, n, m):
@@ -216,12 +229,19 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
         conv = int(np.sum(rel <= 1e-4))
         elem = 8 if opts.precision == cbic.FP64 else 4
         nb = alg_bytes(work, Tvec, n, m, elem)
+        # a lane-schedule solve in one launch finalises inside the iteration
+        # kernel, whose time then holds both (its finalisation phase is 0)
+        fused = kind != I.SYS_QUAD_SYNTH and not (opts.flags & cbic.FLAG_GRAPH) and (
+            opts.iters_per_launch <= 0 or opts.iters_per_launch >= opts.max_iter)
+        nfin = final_bytes(Tvec, T, n, m, 8) if fused else 0.0
+        nb += nfin
         nf = alg_flops(work, Tvec, n, m)
         results[fname] = dict(
             ms_per_step=ms, p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
             converged=conv, converged_frac=conv / B, solves_per_s=B / (ms / 1e3),
             converged_solves_per_s=conv / (ms / 1e3), max_rel_cost_vs_fp64=float(np.nanmax(rel)),
             iterate_ms=ph[1], init_ms=ph[0], final_ms=ph[2], iterate_alg_bytes=nb,
+            iterate_includes_finalize=fused, finalize_alg_bytes=nfin,
             iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
             iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
             mean_sweeps=float(work[:, 0].mean()), lanes_per_instance=width)
@@ -307,7 +327,8 @@ def roofline_for(name, form, res, form_opts):
                 "valu_issue_frac": None if vf is None else round(vf, 4)}
     sysname = {"pm16k": "PointMass", "pm64": "PointMass", "arm4k": "Arm3"}[name]
     bounded = "true" if np.isfinite(form_opts.u_max) else "false"
-    kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']},{bounded}>"
+    fin = "true" if res.get("iterate_includes_finalize") else "false"
+    kernel = f"lane_iterate<{sysname},{prec},{res['lanes_per_instance']},{bounded},{fin}>"
     vf = valu_issue_frac(name, form, kernel, res["iterate_ms"])
     return {"bound": "hbm", "achieved": round(res["iterate_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(res["iterate_GBps"] / HBM_PEAK_GBS, 5), "traffic": traffic_for(name, form, kernel),

@@ -291,9 +291,12 @@ cbic_status cbic_calibrate_max_iter(cbic_context* ctx, const cbic_system* sys, i
 /* Milliseconds spent by the last solve on this context that was launched with
  * CBIC_FLAG_TIMING in its three phases: ms[0] warm start and initial rollout
  * (with the iteration order of CBIC_FLAG_INPUT_ORDER's default), ms[1] the
- * iteration kernels (backward sweeps and line searches), ms[2]
- * finalisation (status, critic targets, outputs).  Waits for that solve's
- * stream work to finish.  CBIC_E_INVALID if no timed solve was launched. */
+ * iteration kernels (backward sweeps and line searches), ms[2] finalisation
+ * (status, critic targets, outputs).  A lane-schedule solve in one launch
+ * (without CBIC_FLAG_GRAPH, iters_per_launch <= 0 or >= max_iter) finalises
+ * each instance inside the iteration kernel as soon as it stops iterating:
+ * ms[1] then holds both and ms[2] is 0.  Waits for that solve's stream work
+ * to finish.  CBIC_E_INVALID if no timed solve was launched. */
 cbic_status cbic_phase_times(cbic_context* ctx, double* ms3);
 
 /* ---------------------------------------------------------------- serving

@@ -244,6 +244,22 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
     const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
     const int chunks = (opts->max_iter + G - 1) / G;
     const bool graph = (opts->flags & CBIC_FLAG_GRAPH) && stream != nullptr;
+    if (!graph && chunks == 1 && L->iterate_final) {
+      // one launch: every group finalises its slot as soon as it stops
+      // iterating (the finalisation then overlaps the other groups'
+      // iterations; the same results as the two launches below).  Timed,
+      // the finalisation counts with the iterations and its own phase is 0.
+      const FinalOutH fo{out->X,    out->U,  out->J,  out->iters,      out->status,
+                         out->Vbar, out->Vx, out->xK, out->cost_trace, out->work};
+      HIP_TRY(L->iterate_final(prm, base, B, Tmax, B, order, sp, G, group, tr, Tmax, opts->lookahead_K, fo,
+                               stream));
+      if (timing) {
+        HIP_TRY(hipEventRecord(ctx->phase_ev[2], stream));
+        HIP_TRY(hipEventRecord(ctx->phase_ev[3], stream));
+      }
+      ctx->timed = ctx->timed || timing;
+      return CBIC_OK;
+    }
     if (!graph) {
       for (int c = 0; c < chunks; ++c)
         HIP_TRY(L->iterate(prm, base, B, Tmax, B, order, sp, G, group, tr, stream));

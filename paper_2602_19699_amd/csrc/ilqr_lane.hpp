@@ -1200,6 +1200,19 @@ struct Lane {
   }
 };
 
+struct FinalOut {
+  double* X;      // [B][Tmax+1][N]
+  double* U;      // [B][Tmax][M]
+  double* J;      // [B]
+  int32_t* iters;
+  uint32_t* status;
+  double* Vbar;   // [B][Tmax+1] or null
+  double* Vx;     // [B][Tmax+1][N] or null
+  double* xK;     // [B][Tmax+1][N] or null
+  double* trace;  // [B][max_iter+1] or null
+  int32_t* work;  // [B][2] or null
+};
+
 // ====================================================================== kernels
 // Warm start and initial rollout, GL lanes per instance: group g initialises
 // slot slots[g] (or g) from caller instance perm[g] (or g).  The rollout runs
@@ -1287,6 +1300,12 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   if (trace) trace[size_t(slots ? s : b) * (max_iter + 1)] = J;
 }
 
+template <class Sys, class R, int GL>
+__device__ __forceinline__ void final_group(const double* __restrict__ prm, const LaneState<R>& w, int s, int b,
+                                            int Ts, int buf, uint32_t st, double J, int iters,
+                                            const int (&wk)[4], int r, int Tmax, int max_iter, int lookahead,
+                                            const FinalOut& o);
+
 // Up to `iters` iterations for every active slot, with GL lanes per instance.
 // The GL lanes of a group run the backward sweep redundantly (identical
 // arithmetic on identical data; the point mass splits each step over lane
@@ -1300,10 +1319,15 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 // for sparse slot sets.
 //
 // BOX selects the variant with the control bound of eq. 1 (sp.umax finite).
-template <class Sys, class R, int GL, bool BOX>
+//
+// FIN: the launch is the solve's last, and each group finalises its slot
+// (final_group) as soon as it has stopped iterating, while other groups still
+// iterate; every slot of the list is finalised, frozen ones included.
+template <class Sys, class R, int GL, bool BOX, bool FIN = false>
 __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ prm, LaneState<R> w,
                                                    int nslots, const int32_t* __restrict__ slots,
-                                                   SolveParams sp, int iters_this_launch, IterTrace tr) {
+                                                   SolveParams sp, int iters_this_launch, IterTrace tr,
+                                                   int Tmax = 0, int lookahead = 0, FinalOut fo = {}) {
   using LN = Lane<Sys, R>;
   static_assert(GL >= 1 && GL <= 16 && (GL & (GL - 1)) == 0, "group width must be a power of two <= 16");
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1312,7 +1336,7 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
   if (gi >= nslots) return;  // whole groups leave together
   const int s = slots ? slots[gi] : gi;
   uint32_t st = w.status[s];
-  if (st) return;
+  if (st && !FIN) return;
   const bool lead = (r == 0);
   const int gbase = (threadIdx.x & 63) & ~(GL - 1);  // first lane of this group in the wave
   const typename LN::Model mdl{prm};
@@ -1490,54 +1514,42 @@ __global__ void __launch_bounds__(64) lane_iterate(const double* __restrict__ pr
     w.work[4 * s + 3] = nwrite;
     w.mu[s] = mu;
   }
+  if constexpr (FIN) {
+    const int wk[4] = {nsweep, npass, nread, nwrite};
+    final_group<Sys, R, GL>(prm, w, s, b, T, buf, st, J, iters, wk, r, Tmax, sp.max_iter, lookahead, fo);
+  }
 }
 
-struct FinalOut {
-  double* X;      // [B][Tmax+1][N]
-  double* U;      // [B][Tmax][M]
-  double* J;      // [B]
-  int32_t* iters;
-  uint32_t* status;
-  double* Vbar;   // [B][Tmax+1] or null
-  double* Vx;     // [B][Tmax+1][N] or null
-  double* xK;     // [B][Tmax+1][N] or null
-  double* trace;  // [B][max_iter+1] or null
-  int32_t* work;  // [B][2] or null
-};
 
 // GL lanes per instance (one group of a wave): the lanes split the output
 // copies and the stage costs by step; the costate recursion walks back over
 // the final trajectory in every lane of the group, fed chunk by chunk by the
 // group's lanes (a serial chain; lane 0 writes it), and lane 0 forms the
 // cost-to-go sums from the stage costs the group wrote, after a wave barrier.
+// The outputs of slot s by its group (lane r of GL): the slot's state (output
+// index b, horizon Ts, iterate buffer, status, J, iterations, work counters)
+// comes in registers, so that the iteration kernel can call this for its own
+// group right after its last iteration.
 template <class Sys, class R, int GL>
-__global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
-                                                 const int32_t* __restrict__ slots, int Tmax, int max_iter,
-                                                 int lookahead, FinalOut o) {
+__device__ __forceinline__ void final_group(const double* __restrict__ prm, const LaneState<R>& w, int s, int b,
+                                            int Ts, int buf, uint32_t st, double J, int iters,
+                                            const int (&wk)[4], int r, int Tmax, int max_iter, int lookahead,
+                                            const FinalOut& o) {
   using LN = Lane<Sys, R>;
   constexpr int N = Sys::N, M = Sys::M;
   static_assert(GL >= 1 && GL <= 64 && (GL & (GL - 1)) == 0, "group width");
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gi = tid / GL, r = tid & (GL - 1);
-  if (gi >= nslots) return;  // whole groups leave together
-  const int s = slots ? slots[gi] : gi;
   const bool lead = r == 0;
   const typename LN::Model mdl{prm};
-  const int b = w.inst[s];
-  const int buf = w.cur[s];
-  uint32_t st = w.status[s];
   if (st == 0) st = ST_MAX_ITER;  // iteration budget ended without freezing
   // an instance with an invalid horizon gets all-zero trajectory outputs
-  const int T = (st & ST_BAD_INPUT) ? -1 : w.T[s];
-  const double J = w.J[s];
-  const int iters = w.iters[s];
+  const int T = (st & ST_BAD_INPUT) ? -1 : Ts;
   if (lead) {
     o.J[b] = J;
     o.iters[b] = iters;
     o.status[b] = st;
     if (o.work)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) o.work[4 * b + i] = w.work[4 * s + i];
+      for (int i = 0; i < 4; ++i) o.work[4 * b + i] = wk[i];
   }
   if (o.trace)
     for (int i = iters + 1 + r; i <= max_iter; i += GL) o.trace[size_t(b) * (max_iter + 1) + i] = J;
@@ -1743,6 +1755,21 @@ __global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm,
       }
     }
   }
+}
+
+// Finalisation kernel: one group of GL lanes per slot (whole groups past
+// nslots leave).
+template <class Sys, class R, int GL>
+__global__ void __launch_bounds__(64) lane_final(const double* __restrict__ prm, LaneState<R> w, int nslots,
+                                                 const int32_t* __restrict__ slots, int Tmax, int max_iter,
+                                                 int lookahead, FinalOut o) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gi = tid / GL, r = tid & (GL - 1);
+  if (gi >= nslots) return;  // whole groups leave together
+  const int s = slots ? slots[gi] : gi;
+  const int wk[4] = {w.work[4 * s], w.work[4 * s + 1], w.work[4 * s + 2], w.work[4 * s + 3]};
+  final_group<Sys, R, GL>(prm, w, s, w.inst[s], w.T[s], w.cur[s], w.status[s], w.J[s], w.iters[s], wk, r, Tmax,
+                          max_iter, lookahead, o);
 }
 
 }  // namespace cbic

@@ -79,34 +79,51 @@ struct LaneLaunch {
   }
 
   // the bounded variant (eq. 1) is a kernel of its own, so that the
-  // unbounded one keeps its register allocation
-  template <int GL>
+  // unbounded one keeps its register allocation; FIN finalises in the same
+  // kernel (fo, Tmax, lookahead)
+  template <int GL, bool FIN>
   static hipError_t iterate_g(const double* prm, const LaneState<R>& w, int nthreads, const int32_t* slots,
-                              const SolveParams& sp, int G, const IterTrace& tr, hipStream_t st) {
+                              const SolveParams& sp, int G, const IterTrace& tr, int Tmax, int lookahead,
+                              const FinalOut& fo, hipStream_t st) {
     const long total = long(nthreads) * GL;
     if (__builtin_isfinite(sp.umax))
-      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, true>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                         nthreads, slots, sp, G, tr);
+      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, true, FIN>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm,
+                         w, nthreads, slots, sp, G, tr, Tmax, lookahead, fo);
     else
-      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, false>), dim3((total + WG - 1) / WG), dim3(WG), 0, st, prm, w,
-                         nthreads, slots, sp, G, tr);
+      hipLaunchKernelGGL((lane_iterate<Sys, R, GL, false, FIN>), dim3((total + WG - 1) / WG), dim3(WG), 0, st,
+                         prm, w, nthreads, slots, sp, G, tr, Tmax, lookahead, fo);
     return hipGetLastError();
+  }
+
+  template <bool FIN>
+  static hipError_t iterate_any(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                                const int32_t* slots, const SolveParamsH& sp, int G, int group, const IterTrace& tr,
+                                int Tmax, int lookahead, const FinalOut& fo, hipStream_t st) {
+    if (nthreads <= 0) return hipSuccess;
+    auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
+    const SolveParams d = to_dev(sp);
+    switch (group) {
+      case 1: return iterate_g<1, FIN>(prm, w, nthreads, slots, d, G, tr, Tmax, lookahead, fo, st);
+      case 2: return iterate_g<2, FIN>(prm, w, nthreads, slots, d, G, tr, Tmax, lookahead, fo, st);
+      case 4: return iterate_g<4, FIN>(prm, w, nthreads, slots, d, G, tr, Tmax, lookahead, fo, st);
+      case 8: return iterate_g<8, FIN>(prm, w, nthreads, slots, d, G, tr, Tmax, lookahead, fo, st);
+      case 16: return iterate_g<16, FIN>(prm, w, nthreads, slots, d, G, tr, Tmax, lookahead, fo, st);
+      default: return hipErrorInvalidValue;
+    }
   }
 
   static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
                             const int32_t* slots, const SolveParamsH& sp, int G, int group, const IterTrace& tr,
                             hipStream_t st) {
-    if (nthreads <= 0) return hipSuccess;
-    auto w = lane_state<R>(base, N, M, Bcap, Tcap, lane_bufs<Sys>());
-    const SolveParams d = to_dev(sp);
-    switch (group) {
-      case 1: return iterate_g<1>(prm, w, nthreads, slots, d, G, tr, st);
-      case 2: return iterate_g<2>(prm, w, nthreads, slots, d, G, tr, st);
-      case 4: return iterate_g<4>(prm, w, nthreads, slots, d, G, tr, st);
-      case 8: return iterate_g<8>(prm, w, nthreads, slots, d, G, tr, st);
-      case 16: return iterate_g<16>(prm, w, nthreads, slots, d, G, tr, st);
-      default: return hipErrorInvalidValue;
-    }
+    return iterate_any<false>(prm, base, Bcap, Tcap, nthreads, slots, sp, G, group, tr, 0, 0, FinalOut{}, st);
+  }
+
+  static hipError_t iterate_final(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                                  const int32_t* slots, const SolveParamsH& sp, int G, int group,
+                                  const IterTrace& tr, int Tmax, int lookahead, const FinalOutH& o,
+                                  hipStream_t st) {
+    const FinalOut fo{o.X, o.U, o.J, o.iters, o.status, o.Vbar, o.Vx, o.xK, o.trace, o.work};
+    return iterate_any<true>(prm, base, Bcap, Tcap, nthreads, slots, sp, G, group, tr, Tmax, lookahead, fo, st);
   }
 
   static hipError_t finalize(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
@@ -124,8 +141,8 @@ struct LaneLaunch {
   }
 
   static const Launcher* get() {
-    static const Launcher L{N, M, int(sizeof(R)), CBIC_SCHED_LANE, &ws_bytes, &init, &iterate, &finalize, 0,
-                            lane_bufs<Sys>()};
+    static const Launcher L{N,         M,       int(sizeof(R)), CBIC_SCHED_LANE, &ws_bytes, &init, &iterate,
+                            &finalize, 0,       lane_bufs<Sys>(), &iterate_final};
     return &L;
   }
 };

@@ -79,6 +79,12 @@ struct Launcher {
   size_t slot_extra = 0;
   // trajectory buffers of the lane layout
   int nbuf = 2;
+  // optional: the iterations of a solve's only launch with every group
+  // finalising its slot as soon as it stops (iterate then finalize in one
+  // kernel; the same results)
+  hipError_t (*iterate_final)(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
+                              const int32_t* slots, const SolveParamsH& sp, int G, int group, const IterTrace& tr,
+                              int Tmax, int lookahead, const FinalOutH& o, hipStream_t st) = nullptr;
 };
 
 const Launcher* find_launcher(int kind, int n, int m, int precision, int schedule);
