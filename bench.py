@@ -59,19 +59,19 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "0b77e85fb0f61c5e960872de9f6ad3c29d1f6b1f5e2b8d0932ec5f8d80749609",
+        "sha256": "dda7f46ceaf488bd5942331b68e9d91c6721bc8275c4846c282548d5a848352b",
         "fetch_kib": 260797.3, "write_kib": 474394.8, "sq_active_inst_valu": 200984205.3,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "78ad9e59a525f6c0169055b079d539114b4fa0c1e9463bc0a162d0c3a2d5a2c2",
+        "sha256": "37b1cbd4471f8caf99fe3fa019afc255dcb7c4e2e6b11fce084c03d02dde717a",
         "fetch_kib": 1490459.9, "write_kib": 12258811.6, "sq_active_inst_valu": 5086073361.8,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "87a9f3e02cb7594f2e7fb7b5bee8664ec218d695ee8a7d7603ec0255827ca5ec",
+        "sha256": "23c0bc2a9be925ceb26840f6c9c486094ed6ce3940ceaa60f2fbec1b5a48ba0e",
         "fetch_kib": 1957350.1, "write_kib": 2120878.6, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },

@@ -451,7 +451,7 @@ struct Lane {
         }
       }
     }
-    // the pair's verdict on its gains (the partner checked its own columns)
+    // the pair's finiteness check of its gains (the partner checked its own columns)
     fin = fin && (__builtin_amdgcn_mov_dpp(int(fin), 0xB1, 0xF, 0xF, true) != 0);
     if (!fin && !bad) bad = ST_NONFINITE;
     {
