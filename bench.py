@@ -15,9 +15,10 @@ form (instances outside the bar do not count).
 The same run measures the other workloads (64 point-mass instances for
 latency, 4096 arm instances with horizons 50..200, 1024 quadruped-sized
 instances) and the serving loop, each with the roofline of its dominant
-kernel (HIP events around the iteration kernel on its stream; algorithmic
-bytes or flops from the per-instance work counters) and the FP64 CPU oracle
-timed on a bounded sample on this host.
+kernel (HIP events around the iteration kernel on its stream, which for a
+lane-schedule solve also finalises the instances; algorithmic bytes or flops
+from the per-instance work counters and the output sizes) and the FP64 CPU
+oracle timed on a bounded sample on this host.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
