@@ -1246,6 +1246,11 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   for (int i = 0; i < N; ++i) x[i] = R(x0[size_t(b) * N + i]);
   for (int q = r; q < w.nbuf; q += GL) LN::st(LN::xp(w, q, 0, s), x);
   double J = 0.0;
+  // a chunk's stage costs are gathered from their lanes at the chunk's end and
+  // added to J after the next chunk's rollout (the same order of additions),
+  // so that the rollout does not wait for the exchange
+  double cprev[GL];
+  int cnprev = 0;
   for (int kc = 0; kc < T; kc += GL) {
     const int kr = kc + r;
     const int cn = T - kc < GL ? T - kc : GL;
@@ -1279,8 +1284,14 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
     }
 #pragma unroll
     for (int q = 0; q < GL; ++q)
-      if (q < cn) J += GL == 1 ? c : __shfl(c, gbase + q, 64);
+      if (q < cnprev) J += cprev[q];
+#pragma unroll
+    for (int q = 0; q < GL; ++q) cprev[q] = GL == 1 ? c : __shfl(c, gbase + q, 64);
+    cnprev = cn;
   }
+#pragma unroll
+  for (int q = 0; q < GL; ++q)
+    if (q < cnprev) J += cprev[q];
   if (r != 0) return;
   J += double(mdl.term(x));
   uint32_t st = isfinite(J) ? 0u : ST_NONFINITE;
