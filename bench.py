@@ -60,20 +60,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "dda7f46ceaf488bd5942331b68e9d91c6721bc8275c4846c282548d5a848352b",
-        "fetch_kib": 260797.3, "write_kib": 474394.8, "sq_active_inst_valu": 200984205.3,
+        "sha256": "d568630b57e73eb0044910be7b920d6bfd16c8ec5775943d32136647f27b4798",
+        "fetch_kib": 260745.2, "write_kib": 474424.8, "sq_active_inst_valu": 200774035.0,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "37b1cbd4471f8caf99fe3fa019afc255dcb7c4e2e6b11fce084c03d02dde717a",
-        "fetch_kib": 1490459.9, "write_kib": 12258811.6, "sq_active_inst_valu": 5086073361.8,
+        "sha256": "a151f92053d0e7e0f0962496b4edd21cccf2a3a71d28e34dd04a8f8ffa2a8160",
+        "fetch_kib": 1490652.0, "write_kib": 12258964.3, "sq_active_inst_valu": 5100079191.8,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "23c0bc2a9be925ceb26840f6c9c486094ed6ce3940ceaa60f2fbec1b5a48ba0e",
-        "fetch_kib": 1957350.1, "write_kib": 2120878.6, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "4bd98d7e3fa38f3df4736f46483e63780c37c3165e118874e79c2a13027fabbd",
+        "fetch_kib": 1961072.3, "write_kib": 2119855.5, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
