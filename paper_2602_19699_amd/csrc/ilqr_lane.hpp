@@ -1254,26 +1254,24 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   for (int kc = 0; kc < T; kc += GL) {
     const int kr = kc + r;
     const int cn = T - kc < GL ? T - kc : GL;
-    R ur[M], xr[N], xr1[N];
+    R ur[M], xr[N] = {}, xr1[N] = {};
 #pragma unroll
     for (int i = 0; i < M; ++i)
       ur[i] = kr < T ? clamp_nan(U0 ? R(U0[(size_t(b) * Tmax + kr) * M + i]) : R(0), R(umax)) : R(0);
+    // every lane steps through the whole chunk without a branch: past the
+    // horizon the state stays at x_T (the extra steps are never kept)
 #pragma unroll
     for (int q = 0; q < GL; ++q) {
-      if (q < cn) {
-        R u[M], xn[N];
+      R u[M], xn[N];
 #pragma unroll
-        for (int i = 0; i < M; ++i) u[i] = GL == 1 ? ur[i] : __shfl(ur[i], gbase + q, 64);
-        mdl.dyn(x, u, xn);
-        if (q == r) {
+      for (int i = 0; i < M; ++i) u[i] = GL == 1 ? ur[i] : __shfl(ur[i], gbase + q, 64);
+      mdl.dyn(x, u, xn);
+      const bool live = q < cn, mine = q == r;
 #pragma unroll
-          for (int i = 0; i < N; ++i) {
-            xr[i] = x[i];
-            xr1[i] = xn[i];
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = xn[i];
+      for (int i = 0; i < N; ++i) {
+        xr[i] = mine ? x[i] : xr[i];
+        xr1[i] = mine ? xn[i] : xr1[i];
+        x[i] = live ? xn[i] : x[i];
       }
     }
     double c = 0.0;
