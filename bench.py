@@ -60,20 +60,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "d568630b57e73eb0044910be7b920d6bfd16c8ec5775943d32136647f27b4798",
-        "fetch_kib": 260745.2, "write_kib": 474424.8, "sq_active_inst_valu": 200774035.0,
+        "sha256": "97ab3b38fd9e107cfbb49183a730e1bb128d34ef86ca8d4cb209ce916d897b80",
+        "fetch_kib": 260770.2, "write_kib": 474403.5, "sq_active_inst_valu": 200872578.2,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "a151f92053d0e7e0f0962496b4edd21cccf2a3a71d28e34dd04a8f8ffa2a8160",
-        "fetch_kib": 1490652.0, "write_kib": 12258964.3, "sq_active_inst_valu": 5100079191.8,
+        "sha256": "d92ad4405c200a41c4d297671b2d379fe7e9d5add1a6025f7f077ad976451734",
+        "fetch_kib": 1490684.5, "write_kib": 12258871.7, "sq_active_inst_valu": 5084758971.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "4bd98d7e3fa38f3df4736f46483e63780c37c3165e118874e79c2a13027fabbd",
-        "fetch_kib": 1961072.3, "write_kib": 2119855.5, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "4eb288ec34303b1b22dc93e06a7e09f0ec1bab8ee2a1724f6b02525f88d23f3d",
+        "fetch_kib": 1959831.3, "write_kib": 2119896.8, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
