@@ -70,7 +70,7 @@ COUNTERS = {
         "fetch_kib": 1490684.5, "write_kib": 12258871.7, "sq_active_inst_valu": 5084758971.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
-    ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false>"): {
+    ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
         "sha256": "4eb288ec34303b1b22dc93e06a7e09f0ec1bab8ee2a1724f6b02525f88d23f3d",
         "fetch_kib": 1959831.3, "write_kib": 2119896.8, "sq_active_inst_valu": 2292687872.0,
@@ -162,7 +162,7 @@ def time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup, autotune=True):
     B = x0d.shape[0]
     out = cbic.Outputs.allocate(B, T, sysm.n, sysm.m, dev, targets=True)
     width = None
-    if autotune and sysm.kind != 3:  # the quadruped has one schedule (a workgroup per instance)
+    if autotune:  # lanes per instance, or the quadruped's workgroups per CU
         width, _ = cbic.autotune(ctx, sysm, x0d, T, T=Td, opts=opts)
     for _ in range(warmup):
         cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=opts, out=out)
@@ -245,7 +245,8 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
             iterate_includes_finalize=fused, finalize_alg_bytes=nfin,
             iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
             iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
-            mean_sweeps=float(work[:, 0].mean()), lanes_per_instance=width)
+            mean_sweeps=float(work[:, 0].mean()))
+        results[fname]["wg_per_cu" if sysm.kind == 3 else "lanes_per_instance"] = width
         if np.isfinite(opts.u_max):
             Uo = out.U.cpu().numpy()
             results[fname]["u_max"] = opts.u_max
@@ -319,7 +320,7 @@ def roofline_for(name, form, res, form_opts):
         peak = FP64_PEAK_TFLOPS if form_opts.precision == 0 else FP32_PEAK_TFLOPS
         box = "true" if np.isfinite(form_opts.u_max) else "false"
         lm = "true" if form_opts.regularization == 1 else "false"
-        kernel = f"quad_iterate<{prec},{box},{lm}>"
+        kernel = f"quad_iterate<{prec},{box},{lm},{res['wg_per_cu']}>"
         vf = valu_issue_frac(name, form, kernel, res["iterate_ms"])
         return {"bound": "mfma", "achieved": round(res["iterate_TFLOPs"], 4), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(res["iterate_TFLOPs"] / peak, 5), "traffic": traffic_for(name, form, kernel),

@@ -125,6 +125,8 @@ typedef struct {
   double lm_mu_max;      /* CBIC_REG_LM: largest mu tried (>= lm_mu0); default 1e10            */
   double u_max;          /* control bound |u_k,i| <= u_max of eq. 1 (> 0); default +infinity
                             (unbounded); see below                                            */
+  int32_t wg_per_cu;     /* workgroup schedule: instances resident per compute unit, 1 or 2;
+                            0 = automatic.  See below                                         */
 } cbic_solve_opts;
 
 /* regularization of the backward sweep (paper Sec. IV-B)
@@ -155,6 +157,19 @@ typedef struct {
 /* schedule ids */
 #define CBIC_SCHED_LANE 1  /* one lane per instance, registers + step-major HBM          */
 #define CBIC_SCHED_GROUP 2 /* a workgroup per instance, matrices in LDS (37-dim system)   */
+
+/* wg_per_cu (workgroup schedule only; the lane schedule ignores it)
+ *   1  one instance per compute unit: the iteration kernel keeps all its
+ *      values in registers (one wave per SIMD)
+ *   2  two instances share a compute unit (two waves per SIMD): registers are
+ *      capped at 256 per lane and some values spill, but the second instance
+ *      hides the latency of the first one's serial chain; pays off once the
+ *      batch has more instances than the device has compute units
+ *   0  the autotuned choice for the problem class (cbic_autotune), else 1 for
+ *      batches of at most one instance per compute unit and 2 above
+ * FP64 solves always run one instance per compute unit (their shared-memory
+ * block is half a compute unit's, and two per unit were slower at every
+ * batch size measured).  No result depends on it. */
 
 /* flags */
 #define CBIC_FLAG_GRAPH 1u  /* launch the iteration chain through a captured HIP graph      */
@@ -260,14 +275,18 @@ cbic_status cbic_solve_batch_noalloc(cbic_context* ctx, const cbic_system* sys, 
                                      const int32_t* d_T, const double* d_x0, const double* d_U0,
                                      const cbic_solve_opts* opts, const cbic_outputs* out, void* stream);
 
-/* Autotune the lane schedule for one problem class: solve the given batch
- * (same arguments as cbic_solve_batch) once per lanes-per-instance width
- * 1, 2, 4, 8, 16, time each on `stream`, and remember the fastest in the
- * context for solves of the same system kind, precision, stop rule, iteration
- * budget, batch size (rounded up to a power of two) and T_max whose
- * group_lanes is 0.  Blocks until done; allocates scratch outputs.  The width
- * does not change results (the line-search rule picks the same step).
- * *best_group / *best_ms (may be NULL) receive the choice and its time. */
+/* Autotune the schedule for one problem class: solve the given batch (same
+ * arguments as cbic_solve_batch) once per candidate, time each on `stream`,
+ * and remember the fastest in the context for solves of the same system kind,
+ * precision, stop rule, iteration budget, batch size (rounded up to a power of
+ * two) and T_max.  The candidates are the lanes-per-instance widths 1, 2, 4,
+ * 8, 16 on the lane schedule (used by solves whose group_lanes is 0), and one
+ * or two instances per compute unit on the workgroup schedule in the mixed
+ * precision (used by solves whose wg_per_cu is 0; an FP64 workgroup solve has
+ * the one choice 1).  Blocks until done; allocates scratch outputs.  No
+ * candidate changes results (the line-search rule picks the same step).
+ * *best_group / *best_ms (may be NULL) receive the choice (the width, or the
+ * instances per compute unit) and its time. */
 cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, int32_t B, int32_t T_max, const int32_t* d_T,
                           const double* d_x0, const double* d_U0, const cbic_solve_opts* opts, void* stream,
                           int32_t* best_group, double* best_ms);

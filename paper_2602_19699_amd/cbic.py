@@ -39,7 +39,8 @@ class _Opts(C.Structure):
                 ("rtol", C.c_double), ("lookahead_K", C.c_int32), ("precision", C.c_int32),
                 ("schedule", C.c_int32), ("iters_per_launch", C.c_int32), ("group_lanes", C.c_int32),
                 ("flags", C.c_uint32), ("regularization", C.c_int32), ("lm_mu0", C.c_double),
-                ("lm_factor", C.c_double), ("lm_mu_max", C.c_double), ("u_max", C.c_double)]
+                ("lm_factor", C.c_double), ("lm_mu_max", C.c_double), ("u_max", C.c_double),
+                ("wg_per_cu", C.c_int32)]
 
 
 class _Outputs(C.Structure):
@@ -158,13 +159,14 @@ class Options:
     lm_factor: float = 10.0
     lm_mu_max: float = 1e10
     u_max: float = float("inf")  # control bound |u_k,i| <= u_max of eq. 1; inf: none
+    wg_per_cu: int = 0  # workgroup schedule: instances per compute unit (1, 2; 0 automatic)
 
     def c(self) -> _Opts:
         o = _Opts()
         _check(lib().cbic_opts_default(C.byref(o)))
         for f in ("max_iter", "psd_eps", "ls_max_trials", "ls_beta", "stop_mode", "rtol", "lookahead_K",
                   "precision", "schedule", "iters_per_launch", "group_lanes", "flags", "regularization",
-                  "lm_mu0", "lm_factor", "lm_mu_max", "u_max"):
+                  "lm_mu0", "lm_factor", "lm_mu_max", "u_max", "wg_per_cu"):
             setattr(o, f, getattr(self, f))
         return o
 
@@ -310,8 +312,10 @@ def solve_batch_noalloc(ctx: Context, sys: System, x0, T_max: int, out: Outputs,
 
 def autotune(ctx: Context, sys: System, x0, T_max: int, T=None, U0=None, opts: Options | None = None,
              stream=None):
-    """Time every lanes-per-instance width on this problem; the context keeps
-    the fastest for later solves with group_lanes=0.  Returns (width, ms)."""
+    """Time every schedule candidate on this problem (lanes per instance, or
+    the workgroup schedule's instances per compute unit); the context keeps
+    the fastest for later solves that leave the choice at 0.  Returns
+    (choice, ms)."""
     import torch
     opts = opts or Options()
     dev = torch.device("cuda", ctx.device)

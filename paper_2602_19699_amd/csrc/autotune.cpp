@@ -1,6 +1,8 @@
-// Autotuner for the lane schedule: times every lanes-per-instance width on
-// the caller's own problem and keeps the fastest per problem class in the
-// context, where solves with group_lanes = 0 find it.
+// Autotuner: times every candidate schedule on the caller's own problem (the
+// lanes-per-instance widths of the lane schedule, one or two instances per
+// compute unit of the workgroup schedule) and keeps the fastest per problem
+// class in the context, where solves that leave the choice to the library
+// (group_lanes, or wg_per_cu, 0) find it.
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -46,6 +48,13 @@ extern "C" cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, 
   }
   hipStream_t st = static_cast<hipStream_t>(stream_v);
   HIP_TRY(hipSetDevice(ctx->device));
+  if (cbic_status rc = check_solve_opts(opts); rc != CBIC_OK) return rc;
+  const Launcher* L = find_launcher(sys->kind, sys->n, sys->m, opts->precision, opts->schedule);
+  if (!L) {
+    set_error("no kernel for this system, precision and schedule");
+    return CBIC_E_UNSUPPORTED;
+  }
+  const bool wg = L->schedule == CBIC_SCHED_GROUP;
   const int n = sys->n, m = sys->m;
   // scratch outputs for the trial solves (a set-up call: it may allocate)
   void* buf = nullptr;
@@ -67,9 +76,10 @@ extern "C" cbic_status cbic_autotune(cbic_context* ctx, const cbic_system* sys, 
   int best = 0;
   float bms = 1e30f;
   cbic_status rc = CBIC_OK;
-  const int cand[] = {1, 2, 4, 8, 16};
+  std::vector<int> cand = {1, 2, 4, 8, 16};
+  if (wg) cand = opts->precision == CBIC_FP64 ? std::vector<int>{1} : std::vector<int>{1, 2};
   for (int g : cand) {
-    o.group_lanes = g;
+    (wg ? o.wg_per_cu : o.group_lanes) = g;
     float mn = 1e30f;
     for (int rep = 0; rep < 3 && rc == CBIC_OK; ++rep) {
       if (hipEventRecord(e0, st) != hipSuccess) { rc = CBIC_E_HIP; break; }

@@ -50,6 +50,7 @@ cbic_status check_solve_opts(const cbic_solve_opts* o) {
     set_error("group_lanes must be 0, 1, 2, 4, 8 or 16");
     return CBIC_E_INVALID;
   }
+  if (o->wg_per_cu < 0 || o->wg_per_cu > 2) { set_error("wg_per_cu must be 0, 1 or 2"); return CBIC_E_INVALID; }
   if (o->regularization != CBIC_REG_CLIP && o->regularization != CBIC_REG_LM) {
     set_error("regularization must be CBIC_REG_CLIP or CBIC_REG_LM");
     return CBIC_E_INVALID;
@@ -235,10 +236,10 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
                               stream));
   }
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));
-  int group = opts->group_lanes;
+  int group = requested_group(L, opts);
   if (group <= 0) {
     auto it = ctx->tuned.find(tune_key(sys, B, Tmax, opts));
-    group = it != ctx->tuned.end() ? it->second : default_group(sys->kind, B, opts->precision);
+    group = it != ctx->tuned.end() ? it->second : default_group(L->schedule, B, opts->precision, ctx->device);
   }
   if (opts->max_iter > 0) {
     const int G = opts->iters_per_launch > 0 ? std::min(opts->iters_per_launch, opts->max_iter) : opts->max_iter;
@@ -375,6 +376,7 @@ cbic_status cbic_opts_default(cbic_solve_opts* o) {
   o->lm_factor = 10.0;
   o->lm_mu_max = 1e10;
   o->u_max = INFINITY;
+  o->wg_per_cu = 0;
   return CBIC_OK;
 }
 

@@ -1004,15 +1004,18 @@ __global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, 
   }
 }
 
-template <class R, bool BOX, bool LM>
-// Two workgroups per CU (registers capped for two, some values spill): the
-// per-step chain is latency-bound, and a second resident instance per CU
-// hides more of it than the spills cost (measured: FP32 -26 %, FP64 -7 %).
+template <class R, bool BOX, bool LM, int OCC>
+// OCC: workgroups resident per CU the registers are sized for.  With 1 the
+// kernel keeps its values in registers (one wave per SIMD); with 2 the
+// registers are capped at 256 and some values spill, but the per-step chain is
+// latency-bound and a second resident instance per CU hides more of it than
+// the spills cost once the batch fills every CU (mixed, 1024 instances: -35 %;
+// at most one instance per CU: +10 %; FP64 is slower with 2 at every size).
 // BOX: the variant with the control bound of eq. 1 (sp.umax finite).  LM: the
 // Levenberg-Marquardt variant (sp.reg = 1), in which a failed Cholesky or line search
 // multiplies mu by mu_fac and retries the sweep while mu stays within mu_max;
 // an accepted step divides it (not below mu0); mu carries over between launches.
-__global__ void __launch_bounds__(NT, 2) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
+__global__ void __launch_bounds__(NT, OCC) quad_iterate(const double* __restrict__ prm, LaneState<R> w, int nslots,
                                                     const int32_t* __restrict__ slots, SolveParams sp,
                                                     int iters_this_launch, IterTrace tr,
                                                     R* __restrict__ dblk) {
@@ -1338,28 +1341,42 @@ struct QuadLaunch {
     return hipGetLastError();
   }
 
+  // the bounded and Levenberg-Marquardt variants are kernels of their own, so
+  // that the plain one keeps its register allocation and shared-memory footprint
+  template <int OCC>
+  static void launch_forms(bool box, bool lm, const double* prm, const LaneState<R>& w, int nthreads,
+                           const int32_t* slots, const SolveParams& d, int G, const IterTrace& tr, R* blk,
+                           hipStream_t st) {
+    if (box && lm)
+      hipLaunchKernelGGL((quad_iterate<R, true, true, OCC>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads,
+                         slots, d, G, tr, blk);
+    else if (box)
+      hipLaunchKernelGGL((quad_iterate<R, true, false, OCC>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads,
+                         slots, d, G, tr, blk);
+    else if (lm)
+      hipLaunchKernelGGL((quad_iterate<R, false, true, OCC>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads,
+                         slots, d, G, tr, blk);
+    else
+      hipLaunchKernelGGL((quad_iterate<R, false, false, OCC>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads,
+                         slots, d, G, tr, blk);
+  }
+
   static hipError_t iterate(const double* prm, void* base, int Bcap, int Tcap, int nthreads,
-                            const int32_t* slots, const SolveParamsH& sp, int G, int, const IterTrace& tr,
+                            const int32_t* slots, const SolveParamsH& sp, int G, int group, const IterTrace& tr,
                             hipStream_t st) {
     if (nthreads <= 0) return hipSuccess;
     auto w = lane_state<R>(base, N, M, Bcap, Tcap, 2);
-    // the bounded variant is a kernel of its own, so that the unbounded one
-    // keeps its register allocation and shared-memory footprint
     const SolveParams d = to_dev(sp);
     R* blk = blocks(base, Bcap, Tcap);
     const bool box = __builtin_isfinite(sp.umax), lm = sp.reg == 1;
-    if (box && lm)
-      hipLaunchKernelGGL((quad_iterate<R, true, true>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots, d,
-                         G, tr, blk);
-    else if (box)
-      hipLaunchKernelGGL((quad_iterate<R, true, false>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
-                         d, G, tr, blk);
-    else if (lm)
-      hipLaunchKernelGGL((quad_iterate<R, false, true>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
-                         d, G, tr, blk);
-    else
-      hipLaunchKernelGGL((quad_iterate<R, false, false>), dim3(nthreads), dim3(NT), 0, st, prm, w, nthreads, slots,
-                         d, G, tr, blk);
+    // group: workgroups per CU (2 only in FP32; FP64 always runs one per CU)
+    if constexpr (sizeof(R) == 4) {
+      if (group == 2) {
+        launch_forms<2>(box, lm, prm, w, nthreads, slots, d, G, tr, blk, st);
+        return hipGetLastError();
+      }
+    }
+    launch_forms<1>(box, lm, prm, w, nthreads, slots, d, G, tr, blk, st);
     return hipGetLastError();
   }
 

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 
 namespace cbic {
 
@@ -62,12 +63,25 @@ const Launcher* find_launcher(int kind, int n, int m, int precision, int schedul
   return L;
 }
 
-int default_group(int kind, int B, int precision) {
-  (void)kind;
-  (void)precision;
+int cu_count(int device) {
+  static std::atomic<int> cache[64];
+  if (device < 0 || device >= 64) return 256;
+  int v = cache[device].load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 256;
+  cache[device].store(v, std::memory_order_relaxed);
+  return v;
+}
+
+int default_group(int schedule, int B, int precision, int device) {
+  if (schedule == CBIC_SCHED_GROUP) return (precision == CBIC_FP64 || B <= cu_count(device)) ? 1 : 2;
   int g = 1;
   while (g < 16 && long(B) * g * 2 <= 65536) g *= 2;
   return g;
+}
+
+int requested_group(const Launcher* L, const cbic_solve_opts* o) {
+  return L->schedule == CBIC_SCHED_GROUP ? o->wg_per_cu : o->group_lanes;
 }
 
 // ------------------------------------------------------------------ host Jacobi (LQ Hessians)

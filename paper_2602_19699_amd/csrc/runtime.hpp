@@ -95,9 +95,16 @@ cbic_status check_solve_opts(const cbic_solve_opts* o);
 // variant clips nothing: eps is then negative)
 SolveParamsH solve_params(const cbic_solve_opts* o);
 
-// lanes per instance of the lane schedule when the caller leaves it to the
-// library: enough groups to give every SIMD of the chip a wave or two
-int default_group(int kind, int B, int precision);
+// the schedule choice when the caller leaves it to the library: lanes per
+// instance of the lane schedule (enough groups to give every SIMD of the chip
+// a wave or two), instances per compute unit of the workgroup schedule (one
+// while the batch fits the device's compute units one instance each, two
+// above; always one in FP64)
+int default_group(int schedule, int B, int precision, int device);
+// the caller's own choice for the launcher's schedule (0: none)
+int requested_group(const Launcher* L, const cbic_solve_opts* o);
+// compute units of a device (cached)
+int cu_count(int device);
 
 // key of the autotuning table for a solve (system kind and size, precision,
 // stop rule, batch rounded up to a power of two, horizon capacity)

@@ -336,7 +336,8 @@ bool launch_iterations(cbic_server* srv, Pool* p) {
   const SolveParamsH sp = solve_params(&p->opts);
   ++srv->launches;
   srv->launched_slots += uint64_t(na);
-  const int group = p->opts.group_lanes > 0 ? p->opts.group_lanes : default_group(p->sys->kind, na, p->precision);
+  const int req = requested_group(p->L, &p->opts);
+  const int group = req > 0 ? req : default_group(p->L->schedule, na, p->precision, srv->ctx->device);
   SRV_TRY(p->L->iterate(p->sys->d_prm, p->ws, p->Bcap, p->Tcap, na, p->d_list, sp,
                         std::max(1, srv->opts.iters_per_launch), group, IterTrace{nullptr, nullptr}, p->stream));
   const uint32_t* st = reinterpret_cast<const uint32_t*>(static_cast<char*>(p->ws) + p->lay.status);

@@ -60,6 +60,11 @@ def test_opts_default_and_host_side_validation(lib):
     with pytest.raises(cbic.CbicError) as e:
         s.workspace_size(4, 100, cbic.Options(ls_beta=1.5))
     assert e.value.code == cbic.E_INVALID
+    for bad_occ in (-1, 3):  # instances per compute unit of the workgroup schedule: 0, 1 or 2
+        with pytest.raises(cbic.CbicError) as e:
+            s.workspace_size(4, 100, cbic.Options(wg_per_cu=bad_occ))
+        assert e.value.code == cbic.E_INVALID and b"wg_per_cu" in lib.cbic_last_error()
+    s.workspace_size(4, 100, cbic.Options(wg_per_cu=2))
     bad = cbic.Options().c()
     bad.struct_size = 8
     v = C.c_size_t()

@@ -150,3 +150,45 @@ def test_quad_chunk_boundaries(ctx):
         assert np.all(g["X"][b, Tb + 1:] == 0) and np.all(g["U"][b, Tb:] == 0)
     gm = gpu_solve(ctx, QUAD, p, x0, 33, T=T, precision=1, stop_mode=1, rtol=1e-7)
     assert rel(gm["J"], r.J).max() <= 1e-4
+
+
+def _same(a, b):
+    return all(np.array_equal(a[k], b[k], equal_nan=True) for k in ("X", "U", "J", "iters", "status", "Vbar", "Vx"))
+
+
+def test_quad_instances_per_cu(ctx):
+    # one or two workgroups per compute unit are register allocations of the
+    # same kernel: every form gives the same bits under either, FP64 runs one
+    # per unit whatever is asked, and the autotuner's choice (used by solves
+    # that leave it at 0) changes nothing either
+    import torch
+    from paper_2602_19699_amd import cbic
+    p = I.quad_params(0)
+    x0 = I.quad_x0(8, p, seed=7)
+    T = np.array([40, 12, 33, 40, 5, 27, 40, 18], np.int32)
+    forms = {"plain": dict(stop_mode=1, rtol=1e-7), "bounded": dict(u_max=5.0),
+             "lm": dict(regularization=1), "bounded_lm": dict(u_max=5.0, regularization=1)}
+    for name, o in forms.items():
+        a = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=12, precision=1, wg_per_cu=1, **o)
+        b = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=12, precision=1, wg_per_cu=2, **o)
+        c = gpu_solve(ctx, QUAD, p, x0, 40, T=T, max_iter=12, precision=1, wg_per_cu=2, iters_per_launch=5, **o)
+        assert _same(a, b) and _same(a, c), name
+        assert np.all(np.isfinite(a["J"])), name
+    a = gpu_solve(ctx, QUAD, p, x0[:3], 20, max_iter=6, wg_per_cu=1)
+    b = gpu_solve(ctx, QUAD, p, x0[:3], 20, max_iter=6, wg_per_cu=2)
+    assert _same(a, b)
+    dev = torch.device("cuda", ctx.device)
+    sysm = cbic.System(ctx, QUAD, p)
+    try:
+        o = cbic.Options(precision=1, stop_mode=1, rtol=1e-4, max_iter=12)
+        choice, ms = cbic.autotune(ctx, sysm, torch.as_tensor(x0, device=dev), 40,
+                                   T=torch.as_tensor(T, device=dev), opts=o)
+        assert choice in (1, 2) and ms > 0
+        choice64, _ = cbic.autotune(ctx, sysm, torch.as_tensor(x0, device=dev), 40,
+                                    T=torch.as_tensor(T, device=dev), opts=cbic.Options(max_iter=4))
+        assert choice64 == 1
+    finally:
+        sysm.close()
+    t = gpu_solve(ctx, QUAD, p, x0, 40, T=T, precision=1, stop_mode=1, rtol=1e-4, max_iter=12)
+    u = gpu_solve(ctx, QUAD, p, x0, 40, T=T, precision=1, stop_mode=1, rtol=1e-4, max_iter=12, wg_per_cu=3 - choice)
+    assert _same(t, u)
