@@ -60,20 +60,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "97ab3b38fd9e107cfbb49183a730e1bb128d34ef86ca8d4cb209ce916d897b80",
-        "fetch_kib": 260770.2, "write_kib": 474403.5, "sq_active_inst_valu": 200872578.2,
+        "sha256": "90d95378263601ae1784ee48f9d0b6a4b9078205820c47a5747872010a027fc1",
+        "fetch_kib": 260822.9, "write_kib": 474380.7, "sq_active_inst_valu": 200746701.7,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "d92ad4405c200a41c4d297671b2d379fe7e9d5add1a6025f7f077ad976451734",
-        "fetch_kib": 1490684.5, "write_kib": 12258871.7, "sq_active_inst_valu": 5084758971.2,
+        "sha256": "8324c573cc0009b980b82f92247da7e2afb2571963f66642d550b1b13ae99a0e",
+        "fetch_kib": 1490667.5, "write_kib": 12259110.6, "sq_active_inst_valu": 5090499293.2,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "4eb288ec34303b1b22dc93e06a7e09f0ec1bab8ee2a1724f6b02525f88d23f3d",
-        "fetch_kib": 1959831.3, "write_kib": 2119896.8, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "d711c7ac2a6f4dbd0b779c16dedda3992c5747d9af3393541a2ba771a2c5e951",
+        "fetch_kib": 1933401.4, "write_kib": 2120316.7, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
