@@ -178,9 +178,11 @@ typedef struct {
 #define CBIC_FLAG_INPUT_ORDER 4u /* iterate the instances in the horizon sort's order.  By
                                default the iteration launches take them longest horizon
                                first and, within a horizon, highest initial cost J^0 first
-                               (quarter-octave levels), so that instances of similar
-                               expected work share a wave; a scheduling choice only: no
-                               result depends on it                                          */
+                               (quarter-octave levels; in a batch of one horizon, within a
+                               level, highest non-convex share of J^0 first where the system
+                               has one: the point mass's obstacle terms, half-octave
+                               levels), so that instances of similar expected work share a
+                               wave; a scheduling choice only: no result depends on it      */
 
 /* Output buffers: caller-owned DEVICE pointers, AoS per instance, padded to
  * T_max; entries past an instance's horizon are written as zero.

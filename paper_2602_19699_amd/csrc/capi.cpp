@@ -225,14 +225,16 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
   HIP_TRY(L->init(prm, base, B, Tmax, B, nullptr, Tmax, d_T, perm, d_x0, d_U0, opts->max_iter,
                   out->cost_trace, sp.umax, stream));
   // the iteration launches take the slots in the order of expected work
-  // (longest horizon, then highest initial cost first) unless the caller
-  // asks for the horizon sort's order; results are the same either way
+  // (longest horizon, then highest initial cost first, then highest
+  // non-convex share of it) unless the caller asks for the horizon sort's
+  // order; results are the same either way
   if ((opts->flags & CBIC_FLAG_INPUT_ORDER) || opts->max_iter <= 0 || !cost_order_supported(d_T != nullptr, Tmax)) {
     order = nullptr;
   } else {
     const LaneLayout lay = lane_layout(L->N, L->M, L->elem, B, Tmax, L->nbuf);
     HIP_TRY(launch_cost_order(reinterpret_cast<const int32_t*>(base + lay.T),
-                              reinterpret_cast<const double*>(base + lay.J), B, Tmax, d_T != nullptr, order,
+                              reinterpret_cast<const double*>(base + lay.J),
+                              reinterpret_cast<const float*>(base + lay.okey), B, Tmax, d_T != nullptr, order,
                               stream));
   }
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));

@@ -110,37 +110,52 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 8192;  // shared-memory histogram (32 KB)
 constexpr int kOrderKeys = 16384;    // slots whose keys stay in shared memory (64 KB)
+constexpr int kOrderOLevels = 32;    // levels of the second key (single-horizon batches)
 
 // levels of J^0 per horizon: quarter octaves below the largest J^0 for a
-// batch of one horizon, whole octaves otherwise, fewer if the horizons need
-// more buckets than the histogram holds
+// batch of one horizon (each split again by the second key), whole octaves
+// otherwise, fewer if the horizons need more buckets than the histogram holds
 __host__ __device__ inline int order_levels(bool ragged, int Tmax) {
   if (!ragged) return 64;
   const int per = kOrderBuckets / (Tmax + 1);
   return per < 16 ? per : 16;
 }
 
-// a slot's key: its horizon (clamped into [1, Tmax]) and the quarter-octave
-// (or octave) index of float(J^0) from the exponent and leading mantissa
-// bits; 0 for J^0 <= 0 or NaN (float(J^0) beyond the float range is infinity
-// and takes the top index)
-__device__ __forceinline__ uint32_t order_key(int t, double J, int Tmax, int sh) {
-  t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
-  const uint32_t a = J > 0.0 ? (__float_as_uint(float(J)) >> sh) + 1u : 0u;
-  return (uint32_t(t) << 11) | a;  // a < 2^(32 - sh) + 1 <= 2^11
+// index of a positive float value in levels of 2^-(23 - sh) octaves, from its
+// exponent and leading mantissa bits; 0 for values <= 0 or NaN (infinity
+// takes the top index)
+__device__ __forceinline__ uint32_t order_index(float v, int sh) {
+  return v > 0.f ? (__float_as_uint(v) >> sh) + 1u : 0u;
 }
 
-// bucket of a key: horizon (longest first), then the level below the largest
-// index `ref` (highest J^0 first); the last level takes J^0 <= 0
-__device__ __forceinline__ int order_bucket(uint32_t key, int Tmax, bool ragged, int nlev, uint32_t ref) {
-  const uint32_t a = key & 2047u;
-  int lvl = nlev - 1;
-  if (a) {
-    const int d = int(ref) - int(a);
-    lvl = d < 0 ? 0 : (d > nlev - 1 ? nlev - 1 : d);
+// a slot's key.  Ragged: its horizon (clamped into [1, Tmax]) above the
+// octave index of float(J^0).  One horizon: the quarter-octave index of
+// float(J^0) above the half-octave index of the second key o (the warm
+// start's non-convex cost share).  Both indexes stay below 2^11.
+template <bool RAGGED>
+__device__ __forceinline__ uint32_t order_key(int t, double J, float o, int Tmax) {
+  if constexpr (RAGGED) {
+    t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
+    return (uint32_t(t) << 11) | order_index(float(J), 23);
+  } else {
+    return (order_index(float(J), 21) << 11) | order_index(o, 22);
   }
-  if (!ragged) return lvl;
-  return (Tmax - int(key >> 11)) * nlev + lvl;
+}
+
+__device__ __forceinline__ int order_level(uint32_t a, uint32_t ref, int nlev) {
+  if (!a) return nlev - 1;
+  const int d = int(ref) - int(a);
+  return d < 0 ? 0 : (d > nlev - 1 ? nlev - 1 : d);
+}
+
+// bucket of a key.  Ragged: horizon (longest first), then the J^0 level below
+// the largest index refJ (highest first).  One horizon: the J^0 level below
+// refJ, then the second key's level below its largest index refO (highest
+// first).  The last level of either takes values <= 0.
+template <bool RAGGED>
+__device__ __forceinline__ int order_bucket(uint32_t key, int Tmax, int nlev, uint32_t refJ, uint32_t refO) {
+  if constexpr (RAGGED) return (Tmax - int(key >> 11)) * nlev + order_level(key & 2047u, refJ, nlev);
+  else return order_level(key >> 11, refJ, nlev) * kOrderOLevels + order_level(key & 2047u, refO, kOrderOLevels);
 }
 
 // horizons must fit the key's 20 bits, and ragged ones a level each in the histogram
@@ -150,42 +165,55 @@ bool cost_order_supported(bool ragged, int Tmax) {
 
 template <bool RAGGED, bool CACHED>
 __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __restrict__ T,
-                                                               const double* __restrict__ J, int B, int Tmax,
+                                                               const double* __restrict__ J,
+                                                               const float* __restrict__ O, int B, int Tmax,
                                                                int32_t* __restrict__ order) {
   __shared__ int32_t hist[kOrderBuckets];
   __shared__ uint32_t keys[CACHED ? kOrderKeys : 1];
-  __shared__ uint32_t wmax[kOrderThreads / 64];
+  __shared__ uint32_t wmax[2][kOrderThreads / 64];
   __shared__ int32_t part[kOrderThreads / 64];
   const int t = threadIdx.x;
-  constexpr int sh = RAGGED ? 23 : 21;
   const int nlev = order_levels(RAGGED, Tmax);
-  const int nb = RAGGED ? (Tmax + 1) * nlev : nlev;
-  auto key_at = [&](int s) -> uint32_t { return order_key(RAGGED ? T[s] : Tmax, J[s], Tmax, sh); };
+  const int nb = RAGGED ? (Tmax + 1) * nlev : nlev * kOrderOLevels;
+  auto key_at = [&](int s) -> uint32_t {
+    return order_key<RAGGED>(RAGGED ? T[s] : Tmax, J[s], RAGGED ? 0.f : O[s], Tmax);
+  };
   auto key_of = [&](int s) -> uint32_t {
     if constexpr (CACHED) return keys[s];
     else return key_at(s);
   };
   for (int i = t; i < nb; i += kOrderThreads) hist[i] = 0;
-  // keys (kept in shared memory when they fit) and the largest J^0 index
-  uint32_t m = 0;
+  // keys (kept in shared memory when they fit) and the largest indexes: of
+  // J^0 (mj) and, for one horizon, of the second key (mo)
+  uint32_t mj = 0, mo = 0;
 #pragma unroll 8
   for (int s = t; s < B; s += kOrderThreads) {
     const uint32_t k = key_at(s);
     if constexpr (CACHED) keys[s] = k;
-    m = (k & 2047u) > m ? (k & 2047u) : m;
+    const uint32_t a = RAGGED ? (k & 2047u) : (k >> 11), c = RAGGED ? 0u : (k & 2047u);
+    mj = a > mj ? a : mj;
+    mo = c > mo ? c : mo;
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
-    const uint32_t v = uint32_t(__shfl_xor(int(m), o, 64));
-    m = v > m ? v : m;
+    const uint32_t v = uint32_t(__shfl_xor(int(mj), o, 64)), u = uint32_t(__shfl_xor(int(mo), o, 64));
+    mj = v > mj ? v : mj;
+    mo = u > mo ? u : mo;
   }
-  if ((t & 63) == 0) wmax[t >> 6] = m;
+  if ((t & 63) == 0) {
+    wmax[0][t >> 6] = mj;
+    wmax[1][t >> 6] = mo;
+  }
   __syncthreads();
-  uint32_t ref = 0;
+  uint32_t refJ = 0, refO = 0;
 #pragma unroll
-  for (int w = 0; w < kOrderThreads / 64; ++w) ref = wmax[w] > ref ? wmax[w] : ref;
+  for (int w = 0; w < kOrderThreads / 64; ++w) {
+    refJ = wmax[0][w] > refJ ? wmax[0][w] : refJ;
+    refO = wmax[1][w] > refO ? wmax[1][w] : refO;
+  }
 #pragma unroll 4
-  for (int s = t; s < B; s += kOrderThreads) atomicAdd(&hist[order_bucket(key_of(s), Tmax, RAGGED, nlev, ref)], 1);
+  for (int s = t; s < B; s += kOrderThreads)
+    atomicAdd(&hist[order_bucket<RAGGED>(key_of(s), Tmax, nlev, refJ, refO)], 1);
   __syncthreads();
   // exclusive scan of hist[0..nb): a serial run per thread, then across threads
   const int per = (nb + kOrderThreads - 1) / kOrderThreads;
@@ -212,19 +240,19 @@ __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __r
   __syncthreads();
 #pragma unroll 4
   for (int s = t; s < B; s += kOrderThreads)
-    order[atomicAdd(&hist[order_bucket(key_of(s), Tmax, RAGGED, nlev, ref)], 1)] = s;
+    order[atomicAdd(&hist[order_bucket<RAGGED>(key_of(s), Tmax, nlev, refJ, refO)], 1)] = s;
 }
 
-hipError_t launch_cost_order(const int32_t* T, const double* J, int B, int Tmax, bool ragged, int32_t* order,
-                             hipStream_t st) {
+hipError_t launch_cost_order(const int32_t* T, const double* J, const float* O, int B, int Tmax, bool ragged,
+                             int32_t* order, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   if (!cost_order_supported(ragged, Tmax)) return hipErrorInvalidValue;
   const dim3 g(1), b(kOrderThreads);
   const bool cached = B <= kOrderKeys;
-  if (ragged && cached) hipLaunchKernelGGL((k_cost_order<true, true>), g, b, 0, st, T, J, B, Tmax, order);
-  else if (ragged) hipLaunchKernelGGL((k_cost_order<true, false>), g, b, 0, st, T, J, B, Tmax, order);
-  else if (cached) hipLaunchKernelGGL((k_cost_order<false, true>), g, b, 0, st, T, J, B, Tmax, order);
-  else hipLaunchKernelGGL((k_cost_order<false, false>), g, b, 0, st, T, J, B, Tmax, order);
+  if (ragged && cached) hipLaunchKernelGGL((k_cost_order<true, true>), g, b, 0, st, T, J, O, B, Tmax, order);
+  else if (ragged) hipLaunchKernelGGL((k_cost_order<true, false>), g, b, 0, st, T, J, O, B, Tmax, order);
+  else if (cached) hipLaunchKernelGGL((k_cost_order<false, true>), g, b, 0, st, T, J, O, B, Tmax, order);
+  else hipLaunchKernelGGL((k_cost_order<false, false>), g, b, 0, st, T, J, O, B, Tmax, order);
   return hipGetLastError();
 }
 

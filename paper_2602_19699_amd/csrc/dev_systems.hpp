@@ -22,6 +22,9 @@ struct PointMass {
   static constexpr int N = 4, M = 2;
   static constexpr int NPRM = 16;
   static constexpr bool kNonNegCost = true;
+  // the warm start records the obstacle bumps' share of its cost, which
+  // predicts an instance's iteration count better than the total cost
+  static constexpr bool kOrderCost = true;
   // a rollout step costs little next to the stores of GL trial trajectories:
   // the line search writes only alpha = 1 and re-rolls another accepted step
   static constexpr bool kOwnTrialBuffers = false;
@@ -67,6 +70,23 @@ struct PointMass {
         const R dx = x[0] - R(p[7 + 3 * i]), dy = x[1] - R(p[8 + 3 * i]);
         l += R(p[4]) * bump(dx * dx + dy * dy, i);
       }
+      return l;
+    }
+
+    // l as cost() computes it (the same operations in the same order), and in
+    // nc the sum of the three unweighted bumps: the non-convex part of l
+    CBIC_HD __forceinline__ R cost(const R* x, const R* u, R& nc) const {
+      const R ex = x[0] - R(p[5]), ey = x[1] - R(p[6]);
+      R l = R(p[1]) * (u[0] * u[0] + u[1] * u[1]) + R(p[2]) * (ex * ex + ey * ey);
+      R b = R(0);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const R dx = x[0] - R(p[7 + 3 * i]), dy = x[1] - R(p[8 + 3 * i]);
+        const R e = bump(dx * dx + dy * dy, i);
+        l += R(p[4]) * e;
+        b += e;
+      }
+      nc = b;
       return l;
     }
 
@@ -192,6 +212,7 @@ struct Arm3 {
   static constexpr int N = 6, M = 3;
   static constexpr int NPRM = 19;
   static constexpr bool kNonNegCost = true;
+  static constexpr bool kOrderCost = false;
   // a rollout step is expensive: every trial lane writes its own trajectory
   // so that an accepted step needs no second rollout
   static constexpr bool kOwnTrialBuffers = true;
@@ -542,6 +563,7 @@ struct LinQuad {
                        OXR = OQT + N * N, OQC = OXR + N, ORC = OQC + N * N, OQTC = ORC + M * M,
                        NPRM = OQTC + N * N;
   static constexpr bool kNonNegCost = false;
+  static constexpr bool kOrderCost = false;
   static constexpr bool kOwnTrialBuffers = false;
   static constexpr bool kAxisPairs = false;
   static constexpr bool kConstJac = true;

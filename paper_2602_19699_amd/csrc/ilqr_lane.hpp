@@ -37,6 +37,8 @@ struct LaneState {
   int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
   int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
   double* mu;        // Levenberg-Marquardt parameter (that variant only)
+  float* okey;       // the warm start's non-convex cost share (0 where the system has
+                     // none): a key of the iteration order, never of a result
   // trajectories and gains, step-major
   R* X;   // [nbuf][Bcap][xs]: x_k at k N; the iterate (buffer cur) and trial trajectories
   R* U;   // [nbuf][Bcap][us]: u_k at k M
@@ -1251,6 +1253,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   // so that the rollout does not wait for the exchange
   double cprev[GL];
   int cnprev = 0;
+  float oc = 0.f;  // this lane's steps' share of the iteration-order key
   for (int kc = 0; kc < T; kc += GL) {
     const int kr = kc + r;
     const int cn = T - kc < GL ? T - kc : GL;
@@ -1276,7 +1279,13 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
     }
     double c = 0.0;
     if (r < cn) {
-      c = double(mdl.cost(xr, ur));
+      if constexpr (Sys::kOrderCost) {
+        R nc;
+        c = double(mdl.cost(xr, ur, nc));
+        oc += float(nc);
+      } else {
+        c = double(mdl.cost(xr, ur));
+      }
       LN::st(LN::up(w, 0, kr, s), ur);
       LN::st(LN::xp(w, 0, kr + 1, s), xr1);
     }
@@ -1290,6 +1299,9 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
 #pragma unroll
   for (int q = 0; q < GL; ++q)
     if (q < cnprev) J += cprev[q];
+  // the group's sum of the order key (any order of additions: it only orders)
+#pragma unroll
+  for (int o = 1; o < GL; o <<= 1) oc += __shfl_xor(oc, o, 64);
   if (r != 0) return;
   J += double(mdl.term(x));
   uint32_t st = isfinite(J) ? 0u : ST_NONFINITE;
@@ -1301,6 +1313,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   w.T[s] = T;
   w.inst[s] = slots ? s : b;  // outputs of slot-addressed solves are indexed by slot
   w.J[s] = J;
+  w.okey[s] = oc;
   w.iters[s] = 0;
   w.status[s] = st;
   w.cur[s] = 0;

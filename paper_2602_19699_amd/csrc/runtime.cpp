@@ -41,6 +41,7 @@ LaneLayout lane_layout(int N, int M, int elem, int Bcap, int Tcap, int nbuf) {
   L.cur = o; o = align256(o + 4 * B);
   L.work = o; o = align256(o + 16 * B);
   L.mu = o; o = align256(o + 8 * B);
+  L.okey = o; o = align256(o + 4 * B);
   // slot-major, each slot's block padded to whole cache lines
   L.X = o; o = align256(o + size_t(elem) * nbuf * B * lane_stride((Tcap + 1) * N, elem));
   L.U = o; o = align256(o + size_t(elem) * nbuf * B * lane_stride(Tcap * M, elem));

@@ -27,7 +27,7 @@ inline int lane_stride(int count, int elem) { return int((size_t(count) * elem +
 // Byte offsets of the per-slot state, trajectories and gains inside one
 // workspace allocation (lane schedule).  All sub-arrays are 256-byte aligned.
 struct LaneLayout {
-  size_t T, inst, J, iters, status, cur, work, mu;
+  size_t T, inst, J, iters, status, cur, work, mu, okey;
   size_t X, U, K, kf;
   size_t total;
 };
@@ -113,14 +113,15 @@ std::string tune_key(const cbic_system* sys, int B, int Tmax, const cbic_solve_o
 // horizon sort (longest first) of B instances -> perm (device)
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st);
 
-// iteration order of B initialised slots (horizon T[s], initial cost J[s];
-// `ragged`: the slots hold several horizons, longest first): within each
-// horizon, highest J^0 first in coarse levels -> order (device, B entries).
-// One workgroup; every horizon up to Tmax must have a level in its
-// shared-memory histogram (cost_order_supported).
+// iteration order of B initialised slots (horizon T[s], initial cost J[s],
+// the warm start's non-convex cost share O[s]; `ragged`: the slots hold
+// several horizons, longest first): within each horizon, highest J^0 first in
+// coarse levels, and for a batch of one horizon highest O first within each
+// level -> order (device, B entries).  One workgroup; every horizon up to
+// Tmax must have a level in its shared-memory histogram (cost_order_supported).
 bool cost_order_supported(bool ragged, int Tmax);
-hipError_t launch_cost_order(const int32_t* T, const double* J, int B, int Tmax, bool ragged, int32_t* order,
-                             hipStream_t st);
+hipError_t launch_cost_order(const int32_t* T, const double* J, const float* O, int B, int Tmax, bool ragged,
+                             int32_t* order, hipStream_t st);
 
 // p[0..n) = v on the device, by a kernel
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
