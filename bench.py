@@ -60,20 +60,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "90d95378263601ae1784ee48f9d0b6a4b9078205820c47a5747872010a027fc1",
-        "fetch_kib": 260822.9, "write_kib": 474380.7, "sq_active_inst_valu": 200746701.7,
+        "sha256": "79ffa320a3cb5db56259631390dc74af36b0e7b21648bae602cdacf0f62c1133",
+        "fetch_kib": 264038.8, "write_kib": 475279.5, "sq_active_inst_valu": 173766939.4,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "8324c573cc0009b980b82f92247da7e2afb2571963f66642d550b1b13ae99a0e",
-        "fetch_kib": 1490667.5, "write_kib": 12259110.6, "sq_active_inst_valu": 5090499293.2,
+        "sha256": "c6662cca1ee496a4909c72203661643356c0fbfe97a4c2b6d968076d37ff7314",
+        "fetch_kib": 1490782.6, "write_kib": 12258714.0, "sq_active_inst_valu": 5089295325.4,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "d711c7ac2a6f4dbd0b779c16dedda3992c5747d9af3393541a2ba771a2c5e951",
-        "fetch_kib": 1933401.4, "write_kib": 2120316.7, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "facb496f77c3445961bd20be15eb4489568dafff6a84200cbe4af8e89bb5aae9",
+        "fetch_kib": 1935109.7, "write_kib": 2119620.5, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
