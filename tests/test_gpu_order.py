@@ -54,6 +54,17 @@ def test_order_point_mass_forms(ctx):
     _same(ctx, kind, p, x, T, group_lanes=2, max_iter=10)
 
 
+def test_order_beyond_shared_keys(ctx):
+    # more slots than the order kernel keeps keys for in shared memory (16384):
+    # the keys are recomputed from the workspace in each pass, for a batch of
+    # one horizon (J^0 levels split by the obstacle share) and a ragged one
+    kind, p, _, T, _ = I.workload("pm16k")
+    B = 16384 + 777
+    x = I.point_mass_x0(B, seed=2024)
+    _same(ctx, kind, p, x, T, precision=1, stop_mode=1, rtol=1e-4)
+    _same(ctx, kind, p, x, T, T=I.horizons(B, 1, 100, seed=5), precision=1, stop_mode=1, rtol=1e-4, max_iter=8)
+
+
 def test_order_arm_ragged(ctx):
     B = 130
     p = I.planar3_params(0)
