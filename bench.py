@@ -63,20 +63,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "79ffa320a3cb5db56259631390dc74af36b0e7b21648bae602cdacf0f62c1133",
-        "fetch_kib": 264038.8, "write_kib": 475279.5, "sq_active_inst_valu": 173766939.4,
+        "sha256": "50bfa093c7b17c62df11ea6ac2c9a5e22f18e1df5a9a9c8cdcc3f40dfb72127b",
+        "fetch_kib": 265006.2, "write_kib": 487317.6, "sq_active_inst_valu": 174680061.5,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "c6662cca1ee496a4909c72203661643356c0fbfe97a4c2b6d968076d37ff7314",
-        "fetch_kib": 1490782.6, "write_kib": 12258714.0, "sq_active_inst_valu": 5089295325.4,
+        "sha256": "5b67af0ded6590e2eaf75646ebaf9c97d3c2a49fa7699041f3bd897591a644c9",
+        "fetch_kib": 1491136.0, "write_kib": 12268131.9, "sq_active_inst_valu": 5096002497.1,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "facb496f77c3445961bd20be15eb4489568dafff6a84200cbe4af8e89bb5aae9",
-        "fetch_kib": 1935109.7, "write_kib": 2119620.5, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "b0fb691ee75de43bf7a11848cb23bee29d3291cee94e7b88f80fe58969e720af",
+        "fetch_kib": 1936348.1, "write_kib": 2120873.4, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }

@@ -232,9 +232,7 @@ cbic_status enqueue_solve(cbic_context* ctx, const cbic_system* sys, const doubl
     order = nullptr;
   } else {
     const LaneLayout lay = lane_layout(L->N, L->M, L->elem, B, Tmax, L->nbuf);
-    HIP_TRY(launch_cost_order(reinterpret_cast<const int32_t*>(base + lay.T),
-                              reinterpret_cast<const double*>(base + lay.J),
-                              reinterpret_cast<const float*>(base + lay.okey), B, Tmax, d_T != nullptr, order,
+    HIP_TRY(launch_cost_order(reinterpret_cast<const uint32_t*>(base + lay.okey), B, Tmax, d_T != nullptr, order,
                               stream));
   }
   if (timing) HIP_TRY(hipEventRecord(ctx->phase_ev[1], stream));

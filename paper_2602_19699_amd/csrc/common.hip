@@ -2,6 +2,7 @@
 // horizon into the same wavefront (longest first), so that lockstep waves of
 // a ragged batch waste few steps and the dispatcher hands out the longest
 // work first.
+#include "dev_common.hpp"
 #include "runtime.hpp"
 
 namespace cbic {
@@ -96,17 +97,20 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st) {
 
 // ---------------------------------------------------------------- iteration order
 // A scheduling heuristic, not part of the method: an instance whose initial
-// cost J^0 is higher tends to need more iterations, and a wave (or a
-// workgroup) lasts as long as its slowest instance.  The iteration launches
-// take the slots grouped by horizon (longest first, the order the horizon
-// sort already gave the slots) and, within a horizon, by J^0 (highest first)
-// in coarse levels below the batch's largest J^0, so that instances of
-// similar expected work share waves.  No result depends on the order: every
-// instance's arithmetic is its own.
+// cost J^0 is higher tends to need more iterations, more so the larger the
+// non-convex share of J^0 (the part the clip of eq. 7 replaces by a convex
+// model), and a wave (or a workgroup) lasts as long as its slowest instance.
+// The iteration launches take the slots grouped by horizon (longest first,
+// the order the horizon sort already gave the slots) and, within a horizon,
+// by J^0 (highest first) in coarse levels below the batch's largest J^0; in a
+// batch of one horizon each level is split by the non-convex share (highest
+// first), so that instances of similar expected work share waves.  No result
+// depends on the order: every instance's arithmetic is its own.
 //
-// One workgroup does it all in shared memory: the largest J^0, a histogram of
-// the (horizon, level) buckets, its scan and the scatter (shared-memory
-// atomics; the order within a bucket is arbitrary).
+// The warm start writes each slot's key (order_key); one workgroup does the
+// rest in shared memory: the largest indexes, a histogram of the buckets, its
+// scan and the scatter (shared-memory atomics; the order within a bucket is
+// arbitrary).
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBuckets = 8192;  // shared-memory histogram (32 KB)
 constexpr int kOrderKeys = 16384;    // slots whose keys stay in shared memory (64 KB)
@@ -119,27 +123,6 @@ __host__ __device__ inline int order_levels(bool ragged, int Tmax) {
   if (!ragged) return 64;
   const int per = kOrderBuckets / (Tmax + 1);
   return per < 16 ? per : 16;
-}
-
-// index of a positive float value in levels of 2^-(23 - sh) octaves, from its
-// exponent and leading mantissa bits; 0 for values <= 0 or NaN (infinity
-// takes the top index)
-__device__ __forceinline__ uint32_t order_index(float v, int sh) {
-  return v > 0.f ? (__float_as_uint(v) >> sh) + 1u : 0u;
-}
-
-// a slot's key.  Ragged: its horizon (clamped into [1, Tmax]) above the
-// octave index of float(J^0).  One horizon: the quarter-octave index of
-// float(J^0) above the half-octave index of the second key o (the warm
-// start's non-convex cost share).  Both indexes stay below 2^11.
-template <bool RAGGED>
-__device__ __forceinline__ uint32_t order_key(int t, double J, float o, int Tmax) {
-  if constexpr (RAGGED) {
-    t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
-    return (uint32_t(t) << 11) | order_index(float(J), 23);
-  } else {
-    return (order_index(float(J), 21) << 11) | order_index(o, 22);
-  }
 }
 
 __device__ __forceinline__ int order_level(uint32_t a, uint32_t ref, int nlev) {
@@ -164,9 +147,7 @@ bool cost_order_supported(bool ragged, int Tmax) {
 }
 
 template <bool RAGGED, bool CACHED>
-__global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __restrict__ T,
-                                                               const double* __restrict__ J,
-                                                               const float* __restrict__ O, int B, int Tmax,
+__global__ void __launch_bounds__(kOrderThreads) k_cost_order(const uint32_t* __restrict__ Kin, int B, int Tmax,
                                                                int32_t* __restrict__ order) {
   __shared__ int32_t hist[kOrderBuckets];
   __shared__ uint32_t keys[CACHED ? kOrderKeys : 1];
@@ -175,9 +156,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __r
   const int t = threadIdx.x;
   const int nlev = order_levels(RAGGED, Tmax);
   const int nb = RAGGED ? (Tmax + 1) * nlev : nlev * kOrderOLevels;
-  auto key_at = [&](int s) -> uint32_t {
-    return order_key<RAGGED>(RAGGED ? T[s] : Tmax, J[s], RAGGED ? 0.f : O[s], Tmax);
-  };
+  auto key_at = [&](int s) -> uint32_t { return Kin[s]; };
   auto key_of = [&](int s) -> uint32_t {
     if constexpr (CACHED) return keys[s];
     else return key_at(s);
@@ -243,16 +222,15 @@ __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const int32_t* __r
     order[atomicAdd(&hist[order_bucket<RAGGED>(key_of(s), Tmax, nlev, refJ, refO)], 1)] = s;
 }
 
-hipError_t launch_cost_order(const int32_t* T, const double* J, const float* O, int B, int Tmax, bool ragged,
-                             int32_t* order, hipStream_t st) {
+hipError_t launch_cost_order(const uint32_t* keys, int B, int Tmax, bool ragged, int32_t* order, hipStream_t st) {
   if (B <= 0) return hipSuccess;
   if (!cost_order_supported(ragged, Tmax)) return hipErrorInvalidValue;
   const dim3 g(1), b(kOrderThreads);
   const bool cached = B <= kOrderKeys;
-  if (ragged && cached) hipLaunchKernelGGL((k_cost_order<true, true>), g, b, 0, st, T, J, O, B, Tmax, order);
-  else if (ragged) hipLaunchKernelGGL((k_cost_order<true, false>), g, b, 0, st, T, J, O, B, Tmax, order);
-  else if (cached) hipLaunchKernelGGL((k_cost_order<false, true>), g, b, 0, st, T, J, O, B, Tmax, order);
-  else hipLaunchKernelGGL((k_cost_order<false, false>), g, b, 0, st, T, J, O, B, Tmax, order);
+  if (ragged && cached) hipLaunchKernelGGL((k_cost_order<true, true>), g, b, 0, st, keys, B, Tmax, order);
+  else if (ragged) hipLaunchKernelGGL((k_cost_order<true, false>), g, b, 0, st, keys, B, Tmax, order);
+  else if (cached) hipLaunchKernelGGL((k_cost_order<false, true>), g, b, 0, st, keys, B, Tmax, order);
+  else hipLaunchKernelGGL((k_cost_order<false, false>), g, b, 0, st, keys, B, Tmax, order);
   return hipGetLastError();
 }
 

@@ -416,4 +416,24 @@ __device__ __forceinline__ bool box_qp(const double (&H)[M][M], const double (&g
   return factor_face();
 }
 
+// ------------------------------------------------------------------ iteration-order keys
+// index of a positive float value in levels of 2^-(23 - sh) octaves, from its
+// exponent and leading mantissa bits; 0 for values <= 0 or NaN (infinity
+// takes the top index)
+__device__ __forceinline__ uint32_t order_index(float v, int sh) {
+  return v > 0.f ? (__float_as_uint(v) >> sh) + 1u : 0u;
+}
+
+// a slot's iteration-order key, written by the warm start.  Ragged batch: the
+// horizon (clamped into [1, Tmax]) above the octave index of float(J^0).  One
+// horizon: the quarter-octave index of float(J^0) above the half-octave index
+// of o, the warm start's non-convex cost share.  Both indexes stay below 2^11.
+__device__ __forceinline__ uint32_t order_key(bool ragged, int t, double J, float o, int Tmax) {
+  if (ragged) {
+    t = t < 1 ? 1 : (t > Tmax ? Tmax : t);
+    return (uint32_t(t) << 11) | order_index(float(J), 23);
+  }
+  return (order_index(float(J), 21) << 11) | order_index(o, 22);
+}
+
 }  // namespace cbic

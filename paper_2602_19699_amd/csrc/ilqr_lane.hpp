@@ -37,8 +37,8 @@ struct LaneState {
   int32_t* cur;      // which trajectory buffer holds the iterate (0/1)
   int32_t* work;     // [Bcap][4]: backward sweeps, rollout passes, rollout steps read, steps written
   double* mu;        // Levenberg-Marquardt parameter (that variant only)
-  float* okey;       // the warm start's non-convex cost share (0 where the system has
-                     // none): a key of the iteration order, never of a result
+  uint32_t* okey;    // iteration-order key (horizon, J^0 and the non-convex share of J^0
+                     // where the system has one): orders the launches, never a result
   // trajectories and gains, step-major
   R* X;   // [nbuf][Bcap][xs]: x_k at k N; the iterate (buffer cur) and trial trajectories
   R* U;   // [nbuf][Bcap][us]: u_k at k M
@@ -1313,7 +1313,7 @@ __global__ void __launch_bounds__(64) lane_init(const double* __restrict__ prm, 
   w.T[s] = T;
   w.inst[s] = slots ? s : b;  // outputs of slot-addressed solves are indexed by slot
   w.J[s] = J;
-  w.okey[s] = oc;
+  w.okey[s] = order_key(Tin != nullptr, T, J, oc, Tmax);
   w.iters[s] = 0;
   w.status[s] = st;
   w.cur[s] = 0;

@@ -995,7 +995,7 @@ __global__ void __launch_bounds__(64) quad_init(const double* __restrict__ prm, 
     w.T[s] = T;
     w.inst[s] = slots ? s : b;
     w.J[s] = J;
-    w.okey[s] = 0.f;  // no second order key: the slots are ordered by J^0 alone
+    w.okey[s] = order_key(Tin != nullptr, T, J, 0.f, Tmax);  // no non-convex share: J^0 alone
     w.iters[s] = 0;
     w.status[s] = st;
     w.cur[s] = 0;

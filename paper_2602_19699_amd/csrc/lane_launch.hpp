@@ -25,7 +25,7 @@ inline LaneState<R> lane_state(void* base, int N, int M, int Bcap, int Tcap, int
   w.cur = reinterpret_cast<int32_t*>(b + L.cur);
   w.work = reinterpret_cast<int32_t*>(b + L.work);
   w.mu = reinterpret_cast<double*>(b + L.mu);
-  w.okey = reinterpret_cast<float*>(b + L.okey);
+  w.okey = reinterpret_cast<uint32_t*>(b + L.okey);
   w.X = reinterpret_cast<R*>(b + L.X);
   w.U = reinterpret_cast<R*>(b + L.U);
   w.K = reinterpret_cast<R*>(b + L.K);

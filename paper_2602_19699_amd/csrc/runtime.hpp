@@ -113,15 +113,16 @@ std::string tune_key(const cbic_system* sys, int B, int Tmax, const cbic_solve_o
 // horizon sort (longest first) of B instances -> perm (device)
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st);
 
-// iteration order of B initialised slots (horizon T[s], initial cost J[s],
-// the warm start's non-convex cost share O[s]; `ragged`: the slots hold
-// several horizons, longest first): within each horizon, highest J^0 first in
-// coarse levels, and for a batch of one horizon highest O first within each
-// level -> order (device, B entries).  One workgroup; every horizon up to
-// Tmax must have a level in its shared-memory histogram (cost_order_supported).
+// iteration order of B initialised slots from the keys their warm start
+// wrote (`ragged`: the slots hold several horizons, longest first; the key is
+// then the horizon above the J^0 octave, else the J^0 quarter octave above
+// the half octave of the non-convex share of J^0): within each horizon,
+// highest J^0 first in coarse levels, and for a batch of one horizon highest
+// non-convex share first within each level -> order (device, B entries).  One
+// workgroup; every horizon up to Tmax must have a level in its shared-memory
+// histogram (cost_order_supported).
 bool cost_order_supported(bool ragged, int Tmax);
-hipError_t launch_cost_order(const int32_t* T, const double* J, const float* O, int B, int Tmax, bool ragged,
-                             int32_t* order, hipStream_t st);
+hipError_t launch_cost_order(const uint32_t* keys, int B, int Tmax, bool ragged, int32_t* order, hipStream_t st);
 
 // p[0..n) = v on the device, by a kernel
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t st);
