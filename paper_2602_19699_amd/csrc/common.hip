@@ -146,6 +146,35 @@ bool cost_order_supported(bool ragged, int Tmax) {
   return Tmax < (1 << 20) && (!ragged || order_levels(true, Tmax) >= 1);
 }
 
+// exclusive scan of a shared-memory histogram hist[0..nb) by the kOrderThreads
+// threads of one workgroup (part: kOrderThreads / 64 entries of shared
+// memory): a serial run per thread, an inclusive scan of the threads' sums
+// within each wave by shuffles, then the wave totals.  Ends with a barrier.
+__device__ __forceinline__ void block_exclusive_scan(int32_t* hist, int nb, int32_t* part) {
+  const int t = threadIdx.x;
+  const int per = (nb + kOrderThreads - 1) / kOrderThreads;
+  const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
+  int32_t sum = 0;
+  for (int i = lo; i < hi; ++i) sum += hist[i];
+  int32_t inc = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t v = __shfl_up(inc, o, 64);
+    if ((t & 63) >= o) inc += v;
+  }
+  if ((t & 63) == 63) part[t >> 6] = inc;
+  __syncthreads();
+  int32_t wbase = 0;
+  for (int w = 0; w < (t >> 6); ++w) wbase += part[w];
+  int32_t run = wbase + inc - sum;
+  for (int i = lo; i < hi; ++i) {
+    const int32_t c = hist[i];
+    hist[i] = run;
+    run += c;
+  }
+  __syncthreads();
+}
+
 template <bool RAGGED, bool CACHED>
 __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const uint32_t* __restrict__ Kin, int B, int Tmax,
                                                                int32_t* __restrict__ order) {
@@ -194,29 +223,7 @@ __global__ void __launch_bounds__(kOrderThreads) k_cost_order(const uint32_t* __
   for (int s = t; s < B; s += kOrderThreads)
     atomicAdd(&hist[order_bucket<RAGGED>(key_of(s), Tmax, nlev, refJ, refO)], 1);
   __syncthreads();
-  // exclusive scan of hist[0..nb): a serial run per thread, then across threads
-  const int per = (nb + kOrderThreads - 1) / kOrderThreads;
-  const int lo = t * per, hi = lo + per < nb ? lo + per : nb;
-  int32_t sum = 0;
-  for (int i = lo; i < hi; ++i) sum += hist[i];
-  // inclusive scan of the threads' sums within each wave, then of the wave totals
-  int32_t inc = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int32_t v = __shfl_up(inc, o, 64);
-    if ((t & 63) >= o) inc += v;
-  }
-  if ((t & 63) == 63) part[t >> 6] = inc;
-  __syncthreads();
-  int32_t wbase = 0;
-  for (int w = 0; w < (t >> 6); ++w) wbase += part[w];
-  int32_t run = wbase + inc - sum;
-  for (int i = lo; i < hi; ++i) {
-    const int32_t c = hist[i];
-    hist[i] = run;
-    run += c;
-  }
-  __syncthreads();
+  block_exclusive_scan(hist, nb, part);
 #pragma unroll 4
   for (int s = t; s < B; s += kOrderThreads)
     order[atomicAdd(&hist[order_bucket<RAGGED>(key_of(s), Tmax, nlev, refJ, refO)], 1)] = s;
@@ -235,7 +242,39 @@ hipError_t launch_cost_order(const uint32_t* keys, int B, int Tmax, bool ragged,
 }
 
 
+// The horizon sort of a batch whose buckets and per-instance bucket indexes
+// fit in shared memory, in one workgroup: the histogram of the buckets
+// Tmax - T (T clamped into [1, Tmax]), its scan and the scatter, all on
+// shared-memory atomics (the order within a bucket is arbitrary, as in the
+// grid-wide version below).
+__global__ void __launch_bounds__(kOrderThreads) k_horizon_sort_lds(const int32_t* __restrict__ T, int B, int Tmax,
+                                                                     int32_t* __restrict__ perm) {
+  __shared__ int32_t hist[kOrderBuckets];
+  __shared__ uint16_t bucket[kOrderKeys];
+  __shared__ int32_t part[kOrderThreads / 64];
+  const int t = threadIdx.x;
+  const int nb = Tmax + 1;
+  for (int i = t; i < nb; i += kOrderThreads) hist[i] = 0;
+  __syncthreads();
+#pragma unroll 4
+  for (int s = t; s < B; s += kOrderThreads) {
+    int h = T[s];
+    h = h < 1 ? 1 : (h > Tmax ? Tmax : h);
+    bucket[s] = uint16_t(Tmax - h);
+    atomicAdd(&hist[Tmax - h], 1);
+  }
+  __syncthreads();
+  block_exclusive_scan(hist, nb, part);
+#pragma unroll 4
+  for (int s = t; s < B; s += kOrderThreads) perm[atomicAdd(&hist[bucket[s]], 1)] = s;
+}
+
 hipError_t launch_horizon_sort(const int32_t* dT, int B, int Tmax, int32_t* hist, int32_t* perm, hipStream_t st) {
+  if (B <= 0) return hipSuccess;
+  if (B <= kOrderKeys && Tmax + 1 <= kOrderBuckets) {
+    hipLaunchKernelGGL(k_horizon_sort_lds, dim3(1), dim3(kOrderThreads), 0, st, dT, B, Tmax, perm);
+    return hipGetLastError();
+  }
   const int nb = Tmax + 1;
   const int g = (B + 255) / 256 < 1024 ? (B + 255) / 256 : 1024;
   hipLaunchKernelGGL(k_zero_i32, dim3((nb + 255) / 256), dim3(256), 0, st, hist, nb);
