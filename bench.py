@@ -63,20 +63,20 @@ QUAD_SOURCES = ("dev_common.hpp", "ilqr_lane.hpp", "lane_launch.hpp", "runtime.h
 COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
-        "sha256": "50bfa093c7b17c62df11ea6ac2c9a5e22f18e1df5a9a9c8cdcc3f40dfb72127b",
-        "fetch_kib": 265006.2, "write_kib": 487317.6, "sq_active_inst_valu": 174680061.5,
+        "sha256": "9c945d2073fde3f7d4f5a917d77d086e48843cb29ecd4b04ff0c66a193d4d5bc",
+        "fetch_kib": 265088.7, "write_kib": 487343.4, "sq_active_inst_valu": 174579225.2,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
-        "sha256": "5b67af0ded6590e2eaf75646ebaf9c97d3c2a49fa7699041f3bd897591a644c9",
-        "fetch_kib": 1491136.0, "write_kib": 12268131.9, "sq_active_inst_valu": 5096002497.1,
+        "sha256": "28f1166092157891156f1f68a86fd118fa463c17c93c8ad20c3502f54f36b82f",
+        "fetch_kib": 1491093.7, "write_kib": 12267687.4, "sq_active_inst_valu": 5085598923.8,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
-        "sha256": "b0fb691ee75de43bf7a11848cb23bee29d3291cee94e7b88f80fe58969e720af",
-        "fetch_kib": 1936348.1, "write_kib": 2120873.4, "sq_active_inst_valu": 2292687872.0,
+        "sha256": "9a81d630ae82dc350a898962b5ef1ceced463dc8bbb150f32f33a08f5d77680c",
+        "fetch_kib": 1932817.5, "write_kib": 2119870.9, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
