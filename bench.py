@@ -11,9 +11,12 @@ less than 1e-4 leaves a gap far below it).  A solve counts as converged when
 its cost is within 1e-4 relative of the plain FP64 fixed-budget GPU solve of
 the same instance; `value` is the converged solves per second of the fastest
 form (instances outside the bar do not count).  A form's `ms_per_step` is the
-wall-clock time of K back-to-back solves between two device synchronisations;
-its p50/p99 latencies come from a second pass of K solves, each between a pair
-of stream events.
+wall-clock time of K solves between two device synchronisations, with two
+batches in flight (--in-flight: each on a context and stream of its own, so
+one batch's tail overlaps the next one's start; every batch is a whole solve);
+`serial` gives the same K solves one at a time on one stream, and the p50/p99
+latencies come from a further pass of K solves, each between a pair of stream
+events.
 
 The same run measures the other workloads (64 point-mass instances for
 latency, 4096 arm instances with horizons 50..200, 1024 quadruped-sized
@@ -64,19 +67,19 @@ COUNTERS = {
     ("pm16k", "mixed_tol1e-4", "lane_iterate<PointMass,float,8,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_pm.hip",),
         "sha256": "9c945d2073fde3f7d4f5a917d77d086e48843cb29ecd4b04ff0c66a193d4d5bc",
-        "fetch_kib": 265088.7, "write_kib": 487343.4, "sq_active_inst_valu": 174579225.2,
+        "fetch_kib": 265724.1, "write_kib": 494885.6, "sq_active_inst_valu": 175081598.3,
         "profile": "profiles/lane_iterate_pointmass_16k_mixed_tol.md",
     },
     ("arm4k", "mixed_tol1e-7", "lane_iterate<Arm3,float,16,false,true>"): {
         "sources": LANE_SOURCES + ("k_lane_arm.hip",),
         "sha256": "28f1166092157891156f1f68a86fd118fa463c17c93c8ad20c3502f54f36b82f",
-        "fetch_kib": 1491093.7, "write_kib": 12267687.4, "sq_active_inst_valu": 5085598923.8,
+        "fetch_kib": 1491516.9, "write_kib": 12274332.1, "sq_active_inst_valu": 5090266665.3,
         "profile": "profiles/lane_iterate_arm3_4k_mixed_tol.md",
     },
     ("quad1k", "mixed_tol1e-4", "quad_iterate<float,false,false,2>"): {
         "sources": QUAD_SOURCES,
         "sha256": "9a81d630ae82dc350a898962b5ef1ceced463dc8bbb150f32f33a08f5d77680c",
-        "fetch_kib": 1932817.5, "write_kib": 2119870.9, "sq_active_inst_valu": 2292687872.0,
+        "fetch_kib": 1939390.4, "write_kib": 2120827.7, "sq_active_inst_valu": 2292687872.0,
         "profile": "profiles/quad_iterate_1k_mixed_tol.md",
     },
 }
@@ -158,7 +161,16 @@ def alg_flops(work, Tb, n, m):
     return float((work[:, 0].astype(np.float64) * Tb).sum() * riccati_flops(n, m))
 
 
+# batches in flight in the throughput loop (set from --in-flight)
+IN_FLIGHT = 2
+
+
 def time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup, autotune=True):
+    """Time one form.  Throughput: `steps` batches with IN_FLIGHT of them in
+    flight, on as many contexts (each with its own workspace) and streams,
+    taking the batches in turn; every batch is the whole solve.  Also the same
+    steps one at a time on one context, the per-batch latency from a pass with
+    stream events around every solve, and the phase times of one solve."""
     import torch
     from paper_2602_19699_amd import cbic
     dev = x0d.device
@@ -171,12 +183,39 @@ def time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup, autotune=True):
         cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=opts, out=out)
     torch.cuda.synchronize(dev)
     stream = torch.cuda.current_stream(dev)
-    # throughput: the steps back to back, nothing else on the stream
+    # throughput with batches in flight: context 0 and IN_FLIGHT - 1 more, the
+    # schedule the autotuner chose passed explicitly
+    nf = max(1, IN_FLIGHT)
+    popts = opts if width is None else cbic.Options(
+        **{**opts.__dict__, ("wg_per_cu" if sysm.kind == 3 else "group_lanes"): width})
+    ctxs = [ctx] + [cbic.Context(ctx.device) for _ in range(nf - 1)]
+    syss = [sysm] + [cbic.System(c, sysm.kind, sysm.params) for c in ctxs[1:]]
+    outs = [out] + [cbic.Outputs.allocate(B, T, sysm.n, sysm.m, dev, targets=True) for _ in ctxs[1:]]
+    strs = [torch.cuda.Stream(dev) for _ in ctxs]
+    try:
+        for _ in range(max(1, warmup)):
+            for c, sy, o, st in zip(ctxs, syss, outs, strs):
+                cbic.solve_batch(c, sy, x0d, T, T=Td, opts=popts, out=o, stream=st.cuda_stream)
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            i = k % nf
+            cbic.solve_batch(ctxs[i], syss[i], x0d, T, T=Td, opts=popts, out=outs[i], stream=strs[i].cuda_stream)
+        torch.cuda.synchronize(dev)
+        wall = (time.perf_counter() - t0) / steps
+        # every context's last batch gave the same bits
+        same = all(bool(torch.equal(o.J, outs[0].J)) and bool(torch.equal(o.U, outs[0].U)) for o in outs[1:])
+    finally:
+        for sy in syss[1:]:
+            sy.close()
+        for c in ctxs[1:]:
+            c.close()
+    # the same steps one at a time: back to back on one context and stream
     t0 = time.perf_counter()
     for _ in range(steps):
         cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=opts, out=out)
     torch.cuda.synchronize(dev)
-    wall = (time.perf_counter() - t0) / steps
+    serial = (time.perf_counter() - t0) / steps
     # per-batch latency: the same number of steps again, each between a pair
     # of stream events (the events' own cost stays out of the throughput)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -190,7 +229,7 @@ def time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup, autotune=True):
     cbic.solve_batch(ctx, sysm, x0d, T, T=Td, opts=topts, out=out)
     ph = ctx.phase_times()
     torch.cuda.synchronize(dev)
-    return out, wall * 1e3, lat, ph, width
+    return out, wall * 1e3, lat, ph, width, serial * 1e3, same
 
 
 def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, quick=False):
@@ -222,7 +261,7 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
     Jforms = {}
     bounded_ref = {}  # u_max -> J of the FP64 50-iteration solve under that bound
     for fname, opts in forms.items():
-        out, ms, lat, ph, width = time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup)
+        out, ms, lat, ph, width, serial_ms, same = time_form(ctx, sysm, x0d, T, Td, opts, steps, warmup)
         J = out.J.cpu().numpy()
         Jforms[fname] = J
         work = out.work.cpu().numpy()
@@ -254,7 +293,8 @@ def workload_bench(ctx, name, forms, steps, warmup, cpu_sample, cpu_opts_form, q
             iterate_includes_finalize=fused, finalize_alg_bytes=nfin,
             iterate_GBps=nb / (ph[1] / 1e3) / 1e9, iterate_alg_flops=nf,
             iterate_TFLOPs=nf / (ph[1] / 1e3) / 1e12, mean_iters=float(out.iters.float().mean().item()),
-            mean_sweeps=float(work[:, 0].mean()))
+            mean_sweeps=float(work[:, 0].mean()), batches_in_flight=IN_FLIGHT, in_flight_outputs_identical=same,
+            serial_ms_per_step=serial_ms, serial_converged_solves_per_s=conv / (serial_ms / 1e3))
         results[fname]["wg_per_cu" if sysm.kind == 3 else "lanes_per_instance"] = width
         if np.isfinite(opts.u_max):
             Uo = out.U.cpu().numpy()
@@ -465,6 +505,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline workload only, no CPU baseline, no serving")
+    ap.add_argument("--in-flight", type=int, default=2,
+                    help="batches in flight in the throughput loop (each on its own context and stream)")
     ap.add_argument("--only", default=None, help="time only this form (for profiler runs)")
     ap.add_argument("--workload", default=None, help="time only this workload (pm16k, pm64, arm4k, quad1k)")
     ap.add_argument("--copy-calib", action="store_true",
@@ -478,6 +520,8 @@ def main():
               f"multi-GPU run would shard the batch with no exchange, which this program does not launch.",
               file=sys.stderr)
         sys.exit(2)
+    global IN_FLIGHT
+    IN_FLIGHT = max(1, args.in_flight)
 
     if args.copy_calib:
         import torch
@@ -568,7 +612,10 @@ def main():
         "dtype": "f64" if forms[nme][best].precision == 0 else "f32+f64",
         "data": "synthetic (seeded system parameters and initial states)",
         "config": {"workload": wl, "form": best, "p50_ms": round(h["p50_ms"], 4), "p99_ms": round(h["p99_ms"], 4),
-                   "converged_frac": round(h["converged_frac"], 5)},
+                   "converged_frac": round(h["converged_frac"], 5), "batches_in_flight": IN_FLIGHT},
+        # the same steps one batch at a time (one context, one stream)
+        "serial": {"value": round(h["serial_converged_solves_per_s"], 1),
+                   "ms_per_step": round(h["serial_ms_per_step"], 4)},
         "forms": entry["forms"],
         "roofline": entry["roofline"],
         "cpu_baseline": entry["cpu_baseline"],
